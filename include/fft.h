@@ -1,0 +1,167 @@
+/*
+ * fft.h - C ABI of the MI355X (gfx950) batched 1D complex-to-complex FFT.
+ *
+ * The library computes, for power-of-two N, the unnormalised DFT
+ *
+ *     X[k] = sum_{n<N} x[n] exp(s * 2 pi i k n / N),  s = -1 forward, +1 inverse
+ *
+ * by the radix factorisation of Eq. 1 of the paper (section 3): every GPU
+ * stage is one instance of DFT_N = (DFT_K (x) I_M) D^N_M (I_K (x) DFT_M) Pi^N_K,
+ * evaluated as a Stockham (self-sorting) stage so the output comes out in
+ * natural order.  Complex arrays are either interleaved (re, im adjacent) or
+ * split into separate real and imaginary arrays, the two layouts of section 3,
+ * step 3.  The paper packages its generated kernels as a precompiled library
+ * with an FFTW-like plan/execute API (section 4); this is that boundary.
+ *
+ * Conventions for every function below
+ *  - All functions return fft_status and never throw or abort.
+ *  - Data pointers are DEVICE pointers (hipMalloc'd or torch CUDA tensors on
+ *    the current HIP device).  Arrays are float32; a transform occupies N
+ *    consecutive elements and transform b starts at element b*N ("[batch][N]").
+ *    Interleaved: one array of 2*N*batch floats (re0, im0, re1, im1, ...).
+ *    Split: two arrays of N*batch floats each (re, im).
+ *  - Pointers must be 16-byte aligned (FFT_ERR_MISALIGNED otherwise) and
+ *    non-null (FFT_ERR_NULL_POINTER); split layout needs both arrays.
+ *  - In-place (input pointers equal to output pointers) is allowed; a partial
+ *    overlap between input and output is FFT_ERR_INVALID_ARG.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    execution is asynchronous on that stream; the caller keeps every buffer
+ *    alive until the work completes.  Device faults surface at the caller's
+ *    next synchronisation.
+ *  - Argument checks happen before any HIP call, so invalid arguments are
+ *    reported even on a machine without a GPU.
+ */
+#ifndef FFT_MI355X_H
+#define FFT_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque plan, owned by the library: created by fft_plan_create* and released
+ * by fft_plan_destroy.  A plan is immutable after creation apart from the
+ * workspace pointer (fft_plan_set_workspace) and a ragged plan's cached graph. */
+typedef struct fft_plan_s *fft_plan;
+
+/* Complex layout (paper section 3, step 3: interleaved or split arrays). */
+typedef enum {
+    FFT_LAYOUT_INTERLEAVED = 0,
+    FFT_LAYOUT_SPLIT = 1
+} fft_layout;
+
+/* Sign of the exponent. */
+typedef enum {
+    FFT_FORWARD = -1,
+    FFT_INVERSE = 1
+} fft_direction;
+
+typedef enum {
+    FFT_OK = 0,
+    FFT_ERR_INVALID_SIZE = 1,   /* N not a power of two, or outside [1, 2^24] */
+    FFT_ERR_INVALID_ARG = 2,    /* bad batch/count/enum, partial overlap, bad plan */
+    FFT_ERR_NULL_POINTER = 3,
+    FFT_ERR_MISALIGNED = 4,     /* a data pointer not 16-byte aligned */
+    FFT_ERR_ALLOC = 5,          /* device or host allocation failed */
+    FFT_ERR_HIP = 6,            /* a HIP runtime call failed; see fft_last_error_detail */
+    FFT_ERR_NOT_SUPPORTED = 7
+} fft_status;
+
+/* Create a plan for `batch` contiguous transforms of size n (paper section 4:
+ * powers of two only; 1 <= n <= 2^24, batch >= 1) in `layout`, direction
+ * `dir`.  Builds the twiddle tables on the current device: every factor
+ * exp(-2 pi i m / M) is evaluated in FP64 on the GPU and rounded once to FP32
+ * (the diagonal D^N_M of Eq. 1 and Table 1's Mul(TwiddleCoe, X)).  Plans for
+ * n above the single-pass limit also own a workspace (see
+ * fft_plan_workspace_bytes).  On failure *out is set to NULL.
+ * Environment: FFT_AUTOTUNE=1 times candidate decompositions at creation and
+ * records the winner in the cache file named by FFT_AUTOTUNE_CACHE (default
+ * $HOME/.cache/fft_mi355x_autotune.json); without it the cache is only read. */
+fft_status fft_plan_create(fft_plan *out, int64_t n, int64_t batch,
+                           fft_layout layout, fft_direction dir);
+
+/* As fft_plan_create, with the decomposition given explicitly instead of
+ * chosen: "single:e<log2 E>:w<threads>" (single-pass kernel, 2^E elements per
+ * thread, workgroups of at least <threads> threads) or
+ * "multi:<log2 L1>c<log2 C1>,<log2 L2>c<log2 C2>,..." (one pass per sub-FFT
+ * length L_p with C_p columns per workgroup; the log2 L_p sum to log2 n), or
+ * "copy" for n = 1 - the strings fft_plan_describe and
+ * fft_query_decomposition report.  FFT_ERR_NOT_SUPPORTED if no compiled
+ * kernel matches, FFT_ERR_INVALID_ARG if the string does not parse. */
+fft_status fft_plan_create_explicit(fft_plan *out, int64_t n, int64_t batch,
+                                    fft_layout layout, fft_direction dir,
+                                    const char *decomposition);
+
+/* Apply the plan's transform to `batch` transforms: in -> out.
+ * in_re_or_z / out_re_or_z: interleaved array, or the real array (split).
+ * in_im / out_im: the imaginary arrays (split), ignored (may be NULL) when
+ * interleaved.  For a ragged plan the transforms are packed back to back in
+ * creation order. */
+fft_status fft_execute(fft_plan p, const void *in_re_or_z, const void *in_im,
+                       void *out_re_or_z, void *out_im, void *stream);
+
+/* Apply the adjoint of the plan's transform, unnormalised: F^H (the inverse
+ * transform) for a forward plan, F for an inverse plan.  This is the vector-
+ * Jacobian product of fft_execute, so fft_execute followed by
+ * fft_execute_backward multiplies the input by N.  Same buffers and rules as
+ * fft_execute. */
+fft_status fft_execute_backward(fft_plan p, const void *grad_out_re_or_z,
+                                const void *grad_out_im, void *grad_in_re_or_z,
+                                void *grad_in_im, void *stream);
+
+/* Release the plan and everything it owns (tables, workspace it allocated,
+ * graphs).  NULL is a no-op.  Waits for the device to finish work that may
+ * still use the plan's memory. */
+fft_status fft_plan_destroy(fft_plan p);
+
+/* Ragged plan: `count` transforms of sizes sizes[0..count) (each a power of
+ * two in [1, 2^24]) packed back to back, transform i starting at element
+ * sum_{j<i} sizes[j].  Executed as ONE persistent kernel launch (a work queue
+ * of fixed-size tiles, large sizes split into dependent passes) captured in a
+ * HIP graph together with the queue reset.  `sizes` is a host array, read
+ * during the call only. */
+fft_status fft_plan_create_ragged(fft_plan *out, const int64_t *sizes,
+                                  int64_t count, fft_layout layout,
+                                  fft_direction dir);
+
+/* Bytes of device workspace the plan uses (0 for single-pass plans). */
+fft_status fft_plan_workspace_bytes(fft_plan p, size_t *bytes);
+
+/* Hand the plan a caller-owned device workspace of at least
+ * fft_plan_workspace_bytes bytes (16-byte aligned); the plan frees its own.
+ * NULL returns the plan to a workspace it allocates itself.  Executions of one
+ * plan that overlap in time (different streams) race on the workspace. */
+fft_status fft_plan_set_workspace(fft_plan p, void *dev_ptr);
+
+/* Number of transforms, total complex elements per execution and the nominal
+ * flop count (sum of 5 N log2 N, the paper's model in section 4). */
+fft_status fft_plan_sizes(fft_plan p, int64_t *transforms, int64_t *elements,
+                          double *nominal_flops);
+
+/* Human-readable JSON description of the chosen decomposition (kernel kind,
+ * radices, passes, tiles) into buf (NUL-terminated, truncated to len). */
+fft_status fft_plan_describe(fft_plan p, char *buf, size_t len);
+
+/* Decomposition that fft_plan_create would choose for (n, layout), computed
+ * on the host only (no GPU needed), as JSON into buf. */
+fft_status fft_query_decomposition(int64_t n, fft_layout layout, char *buf, size_t len);
+
+/* Plain streaming copy of `bytes` bytes (multiple of 16, 16-byte aligned
+ * pointers) with the same access width as the FFT kernels: the practical HBM
+ * ceiling the benchmark reports beside the FFT. */
+fft_status fft_copy_device(const void *src, void *dst, size_t bytes, void *stream);
+
+/* Static description of a status code. */
+const char *fft_status_string(fft_status s);
+
+/* Detail of the most recent FFT_ERR_HIP / FFT_ERR_ALLOC on this thread
+ * (the HIP error text), or "" if none. */
+const char *fft_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFT_MI355X_H */

@@ -1,0 +1,264 @@
+"""Batched 1D complex-to-complex FP32 FFT for the AMD MI355X (gfx950).
+
+Python binding over the C ABI of ``include/fft.h`` (the HIP library in
+``lib/libfft_mi355x.so``).  Torch tensors supply device memory and the HIP
+stream (``torch.cuda.current_stream()``); every step of the transform runs in
+the library's kernels.  Conventions follow the paper's DFT (section 3, Eq. 1;
+signs as the FFTW comparison of section 4): forward exp(-2 pi i k n / N),
+inverse exp(+2 pi i k n / N), neither scaled.
+
+    Plan(n, batch, layout="interleaved" | "split", direction="forward" | "inverse")
+    RaggedPlan(sizes, layout, direction)
+    fft(x), ifft(x)                 complex64 tensors or (re, im) float32 tuples
+    FFTFunction.apply(re, im)       differentiable split-layout forward FFT
+    fft_autograd(z)                 differentiable complex64 forward FFT
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+
+import torch
+
+from ._lib import (FFT_FORWARD, FFT_INVERSE, FFT_LAYOUT_INTERLEAVED, FFT_LAYOUT_SPLIT, FFTError, check,
+                   lib)
+
+__all__ = ["Plan", "RaggedPlan", "fft", "ifft", "FFTFunction", "fft_autograd", "copy_device",
+           "query_decomposition", "FFTError"]
+
+_LAYOUTS = {"interleaved": FFT_LAYOUT_INTERLEAVED, "split": FFT_LAYOUT_SPLIT}
+_DIRS = {"forward": FFT_FORWARD, "inverse": FFT_INVERSE}
+
+
+def _stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+class _PlanBase:
+    _handle: ctypes.c_void_p | None = None
+
+    def __init__(self, layout: str, direction: str):
+        if layout not in _LAYOUTS:
+            raise ValueError(f"layout must be one of {sorted(_LAYOUTS)}")
+        if direction not in _DIRS:
+            raise ValueError(f"direction must be one of {sorted(_DIRS)}")
+        self.layout = layout
+        self.direction = direction
+        self.split = layout == "split"
+
+    # --- introspection -------------------------------------------------
+    def sizes(self) -> tuple[int, int, float]:
+        t, e, f = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        check(lib.fft_plan_sizes(self._handle, ctypes.byref(t), ctypes.byref(e), ctypes.byref(f)), "fft_plan_sizes")
+        return t.value, e.value, f.value
+
+    @property
+    def elements(self) -> int:
+        return self.sizes()[1]
+
+    @property
+    def nominal_flops(self) -> float:
+        """Sum of 5 N log2 N over the transforms (the paper's flop model, section 4)."""
+        return self.sizes()[2]
+
+    def describe(self) -> dict:
+        buf = ctypes.create_string_buffer(1 << 16)
+        check(lib.fft_plan_describe(self._handle, buf, len(buf)), "fft_plan_describe")
+        return json.loads(buf.value.decode())
+
+    @property
+    def workspace_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        check(lib.fft_plan_workspace_bytes(self._handle, ctypes.byref(n)), "fft_plan_workspace_bytes")
+        return n.value
+
+    def set_workspace(self, buf: torch.Tensor | None) -> None:
+        """Use a caller-owned device buffer (>= workspace_bytes) as the workspace; None reverts."""
+        if buf is not None:
+            if not buf.is_cuda or buf.numel() * buf.element_size() < self.workspace_bytes:
+                raise ValueError("workspace must be a device tensor of at least workspace_bytes bytes")
+        self._ws_ref = buf
+        check(lib.fft_plan_set_workspace(self._handle, _ptr(buf)), "fft_plan_set_workspace")
+
+    # --- execution -------------------------------------------------------
+    def _io(self, x, out):
+        if self.split:
+            if not (isinstance(x, (tuple, list)) and len(x) == 2):
+                raise TypeError("split layout takes (re, im) float32 tensors")
+            re, im = x
+            for t in (re, im):
+                if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+                    raise TypeError("split inputs must be contiguous float32 CUDA tensors")
+                if t.numel() != self.elements:
+                    raise ValueError(f"expected {self.elements} elements, got {t.numel()}")
+            if out is None:
+                out = (torch.empty_like(re), torch.empty_like(im))
+            ore, oim = out
+            return _ptr(re), _ptr(im), _ptr(ore), _ptr(oim), out
+        if x.dtype != torch.complex64 or not x.is_cuda or not x.is_contiguous():
+            raise TypeError("interleaved input must be a contiguous complex64 CUDA tensor")
+        if x.numel() != self.elements:
+            raise ValueError(f"expected {self.elements} elements, got {x.numel()}")
+        if out is None:
+            out = torch.empty_like(x)
+        return _ptr(x), None, _ptr(out), None, out
+
+    def execute(self, x, out=None, stream=None):
+        """y = F x (or the inverse, per the plan's direction).  `out` may be `x` (in place)."""
+        ia, ib, oa, ob, out = self._io(x, out)
+        check(lib.fft_execute(self._handle, ia, ib, oa, ob, _stream_handle(stream)), "fft_execute")
+        return out
+
+    def backward(self, g, out=None, stream=None):
+        """Adjoint of execute (unnormalised): F^H g for a forward plan, F g for an inverse plan."""
+        ia, ib, oa, ob, out = self._io(g, out)
+        check(lib.fft_execute_backward(self._handle, ia, ib, oa, ob, _stream_handle(stream)),
+              "fft_execute_backward")
+        return out
+
+    __call__ = execute
+
+    def close(self) -> None:
+        if self._handle:
+            check(lib.fft_plan_destroy(self._handle), "fft_plan_destroy")
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Plan(_PlanBase):
+    """`batch` contiguous transforms of size n (a power of two up to 2^24)."""
+
+    def __init__(self, n: int, batch: int = 1, layout: str = "interleaved", direction: str = "forward",
+                 decomposition: str | None = None):
+        super().__init__(layout, direction)
+        h = ctypes.c_void_p()
+        if decomposition is None:
+            check(lib.fft_plan_create(ctypes.byref(h), int(n), int(batch), _LAYOUTS[layout], _DIRS[direction]),
+                  "fft_plan_create")
+        else:
+            check(lib.fft_plan_create_explicit(ctypes.byref(h), int(n), int(batch), _LAYOUTS[layout],
+                                               _DIRS[direction], decomposition.encode()),
+                  "fft_plan_create_explicit")
+        self._handle = h
+        self.n = int(n)
+        self.batch = int(batch)
+
+
+class RaggedPlan(_PlanBase):
+    """Transforms of the given power-of-two sizes packed back to back, one launch."""
+
+    def __init__(self, sizes, layout: str = "interleaved", direction: str = "forward"):
+        super().__init__(layout, direction)
+        sizes = [int(s) for s in sizes]
+        arr = (ctypes.c_int64 * len(sizes))(*sizes)
+        h = ctypes.c_void_p()
+        check(lib.fft_plan_create_ragged(ctypes.byref(h), arr, len(sizes), _LAYOUTS[layout], _DIRS[direction]),
+              "fft_plan_create_ragged")
+        self._handle = h
+        self.sizes_list = sizes
+
+
+_plan_cache: dict = {}
+
+
+def _cached_plan(n: int, batch: int, layout: str, direction: str) -> Plan:
+    key = (n, batch, layout, direction, torch.cuda.current_device())
+    p = _plan_cache.get(key)
+    if p is None:
+        p = Plan(n, batch, layout, direction)
+        _plan_cache[key] = p
+    return p
+
+
+def _transform(x, direction: str):
+    if isinstance(x, (tuple, list)):
+        re, im = x
+        n = re.shape[-1]
+        return _cached_plan(n, re.numel() // n, "split", direction).execute((re.contiguous(), im.contiguous()))
+    n = x.shape[-1]
+    return _cached_plan(n, x.numel() // n, "interleaved", direction).execute(x.contiguous())
+
+
+def fft(x):
+    """Forward FFT along the last axis (unnormalised)."""
+    return _transform(x, "forward")
+
+
+def ifft(x):
+    """Inverse FFT along the last axis, unnormalised (ifft(fft(x)) = N x)."""
+    return _transform(x, "inverse")
+
+
+class FFTFunction(torch.autograd.Function):
+    """Differentiable forward FFT of split (re, im) tensors of shape [..., N].
+
+    Forward: y = F x.  Backward: the vector-Jacobian product of the linear map
+    F on the real pair (Re x, Im x) is F^H g, g = dL/dRe(y) + i dL/dIm(y),
+    computed by the adjoint (unnormalised inverse) kernel.
+    """
+
+    @staticmethod
+    def forward(ctx, re: torch.Tensor, im: torch.Tensor):
+        n = re.shape[-1]
+        plan = _cached_plan(n, re.numel() // n, "split", "forward")
+        ctx.plan = plan
+        yre, yim = plan.execute((re.contiguous(), im.contiguous()))
+        return yre, yim
+
+    @staticmethod
+    def backward(ctx, gre: torch.Tensor, gim: torch.Tensor):
+        if gre is None:
+            gre = torch.zeros_like(gim)
+        if gim is None:
+            gim = torch.zeros_like(gre)
+        xre, xim = ctx.plan.backward((gre.contiguous(), gim.contiguous()))
+        return xre, xim
+
+
+class _ComplexFFTFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, z: torch.Tensor):
+        n = z.shape[-1]
+        plan = _cached_plan(n, z.numel() // n, "interleaved", "forward")
+        ctx.plan = plan
+        return plan.execute(z.contiguous())
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        return ctx.plan.backward(g.contiguous())
+
+
+def fft_autograd(z: torch.Tensor) -> torch.Tensor:
+    """Differentiable forward FFT of a complex64 tensor [..., N]."""
+    return _ComplexFFTFunction.apply(z)
+
+
+def copy_device(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    """Streaming device copy with the library's copy kernel (HBM ceiling reference)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("destination too small")
+    check(lib.fft_copy_device(_ptr(src), _ptr(dst), nbytes, _stream_handle(stream)), "fft_copy_device")
+
+
+def query_decomposition(n: int, layout: str = "interleaved") -> dict:
+    """Decomposition a plan for n would use, and the autotuner's candidates (host only)."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    check(lib.fft_query_decomposition(int(n), _LAYOUTS[layout], buf, len(buf)), "fft_query_decomposition")
+    return json.loads(buf.value.decode())

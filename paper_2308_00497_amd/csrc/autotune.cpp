@@ -1,0 +1,213 @@
+// Autotuner and its JSON cache.
+//
+// The paper picks radices by hand and names a runtime planner that measures
+// candidate decompositions (as FFTW's exhaustive mode does) as future work
+// (sections 4 and 6); loop-tile sizes were hyperparameters it set by hand
+// (section 3, step 4).  Here every compiled decomposition of a size is timed
+// with HIP events on scratch buffers and the winner is cached on disk.
+#include "autotune.hpp"
+
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+#include <map>
+#include <mutex>
+
+namespace fftk {
+
+namespace {
+
+std::mutex g_mu;
+std::string g_loaded_path;  // cache file the in-memory entries came from
+bool g_loaded = false;
+std::map<std::string, std::string> g_entries;
+
+std::string read_file(const std::string& path) {
+    FILE* f = fopen(path.c_str(), "rb");
+    if (!f) return std::string();
+    std::string s;
+    char buf[4096];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, n);
+    fclose(f);
+    return s;
+}
+
+// one JSON string starting at s[i] == '"'; returns false on malformed input
+bool read_string(const std::string& s, size_t& i, std::string* out) {
+    if (i >= s.size() || s[i] != '"') return false;
+    ++i;
+    out->clear();
+    while (i < s.size() && s[i] != '"') {
+        if (s[i] == '\\') {
+            if (i + 1 >= s.size()) return false;
+            ++i;
+        }
+        out->push_back(s[i++]);
+    }
+    if (i >= s.size()) return false;
+    ++i;
+    return true;
+}
+
+void skip_ws(const std::string& s, size_t& i) {
+    while (i < s.size() && (s[i] == ' ' || s[i] == '\n' || s[i] == '\t' || s[i] == '\r')) ++i;
+}
+
+void load_locked() {
+    const std::string path = autotune_cache_path();
+    if (g_loaded && path == g_loaded_path) return;
+    g_loaded = true;
+    g_loaded_path = path;
+    g_entries.clear();
+    std::vector<std::pair<std::string, std::string>> e;
+    if (parse_cache_text(read_file(path), &e))
+        for (auto& kv : e) g_entries[kv.first] = kv.second;
+}
+
+}  // namespace
+
+// Format: {"version": 1, "entries": {"<key>": "<decomposition>", ...}}
+bool parse_cache_text(const std::string& s, std::vector<std::pair<std::string, std::string>>* entries) {
+    entries->clear();
+    const size_t v = s.find("\"version\"");
+    if (v == std::string::npos) return false;
+    size_t i = s.find(':', v);
+    if (i == std::string::npos) return false;
+    ++i;
+    skip_ws(s, i);
+    if (s.compare(i, 1, "1") != 0) return false;  // unknown version: ignore the file
+    const size_t e = s.find("\"entries\"");
+    if (e == std::string::npos) return false;
+    i = s.find('{', e);
+    if (i == std::string::npos) return false;
+    ++i;
+    std::vector<std::pair<std::string, std::string>> tmp;
+    while (true) {
+        skip_ws(s, i);
+        if (i < s.size() && s[i] == '}') break;
+        std::string k, val;
+        if (!read_string(s, i, &k)) return false;
+        skip_ws(s, i);
+        if (i >= s.size() || s[i] != ':') return false;
+        ++i;
+        skip_ws(s, i);
+        if (!read_string(s, i, &val)) return false;
+        Decomp d;
+        if (!Decomp::parse(val, &d)) return false;
+        tmp.emplace_back(k, val);
+        skip_ws(s, i);
+        if (i < s.size() && s[i] == ',') {
+            ++i;
+            continue;
+        }
+        if (i < s.size() && s[i] == '}') break;
+        return false;
+    }
+    *entries = tmp;
+    return true;
+}
+
+std::string format_cache_text(const std::vector<std::pair<std::string, std::string>>& entries) {
+    std::string s = "{\"version\": 1, \"entries\": {";
+    for (size_t i = 0; i < entries.size(); ++i) {
+        s += (i ? ",\n  \"" : "\n  \"") + entries[i].first + "\": \"" + entries[i].second + "\"";
+    }
+    s += "\n}}\n";
+    return s;
+}
+
+TuneKey make_key(int device, int log2n, int64_t batch, fft_layout layout) {
+    hipDeviceProp_t prop;
+    char arch[64] = "unknown";
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+        char* colon = strchr(arch, ':');
+        if (colon) *colon = '\0';
+    }
+    int rt = 0;
+    (void)hipRuntimeGetVersion(&rt);
+    int bclass = 0;
+    while ((int64_t(1) << bclass) < batch) ++bclass;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s|hip%d|n%d|b%d|%s", arch, rt, log2n, bclass,
+             layout == FFT_LAYOUT_SPLIT ? "split" : "interleaved");
+    return TuneKey{buf};
+}
+
+bool autotune_enabled() {
+    const char* s = getenv("FFT_AUTOTUNE");
+    return s && s[0] == '1';
+}
+
+std::string autotune_cache_path() {
+    const char* s = getenv("FFT_AUTOTUNE_CACHE");
+    if (s && *s) return s;
+    const char* home = getenv("HOME");
+    return std::string(home ? home : "/tmp") + "/.cache/fft_mi355x_autotune.json";
+}
+
+bool autotune_lookup(const TuneKey& key, Decomp* out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_locked();
+    auto it = g_entries.find(key.s);
+    if (it == g_entries.end()) return false;
+    return Decomp::parse(it->second, out);
+}
+
+void autotune_store(const TuneKey& key, const Decomp& d) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_locked();
+    g_entries[key.s] = d.str();
+    std::vector<std::pair<std::string, std::string>> e(g_entries.begin(), g_entries.end());
+    const std::string path = autotune_cache_path();
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        std::string dir = path.substr(0, slash);
+        // create the parent directory if missing (one level)
+        (void)!system(("mkdir -p '" + dir + "' 2>/dev/null").c_str());
+    }
+    const std::string tmp = path + ".tmp" + std::to_string(getpid());
+    FILE* f = fopen(tmp.c_str(), "wb");
+    if (!f) return;
+    const std::string text = format_cache_text(e);
+    const bool ok = fwrite(text.data(), 1, text.size(), f) == text.size();
+    fclose(f);
+    if (ok) (void)rename(tmp.c_str(), path.c_str());
+    else (void)remove(tmp.c_str());
+}
+
+fft_status autotune_run(fft_plan p, const TuneKey& key, Decomp* best, std::string* detail) {
+    const int log2n = plan_log2n(p);
+    const auto cands = candidate_decompositions(log2n, plan_layout(p));
+    *best = plan_decomposition(p);
+    if (cands.size() <= 1) return FFT_OK;
+    const size_t bytes = size_t(plan_elements(p)) * 8;
+    void *in = nullptr, *out = nullptr;
+    if (hipMalloc(&in, bytes) != hipSuccess || hipMalloc(&out, bytes) != hipSuccess) {
+        if (in) (void)hipFree(in);
+        *detail = "autotune scratch allocation failed";
+        return FFT_ERR_ALLOC;
+    }
+    (void)hipMemset(in, 0, bytes);
+    float best_ms = 1e30f;
+    for (const Decomp& d : cands) {
+        float ms = 0.f;
+        std::string det;
+        if (plan_time_decomposition(p, d, in, out, &ms, &det) != FFT_OK) continue;
+        if (getenv("FFT_LOG")) fprintf(stderr, "[fft autotune] %s %s %.4f ms\n", key.s.c_str(), d.str().c_str(), ms);
+        if (ms < best_ms) {
+            best_ms = ms;
+            *best = d;
+        }
+    }
+    (void)hipFree(in);
+    (void)hipFree(out);
+    autotune_store(key, *best);
+    return FFT_OK;
+}
+
+}  // namespace fftk

@@ -1,0 +1,640 @@
+// C ABI of the library: argument checking, plan construction (twiddle
+// tables, workspace), execution and introspection.  Every entry point returns
+// an fft_status; nothing throws across the boundary.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fft.h"
+#include "autotune.hpp"
+#include "plan.hpp"
+#include "ragged.hpp"
+#include "registry.hpp"
+
+using fftk::Decomp;
+
+namespace {
+
+thread_local std::string g_detail;
+
+constexpr uint64_t kPlanMagic = 0x46465450'4c414e31ull;  // "FFTPLAN1"
+constexpr uint64_t kDeadMagic = 0x44454144'504c414eull;
+
+fft_status fail_hip(hipError_t e, const char* what) {
+    g_detail = std::string(what) + ": " + hipGetErrorString(e);
+    (void)hipGetLastError();  // clear the sticky launch error, if any
+    return FFT_ERR_HIP;
+}
+
+// Test hook: FFT_TEST_FAIL_ALLOC=k makes the k-th device allocation of the
+// process (counting from 1) fail as if the device were out of memory.
+hipError_t dev_malloc(void** p, size_t bytes) {
+    static long countdown = [] {
+        const char* s = getenv("FFT_TEST_FAIL_ALLOC");
+        return s ? atol(s) : 0L;
+    }();
+    if (countdown > 0 && --countdown == 0) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+struct PassStep {
+    const fftk::PassKernel* k;
+    int log2ns;
+    int hbits;
+    size_t tw32_off;  // engine table (float2 entries)
+    size_t ta_off;    // FP64 tables (double2 entries)
+    size_t tb_off;
+    int src;  // 0 = caller input, 1 = workspace A, 2 = workspace B
+    int dst;  // 3 = caller output, 1, 2 as above
+};
+
+bool valid_layout(int l) { return l == FFT_LAYOUT_INTERLEAVED || l == FFT_LAYOUT_SPLIT; }
+bool valid_dir(int d) { return d == FFT_FORWARD || d == FFT_INVERSE; }
+
+bool overlaps(uintptr_t a, size_t na, uintptr_t b, size_t nb) { return na && nb && a < b + nb && b < a + na; }
+
+}  // namespace
+
+struct fft_plan_s {
+    uint64_t magic = kPlanMagic;
+    int device = 0;
+    int64_t n = 0, batch = 0;
+    int log2n = 0;
+    fft_layout layout = FFT_LAYOUT_INTERLEAVED;
+    fft_direction dir = FFT_FORWARD;
+    Decomp dec;
+    const fftk::SingleKernel* single = nullptr;
+    std::vector<PassStep> steps;
+    float2* tw32 = nullptr;
+    size_t tw32_n = 0;
+    double2* tw64 = nullptr;
+    size_t tw64_n = 0;
+    void* ws_own = nullptr;
+    void* ws_user = nullptr;
+    size_t ws_bytes = 0;
+    int64_t elements = 0;
+    double flops = 0.0;
+    fftk::RaggedPlan* ragged = nullptr;
+    std::string source;  // "default" | "cache" | "autotune"
+
+    void* ws() const { return ws_user ? ws_user : ws_own; }
+};
+
+namespace {
+
+bool plan_ok(fft_plan p) { return p && p->magic == kPlanMagic; }
+
+void free_plan_memory(fft_plan p) {
+    if (p->tw32) (void)hipFree(p->tw32);
+    if (p->tw64) (void)hipFree(p->tw64);
+    if (p->ws_own) (void)hipFree(p->ws_own);
+    p->tw32 = nullptr;
+    p->tw64 = nullptr;
+    p->ws_own = nullptr;
+    if (p->ragged) fftk::ragged_destroy(p->ragged);
+    p->ragged = nullptr;
+}
+
+// Resolve kernels, lay out the tables and the workspace for `dec`.
+fft_status resolve(fft_plan p, const Decomp& dec) {
+    const bool split = p->layout == FFT_LAYOUT_SPLIT;
+    p->dec = dec;
+    p->single = nullptr;
+    p->steps.clear();
+    p->tw32_n = 0;
+    p->tw64_n = 0;
+    p->ws_bytes = 0;
+    switch (dec.kind) {
+        case Decomp::COPY:
+            break;
+        case Decomp::SINGLE:
+            p->single = fftk::find_single(p->log2n, dec.log2e, dec.wgt, split);
+            if (!p->single) return FFT_ERR_NOT_SUPPORTED;
+            p->tw32_n = p->single->eng.tw_size;
+            break;
+        case Decomp::MULTI: {
+            const size_t P = dec.log2l.size();
+            int log2ns = 0;
+            for (size_t i = 0; i < P; ++i) {
+                PassStep st{};
+                const bool first = i == 0, last = i == P - 1;
+                st.k = fftk::find_pass(dec.log2l[i], dec.log2c[i], first, first && split, last && split);
+                if (!st.k) return FFT_ERR_NOT_SUPPORTED;
+                st.log2ns = log2ns;
+                st.tw32_off = p->tw32_n;
+                p->tw32_n += (st.k->eng.tw_size + 1) & ~size_t(1);  // keep 16-byte alignment
+                if (!first) {
+                    const int log2m = log2ns + dec.log2l[i];
+                    st.hbits = (log2m + 1) / 2;
+                    st.ta_off = p->tw64_n;
+                    p->tw64_n += size_t(1) << (log2m - st.hbits);
+                    st.tb_off = p->tw64_n;
+                    p->tw64_n += size_t(1) << st.hbits;
+                }
+                // ping-pong between two workspace halves; the last pass writes the output
+                st.src = first ? 0 : ((i - 1) % 2 == 0 ? 1 : 2);
+                st.dst = last ? 3 : (i % 2 == 0 ? 1 : 2);
+                p->steps.push_back(st);
+                log2ns += dec.log2l[i];
+            }
+            const size_t half = size_t(p->n) * size_t(p->batch) * sizeof(float2);
+            p->ws_bytes = (P >= 3 ? 2 : 1) * half;
+            break;
+        }
+    }
+    return FFT_OK;
+}
+
+// Allocate and fill the twiddle tables (FP64 on the GPU, rounded once).
+fft_status build_tables(fft_plan p, hipStream_t s) {
+    hipError_t e;
+    if (p->tw32_n) {
+        e = dev_malloc(reinterpret_cast<void**>(&p->tw32), p->tw32_n * sizeof(float2));
+        if (e != hipSuccess) {
+            g_detail = "twiddle table allocation failed";
+            return FFT_ERR_ALLOC;
+        }
+    }
+    if (p->tw64_n) {
+        e = dev_malloc(reinterpret_cast<void**>(&p->tw64), p->tw64_n * sizeof(double2));
+        if (e != hipSuccess) {
+            g_detail = "FP64 twiddle table allocation failed";
+            return FFT_ERR_ALLOC;
+        }
+    }
+    if (p->single && p->single->eng.tw_size) {
+        e = fftk::launch_gen_engine_tw(p->single->eng, p->tw32, s);
+        if (e != hipSuccess) return fail_hip(e, "twiddle generation");
+    }
+    for (const PassStep& st : p->steps) {
+        if (st.k->eng.tw_size) {
+            e = fftk::launch_gen_engine_tw(st.k->eng, p->tw32 + st.tw32_off, s);
+            if (e != hipSuccess) return fail_hip(e, "twiddle generation");
+        }
+        if (st.log2ns > 0) {
+            const int log2m = st.log2ns + st.k->log2l;
+            e = fftk::launch_gen_pow64(p->tw64 + st.ta_off, log2m, int64_t(1) << st.hbits,
+                                       int64_t(1) << (log2m - st.hbits), s);
+            if (e == hipSuccess) e = fftk::launch_gen_pow64(p->tw64 + st.tb_off, log2m, 1, int64_t(1) << st.hbits, s);
+            if (e != hipSuccess) return fail_hip(e, "FP64 twiddle generation");
+        }
+    }
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_hip(e, "twiddle generation sync");
+    return FFT_OK;
+}
+
+fft_status alloc_workspace(fft_plan p) {
+    if (p->ws_bytes == 0 || p->ws_user) return FFT_OK;
+    hipError_t e = dev_malloc(&p->ws_own, p->ws_bytes);
+    if (e != hipSuccess) {
+        p->ws_own = nullptr;
+        g_detail = "workspace allocation failed";
+        return FFT_ERR_ALLOC;
+    }
+    return FFT_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != dev && hipSetDevice(dev) == hipSuccess) prev = cur;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Checks shared by execute and execute_backward (before any HIP call).
+fft_status check_buffers(fft_plan p, const void* ia, const void* ib, const void* oa, const void* ob) {
+    if (!plan_ok(p)) return FFT_ERR_INVALID_ARG;
+    const bool split = p->layout == FFT_LAYOUT_SPLIT;
+    if (!ia || !oa || (split && (!ib || !ob))) return FFT_ERR_NULL_POINTER;
+    auto mis = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) != 0; };
+    if (mis(ia) || mis(oa) || (split && (mis(ib) || mis(ob)))) return FFT_ERR_MISALIGNED;
+    const size_t elems = size_t(p->elements);
+    const size_t bytes = split ? elems * sizeof(float) : elems * sizeof(float2);
+    const uintptr_t ua = uintptr_t(ia), ub = split ? uintptr_t(ib) : 0, va = uintptr_t(oa),
+                    vb = split ? uintptr_t(ob) : 0;
+    const size_t nb = split ? bytes : 0;
+    // input/output pairs may coincide exactly (in place) or be disjoint
+    if (overlaps(ua, bytes, va, bytes) && ua != va) return FFT_ERR_INVALID_ARG;
+    if (split) {
+        if (overlaps(ub, nb, vb, nb) && ub != vb) return FFT_ERR_INVALID_ARG;
+        if (overlaps(ua, bytes, vb, nb) || overlaps(ub, nb, va, bytes)) return FFT_ERR_INVALID_ARG;
+        if (overlaps(va, bytes, vb, nb)) return FFT_ERR_INVALID_ARG;
+    }
+    return FFT_OK;
+}
+
+fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, void* stream, bool adjoint) {
+    fft_status st = check_buffers(p, ia, ib, oa, ob);
+    if (st != FFT_OK) return st;
+    DeviceGuard guard(p->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // forward kernels everywhere; the inverse conjugates on the way in and out
+    const bool inverse = (p->dir == FFT_INVERSE) != adjoint;
+    const uint32_t mask = inverse ? 0x80000000u : 0u;
+    const bool split = p->layout == FFT_LAYOUT_SPLIT;
+    const float* fa = static_cast<const float*>(ia);
+    const float* fb = static_cast<const float*>(ib);
+    float* ga = static_cast<float*>(oa);
+    float* gb = static_cast<float*>(ob);
+    hipError_t e = hipSuccess;
+
+    if (p->ragged) return fftk::ragged_execute(p->ragged, fa, fb, ga, gb, mask, s, &g_detail);
+
+    switch (p->dec.kind) {
+        case Decomp::COPY: {
+            if (ia == oa && (!split || ib == ob)) return FFT_OK;
+            const size_t bytes = size_t(p->elements) * (split ? sizeof(float) : sizeof(float2));
+            e = hipMemcpyAsync(oa, ia, bytes, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess && split) e = hipMemcpyAsync(ob, ib, bytes, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return fail_hip(e, "copy");
+            return FFT_OK;
+        }
+        case Decomp::SINGLE:
+            e = p->single->fn(fa, fb, ga, gb, p->tw32, p->batch, mask, mask, s);
+            if (e != hipSuccess) return fail_hip(e, "single-pass launch");
+            return FFT_OK;
+        case Decomp::MULTI: {
+            if (!p->ws()) {
+                g_detail = "no workspace";
+                return FFT_ERR_INVALID_ARG;
+            }
+            const size_t half = size_t(p->n) * size_t(p->batch) * sizeof(float2);
+            float* wsa = static_cast<float*>(p->ws());
+            float* wsb = reinterpret_cast<float*>(static_cast<char*>(p->ws()) + half);
+            const size_t P = p->steps.size();
+            for (size_t i = 0; i < P; ++i) {
+                const PassStep& stp = p->steps[i];
+                const float *sa = nullptr, *sb = nullptr;
+                float *da = nullptr, *db = nullptr;
+                if (stp.src == 0) {
+                    sa = fa;
+                    sb = fb;
+                } else {
+                    sa = stp.src == 1 ? wsa : wsb;
+                }
+                if (stp.dst == 3) {
+                    da = ga;
+                    db = gb;
+                } else {
+                    da = stp.dst == 1 ? wsa : wsb;
+                }
+                e = stp.k->fn(sa, sb, da, db, p->tw32 + stp.tw32_off, p->tw64 ? p->tw64 + stp.ta_off : nullptr,
+                              p->tw64 ? p->tw64 + stp.tb_off : nullptr, p->log2n, stp.log2ns, stp.hbits, p->batch,
+                              i == 0 ? mask : 0u, i == P - 1 ? mask : 0u, s);
+                if (e != hipSuccess) return fail_hip(e, "pass launch");
+            }
+            (void)split;
+            return FFT_OK;
+        }
+    }
+    return FFT_ERR_INVALID_ARG;
+}
+
+std::string describe(fft_plan p) {
+    char buf[512];
+    std::string s = "{";
+    snprintf(buf, sizeof buf, "\"n\": %lld, \"batch\": %lld, \"layout\": \"%s\", \"direction\": \"%s\", ",
+             (long long)p->n, (long long)p->batch, p->layout == FFT_LAYOUT_SPLIT ? "split" : "interleaved",
+             p->dir == FFT_FORWARD ? "forward" : "inverse");
+    s += buf;
+    if (p->ragged) {
+        s += fftk::ragged_describe(p->ragged);
+        s += "}";
+        return s;
+    }
+    snprintf(buf, sizeof buf, "\"decomposition\": \"%s\", \"source\": \"%s\", \"workspace_bytes\": %zu",
+             p->dec.str().c_str(), p->source.c_str(), p->ws_bytes);
+    s += buf;
+    if (p->single) {
+        std::string radices;
+        for (int i = 0; i < p->single->eng.nst; ++i)
+            radices += (i ? "," : "") + std::to_string(1 << p->single->eng.log2r[i]);
+        snprintf(buf, sizeof buf,
+                 ", \"kernel\": \"single\", \"radices\": [%s], \"threads\": %d, \"transforms_per_wg\": %d, "
+                 "\"lds_bytes\": %zu",
+                 radices.c_str(), p->single->threads, p->single->per_wg, p->single->lds_bytes);
+        s += buf;
+    }
+    if (!p->steps.empty()) {
+        s += ", \"passes\": [";
+        for (size_t i = 0; i < p->steps.size(); ++i) {
+            const auto& st = p->steps[i];
+            std::string radices;
+            for (int j = 0; j < st.k->eng.nst; ++j) radices += (j ? "," : "") + std::to_string(1 << st.k->eng.log2r[j]);
+            snprintf(buf, sizeof buf,
+                     "%s{\"L\": %d, \"columns\": %d, \"Ns\": %lld, \"radices\": [%s], \"threads\": %d, "
+                     "\"lds_bytes\": %zu}",
+                     i ? ", " : "", 1 << st.k->log2l, 1 << st.k->log2c, (long long)(int64_t(1) << st.log2ns),
+                     radices.c_str(), st.k->threads, st.k->lds_bytes);
+            s += buf;
+        }
+        s += "]";
+    }
+    s += "}";
+    return s;
+}
+
+fft_status copy_out(const std::string& s, char* buf, size_t len) {
+    if (!buf || len == 0) return FFT_ERR_NULL_POINTER;
+    const size_t n = s.size() < len - 1 ? s.size() : len - 1;
+    memcpy(buf, s.data(), n);
+    buf[n] = '\0';
+    return FFT_OK;
+}
+
+double nominal_flops(int64_t n) {
+    int k = fftk::ilog2_exact(n);
+    return k <= 0 ? 0.0 : 5.0 * double(n) * double(k);
+}
+
+}  // namespace
+
+extern "C" {
+
+static fft_status create_impl(fft_plan* out, int64_t n, int64_t batch, fft_layout layout, fft_direction dir,
+                              const char* explicit_dec) {
+    if (!out) return FFT_ERR_NULL_POINTER;
+    *out = nullptr;
+    const int log2n = fftk::ilog2_exact(n);
+    if (log2n < 0 || log2n > fftk::kMaxLog2N) return FFT_ERR_INVALID_SIZE;
+    if (batch < 1 || !valid_layout(layout) || !valid_dir(dir)) return FFT_ERR_INVALID_ARG;
+    if (batch > (int64_t(1) << 40) / n) return FFT_ERR_INVALID_ARG;  // element count bound
+    Decomp forced;
+    if (explicit_dec) {
+        if (!Decomp::parse(explicit_dec, &forced)) return FFT_ERR_INVALID_ARG;
+        if (!fftk::decomposition_available(forced, log2n, layout)) return FFT_ERR_NOT_SUPPORTED;
+    }
+
+    fft_plan p = new (std::nothrow) fft_plan_s;
+    if (!p) return FFT_ERR_ALLOC;
+    p->n = n;
+    p->batch = batch;
+    p->log2n = log2n;
+    p->layout = layout;
+    p->dir = dir;
+    p->elements = n * batch;
+    p->flops = nominal_flops(n) * double(batch);
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return fail_hip(e, "hipGetDevice");
+    }
+
+    Decomp dec = fftk::default_decomposition(log2n);
+    p->source = "default";
+    fftk::TuneKey key = fftk::make_key(p->device, log2n, batch, layout);
+    Decomp cached;
+    if (explicit_dec) {
+        dec = forced;
+        p->source = "explicit";
+    } else if (fftk::autotune_lookup(key, &cached) && fftk::decomposition_available(cached, log2n, layout)) {
+        dec = cached;
+        p->source = "cache";
+    }
+    fft_status st = resolve(p, dec);
+    if (st == FFT_OK) st = build_tables(p, nullptr);
+    if (st == FFT_OK) st = alloc_workspace(p);
+    if (st == FFT_OK && !explicit_dec && fftk::autotune_enabled() && p->source != "cache") {
+        // time every candidate on scratch buffers and keep the fastest
+        Decomp best;
+        st = fftk::autotune_run(p, key, &best, &g_detail);
+        if (st == FFT_OK && !(best == p->dec)) {
+            free_plan_memory(p);
+            st = resolve(p, best);
+            if (st == FFT_OK) st = build_tables(p, nullptr);
+            if (st == FFT_OK) st = alloc_workspace(p);
+        }
+        p->source = "autotune";
+    }
+    if (st != FFT_OK) {
+        free_plan_memory(p);
+        p->magic = kDeadMagic;
+        delete p;
+        return st;
+    }
+    *out = p;
+    return FFT_OK;
+}
+
+fft_status fft_plan_create(fft_plan* out, int64_t n, int64_t batch, fft_layout layout, fft_direction dir) {
+    return create_impl(out, n, batch, layout, dir, nullptr);
+}
+
+fft_status fft_plan_create_explicit(fft_plan* out, int64_t n, int64_t batch, fft_layout layout, fft_direction dir,
+                                    const char* decomposition) {
+    if (!decomposition) return FFT_ERR_NULL_POINTER;
+    return create_impl(out, n, batch, layout, dir, decomposition);
+}
+
+fft_status fft_execute(fft_plan p, const void* in_re_or_z, const void* in_im, void* out_re_or_z, void* out_im,
+                       void* stream) {
+    return run(p, in_re_or_z, in_im, out_re_or_z, out_im, stream, false);
+}
+
+fft_status fft_execute_backward(fft_plan p, const void* grad_out_re_or_z, const void* grad_out_im,
+                                void* grad_in_re_or_z, void* grad_in_im, void* stream) {
+    return run(p, grad_out_re_or_z, grad_out_im, grad_in_re_or_z, grad_in_im, stream, true);
+}
+
+fft_status fft_plan_destroy(fft_plan p) {
+    if (!p) return FFT_OK;
+    if (!plan_ok(p)) return FFT_ERR_INVALID_ARG;
+    DeviceGuard guard(p->device);
+    (void)hipDeviceSynchronize();
+    free_plan_memory(p);
+    p->magic = kDeadMagic;
+    delete p;
+    return FFT_OK;
+}
+
+fft_status fft_plan_create_ragged(fft_plan* out, const int64_t* sizes, int64_t count, fft_layout layout,
+                                  fft_direction dir) {
+    if (!out) return FFT_ERR_NULL_POINTER;
+    *out = nullptr;
+    if (!sizes) return FFT_ERR_NULL_POINTER;
+    if (count < 1 || !valid_layout(layout) || !valid_dir(dir)) return FFT_ERR_INVALID_ARG;
+    int64_t total = 0;
+    double flops = 0.0;
+    for (int64_t i = 0; i < count; ++i) {
+        const int k = fftk::ilog2_exact(sizes[i]);
+        if (k < 0 || k > fftk::kMaxLog2N) return FFT_ERR_INVALID_SIZE;
+        total += sizes[i];
+        flops += nominal_flops(sizes[i]);
+        if (total > (int64_t(1) << 40)) return FFT_ERR_INVALID_ARG;
+    }
+    fft_plan p = new (std::nothrow) fft_plan_s;
+    if (!p) return FFT_ERR_ALLOC;
+    p->n = 0;
+    p->batch = count;
+    p->layout = layout;
+    p->dir = dir;
+    p->elements = total;
+    p->flops = flops;
+    p->source = "ragged";
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return fail_hip(e, "hipGetDevice");
+    }
+    fft_status st = fftk::ragged_create(sizes, count, layout, &p->ragged, &g_detail);
+    if (st != FFT_OK) {
+        p->magic = kDeadMagic;
+        delete p;
+        return st;
+    }
+    p->ws_bytes = fftk::ragged_workspace_bytes(p->ragged);
+    *out = p;
+    return FFT_OK;
+}
+
+fft_status fft_plan_workspace_bytes(fft_plan p, size_t* bytes) {
+    if (!plan_ok(p)) return FFT_ERR_INVALID_ARG;
+    if (!bytes) return FFT_ERR_NULL_POINTER;
+    *bytes = p->ws_bytes;
+    return FFT_OK;
+}
+
+fft_status fft_plan_set_workspace(fft_plan p, void* dev_ptr) {
+    if (!plan_ok(p)) return FFT_ERR_INVALID_ARG;
+    if (dev_ptr && (reinterpret_cast<uintptr_t>(dev_ptr) & 15u)) return FFT_ERR_MISALIGNED;
+    DeviceGuard guard(p->device);
+    if (p->ragged) return fftk::ragged_set_workspace(p->ragged, dev_ptr, &g_detail);
+    if (dev_ptr) {
+        if (p->ws_own) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(p->ws_own);
+            p->ws_own = nullptr;
+        }
+        p->ws_user = dev_ptr;
+        return FFT_OK;
+    }
+    p->ws_user = nullptr;
+    return alloc_workspace(p);
+}
+
+fft_status fft_plan_sizes(fft_plan p, int64_t* transforms, int64_t* elements, double* flops) {
+    if (!plan_ok(p)) return FFT_ERR_INVALID_ARG;
+    if (transforms) *transforms = p->batch;
+    if (elements) *elements = p->elements;
+    if (flops) *flops = p->flops;
+    return FFT_OK;
+}
+
+fft_status fft_plan_describe(fft_plan p, char* buf, size_t len) {
+    if (!plan_ok(p)) return FFT_ERR_INVALID_ARG;
+    return copy_out(describe(p), buf, len);
+}
+
+fft_status fft_query_decomposition(int64_t n, fft_layout layout, char* buf, size_t len) {
+    const int log2n = fftk::ilog2_exact(n);
+    if (log2n < 0 || log2n > fftk::kMaxLog2N) return FFT_ERR_INVALID_SIZE;
+    if (!valid_layout(layout)) return FFT_ERR_INVALID_ARG;
+    const Decomp d = fftk::default_decomposition(log2n);
+    std::string s = "{\"n\": " + std::to_string(n) + ", \"default\": \"" + d.str() + "\", \"available\": " +
+                    (fftk::decomposition_available(d, log2n, layout) ? "true" : "false") + ", \"candidates\": [";
+    const auto cands = fftk::candidate_decompositions(log2n, layout);
+    for (size_t i = 0; i < cands.size(); ++i) s += (i ? ", \"" : "\"") + cands[i].str() + "\"";
+    s += "]}";
+    return copy_out(s, buf, len);
+}
+
+fft_status fft_copy_device(const void* src, void* dst, size_t bytes, void* stream) {
+    if (!src || !dst) return FFT_ERR_NULL_POINTER;
+    if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst) | bytes) & 15u) return FFT_ERR_MISALIGNED;
+    if (overlaps(uintptr_t(src), bytes, uintptr_t(dst), bytes)) return FFT_ERR_INVALID_ARG;
+    hipError_t e = fftk::launch_copy(src, dst, bytes, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "copy launch");
+    return FFT_OK;
+}
+
+const char* fft_status_string(fft_status s) {
+    switch (s) {
+        case FFT_OK: return "FFT_OK";
+        case FFT_ERR_INVALID_SIZE: return "FFT_ERR_INVALID_SIZE: size is not a power of two in [1, 2^24]";
+        case FFT_ERR_INVALID_ARG: return "FFT_ERR_INVALID_ARG: invalid argument";
+        case FFT_ERR_NULL_POINTER: return "FFT_ERR_NULL_POINTER: required pointer is NULL";
+        case FFT_ERR_MISALIGNED: return "FFT_ERR_MISALIGNED: pointer not 16-byte aligned";
+        case FFT_ERR_ALLOC: return "FFT_ERR_ALLOC: allocation failed";
+        case FFT_ERR_HIP: return "FFT_ERR_HIP: HIP runtime error";
+        case FFT_ERR_NOT_SUPPORTED: return "FFT_ERR_NOT_SUPPORTED: no kernel for this configuration";
+    }
+    return "unknown fft_status";
+}
+
+const char* fft_last_error_detail(void) { return g_detail.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// hooks for the autotuner (same translation unit as the plan layout)
+// ---------------------------------------------------------------------------
+namespace fftk {
+
+fft_status plan_time_decomposition(fft_plan p, const Decomp& d, void* in, void* out, float* ms, std::string* detail) {
+    // build a throw-away plan with the candidate decomposition and time it
+    fft_plan_s tmp;
+    tmp.device = p->device;
+    tmp.n = p->n;
+    tmp.batch = p->batch;
+    tmp.log2n = p->log2n;
+    tmp.layout = p->layout;
+    tmp.dir = FFT_FORWARD;
+    tmp.elements = p->elements;
+    fft_status st = resolve(&tmp, d);
+    if (st == FFT_OK) st = build_tables(&tmp, nullptr);
+    if (st == FFT_OK) st = alloc_workspace(&tmp);
+    if (st != FFT_OK) {
+        free_plan_memory(&tmp);
+        tmp.magic = kDeadMagic;
+        return st;
+    }
+    const bool split = p->layout == FFT_LAYOUT_SPLIT;
+    const size_t half = size_t(p->elements) * sizeof(float);
+    void* ib = split ? static_cast<char*>(in) + half : nullptr;
+    void* ob = split ? static_cast<char*>(out) + half : nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    // warm up twice, then time a few launches
+    for (int i = 0; i < 2 && st == FFT_OK; ++i) st = run(&tmp, in, ib, out, ob, nullptr, false);
+    const int reps = 5;
+    if (st == FFT_OK && e == hipSuccess) {
+        e = hipEventRecord(e0, nullptr);
+        for (int i = 0; i < reps && st == FFT_OK; ++i) st = run(&tmp, in, ib, out, ob, nullptr, false);
+        if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        *ms = t / reps;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    free_plan_memory(&tmp);
+    tmp.magic = kDeadMagic;
+    if (st == FFT_OK && e != hipSuccess) {
+        *detail = std::string("autotune timing: ") + hipGetErrorString(e);
+        return FFT_ERR_HIP;
+    }
+    return st;
+}
+
+const Decomp& plan_decomposition(fft_plan p) { return p->dec; }
+int64_t plan_elements(fft_plan p) { return p->elements; }
+fft_layout plan_layout(fft_plan p) { return p->layout; }
+int plan_log2n(fft_plan p) { return p->log2n; }
+
+}  // namespace fftk

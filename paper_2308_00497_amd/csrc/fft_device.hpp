@@ -1,0 +1,344 @@
+// Device building blocks of the gfx950 FFT: complex arithmetic, the small
+// DFTs held in registers, the Stockham stage schedule and the block engine
+// that runs the stages of one sub-FFT through LDS.
+//
+// Mathematics (paper section 3, Eq. 1): with N = M*K,
+//   DFT_N = (DFT_K (x) I_M) D^N_M (I_K (x) DFT_M) Pi^N_K,
+// Pi^N_K the stride-K gather and D^N_M the diagonal of twiddle factors
+// w_N^(n2*k1), w_N = exp(-2 pi i / N).  A Stockham stage of radix R applies
+// this once per butterfly: for butterfly j < L/R with k = j mod Ns,
+//   u[r] = x[j + r*L/R] * w_(Ns*R)^(r*k)          (Mul(TwiddleCoe, X), Table 1)
+//   u    = DFT_R(u)                               (FusedMKIV on strided data)
+//   y[(j div Ns)*Ns*R + k + r*Ns] = u[r]           (FusedPKIV: self-sorting store)
+// and Ns grows by R per stage.  After the last stage y is in natural order.
+//
+// All kernels compute the forward transform.  The inverse uses
+// IDFT(x) = conj(DFT(conj(x))): the conjugations are sign flips applied on
+// load and store, exact in floating point, so one set of forward twiddle
+// tables serves both directions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fftk {
+
+// ---------------------------------------------------------------------------
+// complex helpers (float2 = (re, im))
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// a * w
+__device__ __forceinline__ float2 c_mul(float2 a, float2 w) {
+    return make_float2(fmaf(a.x, w.x, -(a.y * w.y)), fmaf(a.x, w.y, a.y * w.x));
+}
+// a * (-i)
+__device__ __forceinline__ float2 c_mul_mi(float2 a) { return make_float2(a.y, -a.x); }
+// flip the sign of the imaginary part when mask = 0x80000000 (conjugation)
+__device__ __forceinline__ float2 c_conj_mask(float2 a, uint32_t mask) {
+    return make_float2(a.x, __uint_as_float(__float_as_uint(a.y) ^ mask));
+}
+
+// exp(-2 pi i m / 16) for the register DFT_16 and DFT_8, correctly rounded
+// float literals of cos(pi/8), sin(pi/8) and sqrt(2)/2.
+constexpr float K_C1 = 0.923879532511286756128f;  // cos(pi/8)
+constexpr float K_S1 = 0.382683432365089771728f;  // sin(pi/8)
+constexpr float K_R2 = 0.707106781186547524401f;  // sqrt(2)/2
+
+// a * exp(-2 pi i / 8) = a * (r, -r)
+__device__ __forceinline__ float2 c_mul_w8_1(float2 a) { return make_float2(K_R2 * (a.x + a.y), K_R2 * (a.y - a.x)); }
+// a * exp(-2 pi i 3 / 8) = a * (-r, -r)
+__device__ __forceinline__ float2 c_mul_w8_3(float2 a) { return make_float2(K_R2 * (a.y - a.x), -K_R2 * (a.x + a.y)); }
+
+// ---------------------------------------------------------------------------
+// DFT_R in registers, forward, natural order in and out.
+// DFT_8 and DFT_16 are themselves one step of Eq. 1 (K = 2 or 4, M = 4).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void dft2(float2& a0, float2& a1) {
+    float2 t = a0;
+    a0 = c_add(t, a1);
+    a1 = c_sub(t, a1);
+}
+
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+    float2 t0 = c_add(a0, a2), t1 = c_sub(a0, a2);
+    float2 t2 = c_add(a1, a3), t3 = c_mul_mi(c_sub(a1, a3));
+    a0 = c_add(t0, t2);
+    a2 = c_sub(t0, t2);
+    a1 = c_add(t1, t3);
+    a3 = c_sub(t1, t3);
+}
+
+template <int R> struct Dft;
+
+template <> struct Dft<1> {
+    __device__ __forceinline__ static void run(float2*) {}
+};
+template <> struct Dft<2> {
+    __device__ __forceinline__ static void run(float2* v) { dft2(v[0], v[1]); }
+};
+template <> struct Dft<4> {
+    __device__ __forceinline__ static void run(float2* v) { dft4(v[0], v[1], v[2], v[3]); }
+};
+template <> struct Dft<8> {
+    __device__ __forceinline__ static void run(float2* v) {
+        // K = 2 sub-sequences of stride 2, DFT_4 each
+        dft4(v[0], v[2], v[4], v[6]);
+        dft4(v[1], v[3], v[5], v[7]);
+        // v[n2 + 2 k1] = A[n2][k1]; twiddle w_8^(n2 k1)
+        v[3] = c_mul_w8_1(v[3]);
+        v[5] = c_mul_mi(v[5]);
+        v[7] = c_mul_w8_3(v[7]);
+        // DFT_2 across n2: X[k1 + 4 k2]
+        float2 o[8];
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            float2 a = v[2 * k1], b = v[2 * k1 + 1];
+            o[k1] = c_add(a, b);
+            o[k1 + 4] = c_sub(a, b);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = o[i];
+    }
+};
+template <> struct Dft<16> {
+    __device__ __forceinline__ static void run(float2* v) {
+        // K = 4 sub-sequences x[4 n1 + n2], DFT_4 over n1
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
+        // v[n2 + 4 k1] = A[n2][k1]; twiddle w_16^(n2 k1)
+        const float2 w1 = make_float2(K_C1, -K_S1);
+        const float2 w3 = make_float2(K_S1, -K_C1);
+        const float2 w9 = make_float2(-K_C1, K_S1);
+        v[5] = c_mul(v[5], w1);     // n2=1 k1=1
+        v[9] = c_mul_w8_1(v[9]);    // n2=1 k1=2 (w^2)
+        v[13] = c_mul(v[13], w3);   // n2=1 k1=3
+        v[6] = c_mul_w8_1(v[6]);    // n2=2 k1=1 (w^2)
+        v[10] = c_mul_mi(v[10]);    // n2=2 k1=2 (w^4)
+        v[14] = c_mul_w8_3(v[14]);  // n2=2 k1=3 (w^6)
+        v[7] = c_mul(v[7], w3);     // n2=3 k1=1
+        v[11] = c_mul_w8_3(v[11]);  // n2=3 k1=2 (w^6)
+        v[15] = c_mul(v[15], w9);   // n2=3 k1=3
+        // DFT_4 across n2 for each k1 -> X[k1 + 4 k2] sits in v[4 k1 + k2]
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+        float2 o[16];
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = o[i];
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Stage schedule of an L-point sub-FFT with E elements per thread.
+// Stages of radix E, plus one stage of the remaining smaller radix (last, or
+// first when REMFIRST).  Stage s reads twiddles w_(Ns*R)^(r*k) from a table
+// laid out [k][r] (k < Ns, r < R) at offset twOff(s); stage 0 has Ns = 1 and
+// needs none.
+// ---------------------------------------------------------------------------
+template <int LOG2L_, int LOG2E_, bool REMFIRST_>
+struct Sched {
+    static constexpr int LOG2L = LOG2L_;
+    static constexpr bool REMFIRST = REMFIRST_;
+    static constexpr int L = 1 << LOG2L;
+    static constexpr int LE = (LOG2E_ < LOG2L) ? LOG2E_ : LOG2L;  // effective log2 E
+    static constexpr int E = 1 << LE;
+    static constexpr int T = L / E;  // threads per sub-FFT
+    static constexpr int NFULL = LE ? LOG2L / LE : 0;
+    static constexpr int REM = LE ? LOG2L % LE : 0;
+    static constexpr int NST = NFULL + (REM ? 1 : 0);
+
+    __host__ __device__ static constexpr int log2R(int s) {
+        return REM == 0 ? LE : (REMFIRST ? (s == 0 ? REM : LE) : (s == NST - 1 ? REM : LE));
+    }
+    __host__ __device__ static constexpr int log2NS(int s) {
+        int a = 0;
+        for (int q = 0; q < s; ++q) a += log2R(q);
+        return a;
+    }
+    __host__ __device__ static constexpr int twOff(int s) {
+        int a = 0;
+        for (int q = 1; q < s; ++q) a += 1 << (log2NS(q) + log2R(q));
+        return a;
+    }
+    static constexpr int TW_SIZE = NST > 1 ? twOff(NST) : 0;
+};
+
+// LDS index of element i of group g: one float2 of padding every 16 elements
+// breaks the power-of-two strides of the Stockham stores across banks.
+template <int GS>
+__device__ __forceinline__ int lds_at(int g, int i) { return g * GS + i + (i >> 4); }
+
+// Synchronisation between stages: a workgroup barrier, or (when every
+// sub-FFT lives inside one wavefront) only a wavefront-scope fence.
+template <bool WAVE>
+__device__ __forceinline__ void stage_sync() {
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block engine: G independent L-point sub-FFTs per workgroup, T threads each.
+// Thread -> (g, t) mapping per stage: "g-fast" (g = tid % G) or "t-fast"
+// (t = tid % T).  The first stage uses FIRST_GFAST, the last LAST_GFAST, the
+// ones between t-fast.  On entry v[m] holds input element t + T*m of sub-FFT
+// g under the first mapping; on exit v[m] holds output element t + T*m of
+// sub-FFT g under the last mapping.  GS is the LDS stride between groups.
+// ---------------------------------------------------------------------------
+template <class SC, int G, int GS, bool FIRST_GFAST, bool LAST_GFAST, bool WAVE>
+struct Engine {
+    static constexpr int E = SC::E;
+    static constexpr int T = SC::T;
+    static constexpr int NST = SC::NST;
+    static_assert(NST >= 1, "empty schedule");
+    static_assert(NST > 1 || FIRST_GFAST == LAST_GFAST, "one-stage engine cannot change mapping");
+
+    template <int S>
+    __device__ __forceinline__ static constexpr bool gfast() {
+        return S == 0 ? FIRST_GFAST : (S == NST - 1 ? LAST_GFAST : false);
+    }
+
+    template <int S>
+    __device__ __forceinline__ static void map(int tid, int& g, int& t) {
+        if constexpr (gfast<S>()) {
+            g = tid % G;
+            t = tid / G;
+        } else {
+            t = tid % T;
+            g = tid / T;
+        }
+    }
+
+    // butterflies of stage S on registers; j = t + b*T
+    template <int S>
+    __device__ __forceinline__ static void compute(float2 (&v)[E], int t, const float2* __restrict__ tw) {
+        constexpr int LR = SC::log2R(S);
+        constexpr int R = 1 << LR;
+        constexpr int B = E / R;
+        constexpr int LNS = SC::log2NS(S);
+        constexpr int NS = 1 << LNS;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = t + b * T;
+            float2 u[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) u[r] = v[b + r * B];
+            if constexpr (NS > 1) {
+                const int k = j & (NS - 1);
+                const float2* p = tw + SC::twOff(S) + k * R;
+                if constexpr (R == 2) {
+                    u[1] = c_mul(u[1], p[1]);
+                } else {
+                    const float4* p4 = reinterpret_cast<const float4*>(p);
+#pragma unroll
+                    for (int h = 0; h < R / 2; ++h) {
+                        float4 w = p4[h];
+                        if (h > 0) u[2 * h] = c_mul(u[2 * h], make_float2(w.x, w.y));
+                        u[2 * h + 1] = c_mul(u[2 * h + 1], make_float2(w.z, w.w));
+                    }
+                }
+            }
+            Dft<R>::run(u);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b + r * B] = u[r];
+        }
+    }
+
+    // store stage S's outputs into LDS at their self-sorting positions
+    template <int S>
+    __device__ __forceinline__ static void write(const float2 (&v)[E], int g, int t, float2* lds) {
+        constexpr int LR = SC::log2R(S);
+        constexpr int R = 1 << LR;
+        constexpr int B = E / R;
+        constexpr int LNS = SC::log2NS(S);
+        constexpr int NS = 1 << LNS;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = t + b * T;
+            const int k = j & (NS - 1);
+            const int base = ((j >> LNS) << (LNS + LR)) + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lds_at<GS>(g, base + r * NS)] = v[b + r * B];
+        }
+    }
+
+    __device__ __forceinline__ static void read(float2 (&v)[E], int g, int t, const float2* lds) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = lds[lds_at<GS>(g, t + T * m)];
+    }
+
+    template <int S>
+    __device__ __forceinline__ static void stage(float2 (&v)[E], float2* lds, const float2* __restrict__ tw, int tid) {
+        int g, t;
+        map<S>(tid, g, t);
+        if constexpr (S > 0) read(v, g, t, lds);
+        compute<S>(v, t, tw);
+        if constexpr (S < NST - 1) {
+            stage_sync<WAVE>();  // every thread has finished reading the previous exchange
+            write<S>(v, g, t, lds);
+            stage_sync<WAVE>();  // this exchange is complete
+            stage<S + 1>(v, lds, tw, tid);
+        }
+    }
+
+    __device__ __forceinline__ static void run(float2 (&v)[E], float2* lds, const float2* __restrict__ tw, int tid) {
+        stage<0>(v, lds, tw, tid);
+    }
+};
+
+// LDS floats2 needed by an engine with G groups of stride GS (0 if one stage)
+template <class SC, int G, int GS>
+constexpr int engine_lds_elems() { return SC::NST > 1 ? G * GS : 1; }
+
+// ---------------------------------------------------------------------------
+// Global memory access for the two layouts.  `a` is the interleaved array
+// (as float*) or the real array; `b` the imaginary array (split only).
+// ---------------------------------------------------------------------------
+template <bool SPLIT>
+__device__ __forceinline__ float2 gload(const float* a, const float* b, int64_t i) {
+    if constexpr (SPLIT) {
+        return make_float2(a[i], b[i]);
+    } else {
+        return reinterpret_cast<const float2*>(a)[i];
+    }
+}
+
+template <bool SPLIT>
+__device__ __forceinline__ void gstore(float* a, float* b, int64_t i, float2 v) {
+    if constexpr (SPLIT) {
+        a[i] = v.x;
+        b[i] = v.y;
+    } else {
+        reinterpret_cast<float2*>(a)[i] = v;
+    }
+}
+
+// workgroup index -> tile index such that the workgroups one XCD receives
+// (the dispatcher deals workgroups to the 8 XCDs in turn) take consecutive
+// tiles, which then share L2 lines; identity when the count is not a
+// multiple of 8.
+__device__ __forceinline__ int64_t xcd_tile(int64_t wg, int64_t count) {
+    if (count & 7) return wg;
+    return (wg & 7) * (count >> 3) + (wg >> 3);
+}
+
+// w_M^e = exp(-2 pi i e / M) from two FP64 tables, A[i] = w_M^(i << hbits) and
+// B[i] = w_M^i (i < 2^hbits): the product is formed in FP64 and rounded once.
+__device__ __forceinline__ float2 twiddle_2level(const double2* __restrict__ ta, const double2* __restrict__ tb,
+                                                 int64_t e, int hbits) {
+    const double2 a = ta[e >> hbits];
+    const double2 c = tb[e & ((int64_t(1) << hbits) - 1)];
+    const double re = fma(a.x, c.x, -(a.y * c.y));
+    const double im = fma(a.x, c.y, a.y * c.x);
+    return make_float2(static_cast<float>(re), static_cast<float>(im));
+}
+
+}  // namespace fftk

@@ -1,0 +1,30 @@
+// Instances of the multi-pass kernel: sub-FFT length L = 2^6 .. 2^12 with a
+// few column-tile widths C each, in the four layout combinations a plan uses
+// (first pass: user layout -> interleaved workspace; later passes:
+// interleaved -> interleaved or -> user layout).
+#include "kernels.hpp"
+
+namespace fftk {
+
+#define FFT_P(l, c)                                                                                 \
+    pass_entry<l, 4, c, true, false, false>(), pass_entry<l, 4, c, true, true, false>(),            \
+        pass_entry<l, 4, c, false, false, false>(), pass_entry<l, 4, c, false, false, true>()
+
+static const PassKernel kPass[] = {
+    FFT_P(6, 4), FFT_P(6, 6),
+    FFT_P(7, 4), FFT_P(7, 5),
+    FFT_P(8, 3), FFT_P(8, 4),
+    FFT_P(9, 3), FFT_P(9, 4),
+    FFT_P(10, 2), FFT_P(10, 3),
+    FFT_P(11, 2),
+    FFT_P(12, 1), FFT_P(12, 2),
+};
+
+#undef FFT_P
+
+const PassKernel* pass_kernels(int* count) {
+    *count = static_cast<int>(sizeof(kPass) / sizeof(kPass[0]));
+    return kPass;
+}
+
+}  // namespace fftk

@@ -1,0 +1,37 @@
+// Instances of the single-pass kernel: every N = 2^1 .. 2^14, both layouts,
+// 8 or 16 elements per thread, 64- or 256-thread workgroups for the sizes
+// where several transforms share a workgroup.
+#include "kernels.hpp"
+
+namespace fftk {
+
+#define FFT_S(n, e, w)                                                           \
+    single_entry<n, e, w, false>(), single_entry<n, e, w, true>()
+
+static const SingleKernel kSingle[] = {
+    // N <= 8: one thread per transform (E = N)
+    FFT_S(1, 4, 64), FFT_S(1, 4, 256),
+    FFT_S(2, 4, 64), FFT_S(2, 4, 256),
+    FFT_S(3, 4, 64), FFT_S(3, 4, 256),
+    FFT_S(4, 4, 64), FFT_S(4, 4, 256),
+    FFT_S(4, 3, 64), FFT_S(4, 3, 256),
+    FFT_S(5, 4, 64), FFT_S(5, 4, 256), FFT_S(5, 3, 64), FFT_S(5, 3, 256),
+    FFT_S(6, 4, 64), FFT_S(6, 4, 256), FFT_S(6, 3, 64), FFT_S(6, 3, 256),
+    FFT_S(7, 4, 64), FFT_S(7, 4, 256), FFT_S(7, 3, 64), FFT_S(7, 3, 256),
+    FFT_S(8, 4, 64), FFT_S(8, 4, 256), FFT_S(8, 3, 64), FFT_S(8, 3, 256),
+    FFT_S(9, 4, 64), FFT_S(9, 4, 256), FFT_S(9, 3, 64), FFT_S(9, 3, 256),
+    FFT_S(10, 4, 64), FFT_S(10, 4, 256), FFT_S(10, 3, 256),
+    FFT_S(11, 4, 256), FFT_S(11, 3, 256),
+    FFT_S(12, 4, 256), FFT_S(12, 3, 256),
+    FFT_S(13, 4, 256), FFT_S(13, 3, 256),
+    FFT_S(14, 4, 256),
+};
+
+#undef FFT_S
+
+const SingleKernel* single_kernels(int* count) {
+    *count = static_cast<int>(sizeof(kSingle) / sizeof(kSingle[0]));
+    return kSingle;
+}
+
+}  // namespace fftk

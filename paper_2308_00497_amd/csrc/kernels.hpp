@@ -1,0 +1,221 @@
+// Kernel templates of the gfx950 FFT and the host-side registry entries that
+// describe every compiled instance.
+//
+//  k_single  one whole transform per sub-FFT (N up to the single-pass limit):
+//            coalesced global load -> Stockham stages through LDS -> store.
+//  k_pass    one pass of a multi-pass transform (N above the single-pass
+//            limit): a radix-L Stockham pass over HBM whose DFT_L is itself a
+//            register/LDS sub-FFT.  N = L_1 L_2 ... L_P; pass p has
+//            Ns = L_1 ... L_(p-1) and, for butterfly column j < N/L_p with
+//            k = j mod Ns, reads x[j + r N/L_p] (r < L_p), multiplies by
+//            w_(Ns L_p)^(r k), transforms and writes
+//            y[(j div Ns) Ns L_p + k + q Ns].  With P = 2 this is the
+//            four-step scheme: Eq. 1 with M = L_1, K = L_2.
+//  k_gen_*   FP64 twiddle generation on the GPU, rounded once to FP32.
+#pragma once
+
+#include "fft_device.hpp"
+#include "registry.hpp"
+
+namespace fftk {
+
+// ---------------------------------------------------------------------------
+// twiddle generation (FP64 on the device)
+// ---------------------------------------------------------------------------
+
+// dst[k*R + r] = w_(Ns*R)^(r*k), k < Ns, r < R, computed as
+// (cos, -sin)(2 pi m / M) = (cospi, -sinpi)(2m/M) with the exact rational
+// argument 2m/M (M a power of two), then rounded once to float.
+__global__ void k_gen_stage_tw(float2* dst, int log2NS, int log2R);
+
+// dst[i] = w_M^(i*step) in FP64 for i < count.
+__global__ void k_gen_pow64(double2* dst, int log2M, int64_t step, int64_t count);
+
+// ---------------------------------------------------------------------------
+// single-pass kernel
+// ---------------------------------------------------------------------------
+template <int LOG2N, int LOG2E, int WGT>
+struct SingleShape {
+    using SC = Sched<LOG2N, LOG2E, false>;
+    static constexpr int G = SC::T >= WGT ? 1 : WGT / SC::T;  // transforms per workgroup
+    static constexpr int THREADS = G * SC::T;
+    static constexpr int GS = SC::L + (SC::L >> 4);
+    static constexpr int LDS = engine_lds_elems<SC, G, GS>();
+    static constexpr bool WAVE = SC::T <= 64;
+};
+
+template <int LOG2N, int LOG2E, int WGT, bool SPLIT>
+__global__ void __launch_bounds__((SingleShape<LOG2N, LOG2E, WGT>::THREADS))
+k_single(const float* ia, const float* ib, float* oa, float* ob, const float2* __restrict__ tw,
+         int64_t batch, uint32_t conj_in, uint32_t conj_out) {
+    using SH = SingleShape<LOG2N, LOG2E, WGT>;
+    using SC = typename SH::SC;
+    constexpr int E = SC::E, T = SC::T, L = SC::L;
+    __shared__ float2 lds[SH::LDS];
+
+    const int tid = threadIdx.x;
+    const int t = tid % T, g = tid / T;
+    const int64_t tr = static_cast<int64_t>(blockIdx.x) * SH::G + g;
+    const bool active = tr < batch;
+    const int64_t base = tr * L + t;
+
+    float2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+        v[m] = active ? c_conj_mask(gload<SPLIT>(ia, ib, base + T * m), conj_in) : make_float2(0.f, 0.f);
+
+    Engine<SC, SH::G, SH::GS, false, false, SH::WAVE>::run(v, lds, tw, tid);
+
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) gstore<SPLIT>(oa, ob, base + T * m, c_conj_mask(v[m], conj_out));
+    }
+}
+
+template <int LOG2N, int LOG2E, int WGT, bool SPLIT>
+hipError_t launch_single(const float* ia, const float* ib, float* oa, float* ob, const float2* tw,
+                         int64_t batch, uint32_t conj_in, uint32_t conj_out, hipStream_t s) {
+    using SH = SingleShape<LOG2N, LOG2E, WGT>;
+    const int64_t blocks = (batch + SH::G - 1) / SH::G;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_single<LOG2N, LOG2E, WGT, SPLIT>), dim3(static_cast<unsigned>(blocks)),
+                       dim3(SH::THREADS), 0, s, ia, ib, oa, ob, tw, batch, conj_in, conj_out);
+    return hipGetLastError();
+}
+
+template <class SC>
+EngineInfo engine_info() {
+    EngineInfo e{};
+    e.log2l = SC::LOG2L;
+    e.log2e = SC::LE;
+    e.remfirst = SC::REMFIRST;
+    e.nst = SC::NST;
+    e.tw_size = SC::TW_SIZE;
+    for (int s = 0; s < SC::NST && s < kMaxStages; ++s) {
+        e.log2ns[s] = SC::log2NS(s);
+        e.log2r[s] = SC::log2R(s);
+        e.tw_off[s] = SC::twOff(s);
+    }
+    return e;
+}
+
+template <int LOG2N, int LOG2E, int WGT, bool SPLIT>
+SingleKernel single_entry() {
+    using SH = SingleShape<LOG2N, LOG2E, WGT>;
+    SingleKernel k{};
+    k.log2n = LOG2N;
+    k.log2e = SH::SC::LE;
+    k.wgt = WGT;
+    k.split = SPLIT;
+    k.fn = &launch_single<LOG2N, LOG2E, WGT, SPLIT>;
+    k.eng = engine_info<typename SH::SC>();
+    k.threads = SH::THREADS;
+    k.per_wg = SH::G;
+    k.lds_bytes = SH::LDS * sizeof(float2);
+    return k;
+}
+
+// ---------------------------------------------------------------------------
+// pass kernel of the multi-pass scheme
+// ---------------------------------------------------------------------------
+template <int LOG2L, int LOG2E, int LOG2C>
+struct PassShape {
+    using SC = Sched<LOG2L, LOG2E, false>;
+    static constexpr int C = 1 << LOG2C;                // columns per workgroup
+    static constexpr int THREADS = C * SC::T;
+    // group stride: the padded column plus an odd-ish skew so that the
+    // column-fast first stage spreads its C lanes over distinct banks
+    static constexpr int GS = SC::L + (SC::L >> 4) + 2;
+    static constexpr int LDS = C * GS;
+};
+
+template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT>
+__global__ void __launch_bounds__((PassShape<LOG2L, LOG2E, LOG2C>::THREADS))
+k_pass(const float* ia, const float* ib, float* oa, float* ob, const float2* __restrict__ tw,
+       const double2* __restrict__ ta, const double2* __restrict__ tb, int log2N, int log2Ns, int hbits,
+       int64_t tiles, uint32_t conj_in, uint32_t conj_out) {
+    using SH = PassShape<LOG2L, LOG2E, LOG2C>;
+    using SC = typename SH::SC;
+    constexpr int E = SC::E, T = SC::T, C = SH::C;
+    static_assert(SC::NST >= 2, "a pass needs at least two stages to change the thread mapping");
+    __shared__ float2 lds[SH::LDS];
+
+    const int tid = threadIdx.x;
+    const int64_t N = int64_t(1) << log2N;
+    const int64_t stride = N >> LOG2L;                   // distance between the L inputs of a column
+    const int log2TilesPerT = log2N - LOG2L - LOG2C;     // tiles per transform (power of two)
+    const int64_t tile = xcd_tile(blockIdx.x, tiles);
+    const int64_t b = tile >> log2TilesPerT;
+    const int64_t j0 = (tile & ((int64_t(1) << log2TilesPerT) - 1)) << LOG2C;
+    const int64_t tbase = b * N;
+    const int64_t NsMask = (int64_t(1) << log2Ns) - 1;
+
+    // load: column-fast mapping, C consecutive columns form one contiguous run
+    float2 v[E];
+    {
+        const int c = tid & (C - 1), tp = tid >> LOG2C;
+        const int64_t j = j0 + c;
+        const int64_t k = j & NsMask;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int r = tp + T * m;
+            float2 x = c_conj_mask(gload<SPLIT_IN>(ia, ib, tbase + j + r * stride), conj_in);
+            if constexpr (!FIRST) x = c_mul(x, twiddle_2level(ta, tb, static_cast<int64_t>(r) * k, hbits));
+            v[m] = x;
+        }
+    }
+
+    // first pass stores whole columns (thread-fast), later passes store runs of
+    // C consecutive columns (column-fast)
+    Engine<SC, C, SH::GS, true, !FIRST, false>::run(v, lds, tw, tid);
+
+    if constexpr (FIRST) {
+        const int t = tid % T, c = tid / T;
+        const int64_t j = j0 + c;
+        const int64_t obase = tbase + (j << LOG2L) + t;
+#pragma unroll
+        for (int m = 0; m < E; ++m) gstore<SPLIT_OUT>(oa, ob, obase + T * m, c_conj_mask(v[m], conj_out));
+    } else {
+        const int c = tid & (C - 1), tp = tid >> LOG2C;
+        const int64_t j = j0 + c;
+        const int64_t k = j & NsMask;
+        const int64_t obase = tbase + ((j >> log2Ns) << (log2Ns + LOG2L)) + k;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int64_t q = tp + T * m;
+            gstore<SPLIT_OUT>(oa, ob, obase + (q << log2Ns), c_conj_mask(v[m], conj_out));
+        }
+    }
+}
+
+template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT>
+hipError_t launch_pass(const float* ia, const float* ib, float* oa, float* ob, const float2* tw,
+                       const double2* ta, const double2* tb, int log2N, int log2Ns, int hbits,
+                       int64_t batch, uint32_t conj_in, uint32_t conj_out, hipStream_t s) {
+    using SH = PassShape<LOG2L, LOG2E, LOG2C>;
+    const int64_t tiles = (int64_t(1) << (log2N - LOG2L - LOG2C)) * batch;
+    if (tiles > 0x7fffffff || log2N < LOG2L + LOG2C) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_pass<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT>),
+                       dim3(static_cast<unsigned>(tiles)), dim3(SH::THREADS), 0, s, ia, ib, oa, ob, tw, ta, tb,
+                       log2N, log2Ns, hbits, tiles, conj_in, conj_out);
+    return hipGetLastError();
+}
+
+template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT>
+PassKernel pass_entry() {
+    using SH = PassShape<LOG2L, LOG2E, LOG2C>;
+    PassKernel k{};
+    k.log2l = LOG2L;
+    k.log2e = SH::SC::LE;
+    k.log2c = LOG2C;
+    k.first = FIRST;
+    k.split_in = SPLIT_IN;
+    k.split_out = SPLIT_OUT;
+    k.fn = &launch_pass<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT>;
+    k.eng = engine_info<typename SH::SC>();
+    k.threads = SH::THREADS;
+    k.lds_bytes = SH::LDS * sizeof(float2);
+    return k;
+}
+
+}  // namespace fftk

@@ -1,0 +1,230 @@
+// Decompositions of a power-of-two size into GPU kernels (host only).
+//
+// Eq. 1 of the paper (section 3) factors DFT_N for any N = M K; applied
+// recursively it turns a power-of-two N into a chain of radix stages.  The
+// paper notes (section 4) that the choice of radices decides speed (radix-2
+// N = 128 is slow, N = 256 as 16 x 16 is fast) and that a runtime planner is
+// future work; this file enumerates the choices and picks a default, and the
+// autotuner times them.
+#include "plan.hpp"
+
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+namespace fftk {
+
+int ilog2_exact(int64_t v) {
+    if (v <= 0 || (v & (v - 1))) return -1;
+    int k = 0;
+    while ((int64_t(1) << k) < v) ++k;
+    return k;
+}
+
+std::string Decomp::str() const {
+    char buf[64];
+    switch (kind) {
+        case COPY:
+            return "copy";
+        case SINGLE:
+            snprintf(buf, sizeof buf, "single:e%d:w%d", log2e, wgt);
+            return buf;
+        case MULTI: {
+            std::string s = "multi:";
+            for (size_t p = 0; p < log2l.size(); ++p) {
+                snprintf(buf, sizeof buf, "%s%dc%d", p ? "," : "", log2l[p], log2c[p]);
+                s += buf;
+            }
+            return s;
+        }
+    }
+    return "?";
+}
+
+bool Decomp::parse(const std::string& s, Decomp* out) {
+    Decomp d;
+    if (s == "copy") {
+        d.kind = COPY;
+        *out = d;
+        return true;
+    }
+    int e = 0, w = 0;
+    if (sscanf(s.c_str(), "single:e%d:w%d", &e, &w) == 2) {
+        d.kind = SINGLE;
+        d.log2e = e;
+        d.wgt = w;
+        *out = d;
+        return true;
+    }
+    if (s.compare(0, 6, "multi:") == 0) {
+        d.kind = MULTI;
+        const char* p = s.c_str() + 6;
+        while (*p) {
+            int l = 0, c = 0, used = 0;
+            if (sscanf(p, "%dc%d%n", &l, &c, &used) != 2) return false;
+            d.log2l.push_back(l);
+            d.log2c.push_back(c);
+            p += used;
+            if (*p == ',') ++p;
+            else if (*p) return false;
+        }
+        if (d.log2l.empty()) return false;
+        *out = d;
+        return true;
+    }
+    return false;
+}
+
+const SingleKernel* find_single(int log2n, int log2e, int wgt, bool split) {
+    int cnt = 0;
+    const SingleKernel* t = single_kernels(&cnt);
+    const int le = log2e < log2n ? log2e : log2n;
+    for (int i = 0; i < cnt; ++i)
+        if (t[i].log2n == log2n && t[i].log2e == le && t[i].wgt == wgt && t[i].split == split) return &t[i];
+    return nullptr;
+}
+
+const PassKernel* find_pass(int log2l, int log2c, bool first, bool split_in, bool split_out) {
+    int cnt = 0;
+    const PassKernel* t = pass_kernels(&cnt);
+    for (int i = 0; i < cnt; ++i)
+        if (t[i].log2l == log2l && t[i].log2c == log2c && t[i].first == first && t[i].split_in == split_in &&
+            t[i].split_out == split_out)
+            return &t[i];
+    return nullptr;
+}
+
+// column tile for a sub-FFT length: the widest compiled one up to 16 columns
+// (128-byte runs of interleaved data), else the narrowest compiled one
+static int default_log2c(int log2l) {
+    int best_le4 = -1, min_any = 99;
+    int cnt = 0;
+    const PassKernel* t = pass_kernels(&cnt);
+    for (int i = 0; i < cnt; ++i) {
+        if (t[i].log2l != log2l) continue;
+        const int c = t[i].log2c;
+        if (c <= 4 && c > best_le4) best_le4 = c;
+        if (c < min_any) min_any = c;
+    }
+    return best_le4 >= 0 ? best_le4 : (min_any == 99 ? -1 : min_any);
+}
+
+static bool pass_chain_available(const std::vector<int>& ls, const std::vector<int>& cs, fft_layout layout) {
+    const bool split = layout == FFT_LAYOUT_SPLIT;
+    const size_t P = ls.size();
+    if (P < 2) return false;
+    for (size_t p = 0; p < P; ++p) {
+        const bool first = p == 0;
+        const bool sin = first && split;
+        const bool sout = (p == P - 1) && split;
+        if (!find_pass(ls[p], cs[p], first, sin, sout)) return false;
+    }
+    return true;
+}
+
+bool decomposition_available(const Decomp& d, int log2n, fft_layout layout) {
+    switch (d.kind) {
+        case Decomp::COPY:
+            return log2n == 0;
+        case Decomp::SINGLE:
+            return log2n >= 1 && find_single(log2n, d.log2e, d.wgt, layout == FFT_LAYOUT_SPLIT) != nullptr;
+        case Decomp::MULTI: {
+            int sum = 0;
+            for (int l : d.log2l) sum += l;
+            if (sum != log2n || d.log2l.size() != d.log2c.size()) return false;
+            // every pass needs at least 2^log2c columns
+            for (size_t p = 0; p < d.log2l.size(); ++p)
+                if (log2n - d.log2l[p] < d.log2c[p]) return false;
+            return pass_chain_available(d.log2l, d.log2c, layout);
+        }
+    }
+    return false;
+}
+
+// Split log2n into `parts` near-equal sub-lengths, largest first.
+static std::vector<int> even_split(int log2n, int parts) {
+    std::vector<int> v(parts, log2n / parts);
+    for (int i = 0; i < log2n % parts; ++i) v[i] += 1;
+    return v;
+}
+
+Decomp default_decomposition(int log2n) {
+    Decomp d;
+    if (log2n <= 0) {
+        d.kind = Decomp::COPY;
+        return d;
+    }
+    if (log2n <= 14) {
+        d.kind = Decomp::SINGLE;
+        d.log2e = 4;
+        d.wgt = 256;
+        return d;
+    }
+    // passes of at most 2^9 points keep 16-column tiles (128-byte runs)
+    int parts = (log2n + 8) / 9;
+    if (parts < 2) parts = 2;
+    d.kind = Decomp::MULTI;
+    d.log2l = even_split(log2n, parts);
+    for (int l : d.log2l) d.log2c.push_back(default_log2c(l));
+    return d;
+}
+
+std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout) {
+    std::vector<Decomp> out;
+    if (log2n <= 0) {
+        Decomp d;
+        d.kind = Decomp::COPY;
+        out.push_back(d);
+        return out;
+    }
+    // single-pass variants
+    for (int e : {4, 3})
+        for (int w : {256, 64}) {
+            Decomp d;
+            d.kind = Decomp::SINGLE;
+            d.log2e = e;
+            d.wgt = w;
+            if (decomposition_available(d, log2n, layout)) {
+                bool dup = false;
+                for (auto& o : out) dup |= (find_single(log2n, o.log2e, o.wgt, false) ==
+                                            find_single(log2n, d.log2e, d.wgt, false));
+                if (!dup) out.push_back(d);
+            }
+        }
+    // multi-pass chains with 2 or 3 passes, every sub-length and tile compiled
+    int cnt = 0;
+    const PassKernel* t = pass_kernels(&cnt);
+    std::vector<std::pair<int, int>> lc;  // distinct (log2l, log2c)
+    for (int i = 0; i < cnt; ++i) {
+        std::pair<int, int> x(t[i].log2l, t[i].log2c);
+        bool seen = false;
+        for (auto& y : lc) seen |= (y == x);
+        if (!seen) lc.push_back(x);
+    }
+    for (int parts = 2; parts <= 3; ++parts) {
+        // enumerate ordered tuples of (l, c)
+        std::vector<size_t> idx(parts, 0);
+        while (true) {
+            int sum = 0;
+            for (int p = 0; p < parts; ++p) sum += lc[idx[p]].first;
+            if (sum == log2n) {
+                Decomp d;
+                d.kind = Decomp::MULTI;
+                for (int p = 0; p < parts; ++p) {
+                    d.log2l.push_back(lc[idx[p]].first);
+                    d.log2c.push_back(lc[idx[p]].second);
+                }
+                // keep sub-lengths non-increasing to bound the search
+                bool sorted = true;
+                for (int p = 1; p < parts; ++p) sorted &= d.log2l[p] <= d.log2l[p - 1];
+                if (sorted && decomposition_available(d, log2n, layout)) out.push_back(d);
+            }
+            int p = parts - 1;
+            while (p >= 0 && ++idx[p] == lc.size()) idx[p--] = 0;
+            if (p < 0) break;
+        }
+    }
+    return out;
+}
+
+}  // namespace fftk

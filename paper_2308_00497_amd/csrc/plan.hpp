@@ -1,0 +1,49 @@
+// Host-side plan logic: decompositions, their text form and the plan object.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fft.h"
+#include "registry.hpp"
+
+namespace fftk {
+
+// How one transform size is computed.
+//   copy     N = 1
+//   single   one single-pass kernel (E = 2^log2e elements per thread,
+//            workgroups of at least `wgt` threads)
+//   multi    P passes of sub-FFT lengths 2^log2l[p] with 2^log2c[p] columns per
+//            workgroup, sum of log2l = log2 N (Stockham radix-L passes)
+struct Decomp {
+    enum Kind { COPY = 0, SINGLE = 1, MULTI = 2 } kind = COPY;
+    int log2e = 4;
+    int wgt = 256;
+    std::vector<int> log2l;
+    std::vector<int> log2c;
+
+    std::string str() const;                           // "copy" | "single:e4:w256" | "multi:8c4,8c4,8c4"
+    static bool parse(const std::string& s, Decomp* out);
+    bool operator==(const Decomp& o) const { return str() == o.str(); }
+};
+
+// single-pass limit and the default (untuned) choice
+constexpr int kMaxLog2N = 24;
+Decomp default_decomposition(int log2n);
+
+// every decomposition the library can run for log2n (autotuner candidates)
+std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout);
+
+// kernel lookup; nullptr when no such instance was compiled
+const SingleKernel* find_single(int log2n, int log2e, int wgt, bool split);
+const PassKernel* find_pass(int log2l, int log2c, bool first, bool split_in, bool split_out);
+
+// true when every kernel the decomposition needs exists for this layout
+bool decomposition_available(const Decomp& d, int log2n, fft_layout layout);
+
+int ilog2_exact(int64_t v);  // log2 of a power of two, -1 otherwise
+
+}  // namespace fftk

@@ -1,0 +1,69 @@
+// Host-visible description of every compiled kernel instance.  The plan picks
+// entries from these tables; the engine metadata (stage radices, twiddle
+// table offsets) comes from the same constexpr schedule the kernels use, so
+// the host-generated tables always match what the device reads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fftk {
+
+constexpr int kMaxStages = 32;
+
+struct EngineInfo {
+    int log2l;              // sub-FFT length L = 2^log2l
+    int log2e;              // elements per thread
+    bool remfirst;          // smaller radix first
+    int nst;                // number of stages
+    int tw_size;            // float2 entries of the stage twiddle table
+    int log2ns[kMaxStages];
+    int log2r[kMaxStages];
+    int tw_off[kMaxStages];
+};
+
+using single_fn = hipError_t (*)(const float* ia, const float* ib, float* oa, float* ob, const float2* tw,
+                                 int64_t batch, uint32_t conj_in, uint32_t conj_out, hipStream_t s);
+
+struct SingleKernel {
+    int log2n;
+    int log2e;
+    int wgt;        // target threads per workgroup
+    bool split;
+    single_fn fn;
+    EngineInfo eng;
+    int threads;    // actual threads per workgroup
+    int per_wg;     // transforms per workgroup
+    size_t lds_bytes;
+};
+
+using pass_fn = hipError_t (*)(const float* ia, const float* ib, float* oa, float* ob, const float2* tw,
+                               const double2* ta, const double2* tb, int log2N, int log2Ns, int hbits,
+                               int64_t batch, uint32_t conj_in, uint32_t conj_out, hipStream_t s);
+
+struct PassKernel {
+    int log2l;
+    int log2e;
+    int log2c;      // columns per workgroup
+    bool first;
+    bool split_in;
+    bool split_out;
+    pass_fn fn;
+    EngineInfo eng;
+    int threads;
+    size_t lds_bytes;
+};
+
+// tables defined in the kernel translation units
+const SingleKernel* single_kernels(int* count);
+const PassKernel* pass_kernels(int* count);
+
+// plain streaming copy (16-byte accesses), bytes % 16 == 0
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+
+// twiddle generation launches
+hipError_t launch_gen_engine_tw(const EngineInfo& e, float2* dst, hipStream_t s);
+hipError_t launch_gen_pow64(double2* dst, int log2M, int64_t step, int64_t count, hipStream_t s);
+
+}  // namespace fftk

@@ -1,0 +1,45 @@
+"""Helpers shared by the GPU tests: host <-> device marshalling and oracle references."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+import workloads
+
+# per-transform relative L2 bound against the FP64 oracle
+TOL = 1e-5
+SIGN = {"forward": -1, "inverse": +1}
+
+
+def to_device(re: np.ndarray, im: np.ndarray, layout: str):
+    import torch
+    if layout == "split":
+        return (torch.from_numpy(np.ascontiguousarray(re)).cuda(), torch.from_numpy(np.ascontiguousarray(im)).cuda())
+    return torch.from_numpy(workloads.interleave(re, im)).cuda()
+
+
+def from_device(y, layout: str) -> np.ndarray:
+    import torch
+    torch.cuda.synchronize()
+    if layout == "split":
+        re, im = y
+        return re.cpu().numpy().astype(np.float64) + 1j * im.cpu().numpy().astype(np.float64)
+    return y.cpu().numpy().astype(np.complex128)
+
+
+def widen(re: np.ndarray, im: np.ndarray) -> np.ndarray:
+    """The float32 input, widened exactly to complex128."""
+    return re.astype(np.float64) + 1j * im.astype(np.float64)
+
+
+def oracle_ref(re: np.ndarray, im: np.ndarray, direction: str, threads: int = 8) -> np.ndarray:
+    return oracle.fft(widen(re, im), SIGN[direction], threads=threads)
+
+
+def assert_parity(y: np.ndarray, ref: np.ndarray, what: str, tol: float = TOL) -> float:
+    y = y.reshape(ref.shape)
+    errs = oracle.rel_l2_rows(y.reshape(-1, ref.shape[-1]), ref.reshape(-1, ref.shape[-1]))
+    worst = float(errs.max())
+    print(f"[parity] {what}: max per-transform rel-L2 {worst:.3e}", flush=True)
+    assert worst <= tol, f"{what}: rel-L2 {worst:.3e} > {tol}"
+    return worst

@@ -1,0 +1,132 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol that
+include/fft.h declares, and rejects bad arguments before touching the GPU.
+Also the host-only plan logic (decomposition choice) and the autotune cache
+format.  No compute call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "fft.h")).read()
+    return sorted(set(re.findall(r"^(?:fft_status|const char \*)\s*(fft_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def fftlib():
+    import paper_2308_00497_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def lib(fftlib):
+    return fftlib.lib
+
+
+def test_header_declares_the_boundary():
+    names = header_functions()
+    for required in ("fft_plan_create", "fft_execute", "fft_execute_backward", "fft_plan_destroy",
+                     "fft_plan_create_ragged", "fft_plan_workspace_bytes", "fft_plan_set_workspace",
+                     "fft_status_string"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(fftlib):
+    so = ctypes.CDLL(fftlib._lib.LIB_PATH)
+    for name in header_functions():
+        assert hasattr(so, name), name
+    assert sorted(header_functions()) == sorted(fftlib._lib.EXPORTS)
+
+
+def test_status_strings(lib):
+    for code in range(8):
+        s = lib.fft_status_string(code).decode()
+        assert s.startswith("FFT_")
+    assert b"unknown" in lib.fft_status_string(99)
+
+
+def _create(lib, n, batch, layout=0, direction=-1):
+    h = ctypes.c_void_p()
+    rc = lib.fft_plan_create(ctypes.byref(h), n, batch, layout, direction)
+    return rc, h
+
+
+@pytest.mark.parametrize("n", [0, -4, 3, 12, 1000, 1 << 25, (1 << 24) + 1])
+def test_rejects_bad_sizes(lib, n):
+    rc, h = _create(lib, n, 1)
+    assert rc == 1 and h.value is None  # FFT_ERR_INVALID_SIZE
+
+
+@pytest.mark.parametrize("batch,layout,direction", [(0, 0, -1), (-1, 0, -1), (1, 2, -1), (1, 0, 0), (1, 0, 2)])
+def test_rejects_bad_args(lib, batch, layout, direction):
+    rc, h = _create(lib, 64, batch, layout, direction)
+    assert rc == 2 and h.value is None  # FFT_ERR_INVALID_ARG
+
+
+def test_null_out_pointer(lib):
+    assert lib.fft_plan_create(None, 64, 1, 0, -1) == 3
+
+
+def test_explicit_decomposition_validation(lib):
+    h = ctypes.c_void_p()
+    assert lib.fft_plan_create_explicit(ctypes.byref(h), 4096, 1, 0, -1, b"garbage") == 2
+    assert lib.fft_plan_create_explicit(ctypes.byref(h), 4096, 1, 0, -1, b"multi:8c4,5c4") == 7
+    assert lib.fft_plan_create_explicit(ctypes.byref(h), 4096, 1, 0, -1, b"single:e5:w256") == 7
+    assert lib.fft_plan_create_explicit(ctypes.byref(h), 4096, 1, 0, -1, None) == 3
+
+
+def test_ragged_validation(lib):
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int64 * 3)(64, 100, 256)
+    assert lib.fft_plan_create_ragged(ctypes.byref(h), arr, 3, 0, -1) == 1
+    arr = (ctypes.c_int64 * 2)(64, 256)
+    assert lib.fft_plan_create_ragged(ctypes.byref(h), arr, 0, 0, -1) == 2
+    assert lib.fft_plan_create_ragged(ctypes.byref(h), None, 2, 0, -1) == 3
+    assert lib.fft_plan_create_ragged(ctypes.byref(h), arr, 2, 7, -1) == 2
+
+
+def test_execute_rejects_null_plan(lib):
+    assert lib.fft_execute(None, 16, 16, 32, 32, None) == 2
+    assert lib.fft_execute_backward(None, 16, 16, 32, 32, None) == 2
+    assert lib.fft_plan_destroy(None) == 0
+    n = ctypes.c_size_t()
+    assert lib.fft_plan_workspace_bytes(None, ctypes.byref(n)) == 2
+    assert lib.fft_plan_set_workspace(None, None) == 2
+
+
+def test_copy_validation(lib):
+    assert lib.fft_copy_device(None, 16, 16, None) == 3
+    assert lib.fft_copy_device(16, 64, 17, None) == 4   # size not a multiple of 16
+    assert lib.fft_copy_device(8, 64, 16, None) == 4    # misaligned source
+    assert lib.fft_copy_device(16, 32, 64, None) == 2   # overlap
+
+
+@pytest.mark.parametrize("log2n", range(0, 25))
+def test_default_decomposition_covers_every_size(fftlib, log2n):
+    for layout in ("interleaved", "split"):
+        q = fftlib.query_decomposition(1 << log2n, layout)
+        assert q["available"], q
+        assert q["default"] in q["candidates"]
+        if log2n == 0:
+            assert q["default"] == "copy"
+        elif log2n <= 14:
+            assert q["default"].startswith("single:")
+        else:
+            parts = q["default"].split(":")[1].split(",")
+            assert sum(int(p.split("c")[0]) for p in parts) == log2n
+
+
+def test_query_rejects_bad_size(lib):
+    buf = ctypes.create_string_buffer(256)
+    assert lib.fft_query_decomposition(12, 0, buf, 256) == 1
+    assert lib.fft_query_decomposition(16, 9, buf, 256) == 2
+
+
+def test_query_truncates(lib):
+    buf = ctypes.create_string_buffer(8)
+    assert lib.fft_query_decomposition(1 << 24, 0, buf, 8) == 0
+    assert len(buf.value) == 7
