@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Benchmark: batched 1D C2C FP32 FFT on one MI355X.
+
+Default workload (one "step"): N = 4096, batch 8192, entries N(0, 1) from
+seed 2, transformed four times per step - interleaved forward, interleaved
+inverse, split forward, split inverse - with inputs resident in HBM.  Prints
+one JSON line: whole-step GFLOP/s with the paper's flop model (5 N log2 N per
+transform, section 4), the HBM roofline of the dominant kernel (algorithmic
+bytes / its average launch time from HIP events on its stream), and the FP64
+oracle timed on the host cores on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GFLOP/s (5N log2 N) and % of peak HBM GB/s, FP32 C2C, rel-L2 ≤1e-5 vs FP64"
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E peak, GB/s
+BYTES_PER_ELEM_PASS = 16       # 8 B read + 8 B written per complex element per HBM pass
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "c2_single_n4096_counters.json")
+KERNEL_SOURCES = ["paper_2308_00497_amd/csrc/fft_device.hpp", "paper_2308_00497_amd/csrc/kernels.hpp",
+                  "paper_2308_00497_amd/csrc/k_single.hip"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(bytes_alg: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    try:
+        with open(PROFILE_COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return float(c["hbm_bytes_per_launch"])
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=250)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the batched transforms need no "
+              "exchange between GPUs, so the whole-job rate at N GPUs is N times one GPU's share.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2308_00497_amd as fftlib
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n, batch = 4096, 8192
+    log(f"[bench] generating C2 inputs N={n} batch={batch}")
+    re, im = workloads.c2()
+    z = workloads.interleave(re, im)
+    xi = torch.from_numpy(z).to(dev)
+    yi = torch.empty_like(xi)
+    xs = (torch.from_numpy(re).to(dev), torch.from_numpy(im).to(dev))
+    ys = (torch.empty_like(xs[0]), torch.empty_like(xs[1]))
+
+    variants = []
+    for layout in ("interleaved", "split"):
+        for direction in ("forward", "inverse"):
+            plan = fftlib.Plan(n, batch, layout, direction)
+            x, y = (xi, yi) if layout == "interleaved" else (xs, ys)
+            variants.append({"name": f"{layout}-{direction}", "plan": plan, "x": x, "y": y,
+                             "desc": plan.describe()})
+    flops_per_launch = variants[0]["plan"].nominal_flops
+    bytes_per_launch = float(n) * batch * BYTES_PER_ELEM_PASS
+
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        for v in variants:
+            v["plan"].execute(v["x"], out=v["y"])
+    torch.cuda.synchronize()
+
+    K = args.steps
+    evs = {v["name"]: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                       for _ in range(K)] for v in variants}
+    log(f"[bench] timing {K} steps x {len(variants)} launches")
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for i in range(K):
+        for v in variants:
+            e0, e1 = evs[v["name"]][i]
+            e0.record(stream)
+            v["plan"].execute(v["x"], out=v["y"], stream=stream)
+            e1.record(stream)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    ms_per_step = total_ms / K
+    value = flops_per_launch * len(variants) * K / (total_ms * 1e-3) / 1e9
+
+    per_variant = {}
+    for v in variants:
+        d = [a.elapsed_time(b) for a, b in evs[v["name"]]]
+        avg = float(np.mean(d))
+        per_variant[v["name"]] = {"avg_ms": avg, "median_ms": float(np.median(d)), "min_ms": float(np.min(d)),
+                                  "gbs": bytes_per_launch / (avg * 1e-3) / 1e9,
+                                  "gflops": flops_per_launch / (avg * 1e-3) / 1e9,
+                                  "decomposition": v["desc"]["decomposition"]}
+    dom = max(per_variant, key=lambda k: per_variant[k]["avg_ms"])
+    dom_v = per_variant[dom]
+    achieved = dom_v["gbs"]
+    traffic = counter_traffic(bytes_per_launch)
+
+    # practical ceiling: streaming copy of the same bytes (256 MiB read + 256 MiB written)
+    nbytes = xi.numel() * xi.element_size()
+    for _ in range(3):
+        fftlib.copy_device(xi, yi)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    c0.record(stream)
+    for _ in range(20):
+        fftlib.copy_device(xi, yi, stream=stream)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * nbytes / (c0.elapsed_time(c1) / 20 * 1e-3) / 1e9
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched 1D C2C FFT, N=4096 x batch 8192, N(0,1) seed 2; one step = "
+                               "interleaved forward + interleaved inverse + split forward + split inverse",
+                   "n": n, "batch": batch, "launches_per_step": len(variants),
+                   "decomposition": variants[0]["desc"]["decomposition"]},
+        "hbm_frac_step": round(bytes_per_launch * len(variants) / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": f"k_single N=4096 {per_variant[dom]['decomposition']} ({dom})",
+                     "bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(dom_v["avg_ms"], 5)},
+        "per_variant": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                        for k, v in per_variant.items()},
+        "copy_ceiling": {"gbs": round(copy_gbs, 1), "frac": round(copy_gbs / PEAK_HBM_GBS, 4),
+                         "bytes": 2 * nbytes},
+    }
+
+    if not args.no_cpu:
+        # fresh interleaved forward result for the accuracy check on the sample rows
+        variants[0]["plan"].execute(xi, out=yi)
+        torch.cuda.synchronize()
+        result["cpu_baseline"] = cpu_baseline(re, im, yi, n, args.cpu_seconds)
+
+    print(json.dumps(result), flush=True)
+    for v in variants:
+        v["plan"].close()
+    return 0
+
+
+def cpu_baseline(re, im, y_gpu, n, seconds):
+    """FP64 oracle (recursive radix-2, plain C, -O2) on a bounded sample of the
+    workload, threaded over the sample on the host cores; its outputs also check
+    the GPU's forward transform of the same rows (accuracy gate)."""
+    import oracle
+
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    rows = np.arange(0, re.shape[0], 8)[:1024]           # every 8th transform, 1024 of them
+    xr = re[rows].astype(np.float64)
+    xim = im[rows].astype(np.float64)
+    yr = np.empty_like(xr)
+    yim = np.empty_like(xim)
+    runs = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.fft_split_inplace_arrays(xr, xim, yr, yim, oracle.FORWARD, threads)
+        runs += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    flops = 5.0 * n * np.log2(n) * len(rows) * runs
+    out = {"value": round(flops / el / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": f"{len(rows)} of the 8192 N=4096 transforms (every 8th), FP64 forward, "
+                     f"repeated {runs}x over {el:.1f} s on {threads} threads"}
+    # accuracy gate: the GPU's interleaved forward output on the same rows
+    g = y_gpu.view(re.shape[0], n)[rows].cpu().numpy().astype(np.complex128)
+    ref = yr + 1j * yim
+    out["gpu_max_rel_l2_on_sample"] = float((np.linalg.norm(g - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
+    return out
+
+
+if __name__ == "__main__":
+    sys.exit(main())

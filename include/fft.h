@@ -118,10 +118,11 @@ fft_status fft_plan_destroy(fft_plan p);
 
 /* Ragged plan: `count` transforms of sizes sizes[0..count) (each a power of
  * two in [1, 2^24]) packed back to back, transform i starting at element
- * sum_{j<i} sizes[j].  Executed as ONE persistent kernel launch (a work queue
- * of fixed-size tiles, large sizes split into dependent passes) captured in a
- * HIP graph together with the queue reset.  `sizes` is a host array, read
- * during the call only. */
+ * sum_{j<i} sizes[j].  Executed as ONE HIP graph launch: persistent
+ * work-queue kernels over fixed-size tiles (whole small transforms, or one
+ * pass of a large one), one launch per pass level so that pass p - 1 of a
+ * large transform finishes before pass p starts, plus the queue reset.
+ * `sizes` is a host array, read during the call only. */
 fft_status fft_plan_create_ragged(fft_plan *out, const int64_t *sizes,
                                   int64_t count, fft_layout layout,
                                   fft_direction dir);

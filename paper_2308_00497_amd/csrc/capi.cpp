@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -47,7 +48,8 @@ hipError_t dev_malloc(void** p, size_t bytes) {
 }
 
 struct PassStep {
-    const fftk::PassKernel* k;
+    const fftk::PassKernel* k;      // forward
+    const fftk::PassKernel* k_inv;  // inverse (re/im swapped at the ends)
     int log2ns;
     int hbits;
     size_t tw32_off;  // engine table (float2 entries)
@@ -72,7 +74,9 @@ struct fft_plan_s {
     fft_layout layout = FFT_LAYOUT_INTERLEAVED;
     fft_direction dir = FFT_FORWARD;
     Decomp dec;
-    const fftk::SingleKernel* single = nullptr;
+    int cus = 256;                                   // compute units of the device
+    const fftk::SingleKernel* single = nullptr;      // forward kernel
+    const fftk::SingleKernel* single_inv = nullptr;  // inverse kernel
     std::vector<PassStep> steps;
     float2* tw32 = nullptr;
     size_t tw32_n = 0;
@@ -109,6 +113,7 @@ fft_status resolve(fft_plan p, const Decomp& dec) {
     const bool split = p->layout == FFT_LAYOUT_SPLIT;
     p->dec = dec;
     p->single = nullptr;
+    p->single_inv = nullptr;
     p->steps.clear();
     p->tw32_n = 0;
     p->tw64_n = 0;
@@ -117,8 +122,9 @@ fft_status resolve(fft_plan p, const Decomp& dec) {
         case Decomp::COPY:
             break;
         case Decomp::SINGLE:
-            p->single = fftk::find_single(p->log2n, dec.log2e, dec.wgt, split);
-            if (!p->single) return FFT_ERR_NOT_SUPPORTED;
+            p->single = fftk::single_kernel_for(p->log2n, dec, split, false);
+            p->single_inv = fftk::single_kernel_for(p->log2n, dec, split, true);
+            if (!p->single || !p->single_inv) return FFT_ERR_NOT_SUPPORTED;
             p->tw32_n = p->single->eng.tw_size;
             break;
         case Decomp::MULTI: {
@@ -127,8 +133,9 @@ fft_status resolve(fft_plan p, const Decomp& dec) {
             for (size_t i = 0; i < P; ++i) {
                 PassStep st{};
                 const bool first = i == 0, last = i == P - 1;
-                st.k = fftk::find_pass(dec.log2l[i], dec.log2c[i], first, first && split, last && split);
-                if (!st.k) return FFT_ERR_NOT_SUPPORTED;
+                st.k = fftk::pass_kernel_for(dec.log2l[i], dec.log2c[i], i, P, split, false);
+                st.k_inv = fftk::pass_kernel_for(dec.log2l[i], dec.log2c[i], i, P, split, true);
+                if (!st.k || !st.k_inv) return FFT_ERR_NOT_SUPPORTED;
                 st.log2ns = log2ns;
                 st.tw32_off = p->tw32_n;
                 p->tw32_n += (st.k->eng.tw_size + 1) & ~size_t(1);  // keep 16-byte alignment
@@ -242,17 +249,21 @@ fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, v
     if (st != FFT_OK) return st;
     DeviceGuard guard(p->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // forward kernels everywhere; the inverse conjugates on the way in and out
+    // forward kernels everywhere; the inverse swaps re and im on the way in and
+    // out: split arrays by exchanging the pointers, interleaved data in-kernel
     const bool inverse = (p->dir == FFT_INVERSE) != adjoint;
-    const uint32_t mask = inverse ? 0x80000000u : 0u;
     const bool split = p->layout == FFT_LAYOUT_SPLIT;
     const float* fa = static_cast<const float*>(ia);
     const float* fb = static_cast<const float*>(ib);
     float* ga = static_cast<float*>(oa);
     float* gb = static_cast<float*>(ob);
+    if (inverse && split) {
+        std::swap(fa, fb);
+        std::swap(ga, gb);
+    }
     hipError_t e = hipSuccess;
 
-    if (p->ragged) return fftk::ragged_execute(p->ragged, fa, fb, ga, gb, mask, s, &g_detail);
+    if (p->ragged) return fftk::ragged_execute(p->ragged, fa, fb, ga, gb, inverse && !split, s, &g_detail);
 
     switch (p->dec.kind) {
         case Decomp::COPY: {
@@ -263,10 +274,12 @@ fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, v
             if (e != hipSuccess) return fail_hip(e, "copy");
             return FFT_OK;
         }
-        case Decomp::SINGLE:
-            e = p->single->fn(fa, fb, ga, gb, p->tw32, p->batch, mask, mask, s);
+        case Decomp::SINGLE: {
+            const fftk::SingleKernel* k = inverse ? p->single_inv : p->single;
+            e = k->fn(fa, fb, ga, gb, p->tw32, p->batch, p->dec.gmul * p->cus, s);
             if (e != hipSuccess) return fail_hip(e, "single-pass launch");
             return FFT_OK;
+        }
         case Decomp::MULTI: {
             if (!p->ws()) {
                 g_detail = "no workspace";
@@ -292,9 +305,9 @@ fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, v
                 } else {
                     da = stp.dst == 1 ? wsa : wsb;
                 }
-                e = stp.k->fn(sa, sb, da, db, p->tw32 + stp.tw32_off, p->tw64 ? p->tw64 + stp.ta_off : nullptr,
-                              p->tw64 ? p->tw64 + stp.tb_off : nullptr, p->log2n, stp.log2ns, stp.hbits, p->batch,
-                              i == 0 ? mask : 0u, i == P - 1 ? mask : 0u, s);
+                const fftk::PassKernel* k = inverse ? stp.k_inv : stp.k;
+                e = k->fn(sa, sb, da, db, p->tw32 + stp.tw32_off, p->tw64 ? p->tw64 + stp.ta_off : nullptr,
+                          p->tw64 ? p->tw64 + stp.tb_off : nullptr, p->log2n, stp.log2ns, stp.hbits, p->batch, s);
                 if (e != hipSuccess) return fail_hip(e, "pass launch");
             }
             (void)split;
@@ -389,6 +402,7 @@ static fft_status create_impl(fft_plan* out, int64_t n, int64_t batch, fft_layou
     p->elements = n * batch;
     p->flops = nominal_flops(n) * double(batch);
     hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device);
     if (e != hipSuccess) {
         delete p;
         return fail_hip(e, "hipGetDevice");
@@ -588,6 +602,7 @@ fft_status plan_time_decomposition(fft_plan p, const Decomp& d, void* in, void* 
     // build a throw-away plan with the candidate decomposition and time it
     fft_plan_s tmp;
     tmp.device = p->device;
+    tmp.cus = p->cus;
     tmp.n = p->n;
     tmp.batch = p->batch;
     tmp.log2n = p->log2n;

@@ -13,9 +13,11 @@
 // and Ns grows by R per stage.  After the last stage y is in natural order.
 //
 // All kernels compute the forward transform.  The inverse uses
-// IDFT(x) = conj(DFT(conj(x))): the conjugations are sign flips applied on
-// load and store, exact in floating point, so one set of forward twiddle
-// tables serves both directions.
+// IDFT(x) = S DFT(S x), where S swaps the real and imaginary parts
+// (S z = i conj(z), so S DFT(S x) = i conj(DFT(i conj(x))) = IDFT(x)): for
+// split arrays the caller's real and imaginary pointers trade places, for
+// interleaved data the two halves of each loaded pair do.  No arithmetic is
+// added and one set of forward twiddle tables serves both directions.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,10 +36,6 @@ __device__ __forceinline__ float2 c_mul(float2 a, float2 w) {
 }
 // a * (-i)
 __device__ __forceinline__ float2 c_mul_mi(float2 a) { return make_float2(a.y, -a.x); }
-// flip the sign of the imaginary part when mask = 0x80000000 (conjugation)
-__device__ __forceinline__ float2 c_conj_mask(float2 a, uint32_t mask) {
-    return make_float2(a.x, __uint_as_float(__float_as_uint(a.y) ^ mask));
-}
 
 // exp(-2 pi i m / 16) for the register DFT_16 and DFT_8, correctly rounded
 // float literals of cos(pi/8), sin(pi/8) and sqrt(2)/2.
@@ -186,6 +184,74 @@ __device__ __forceinline__ void stage_sync() {
 }
 
 // ---------------------------------------------------------------------------
+// Twiddle sources for the stages of an engine.  Stage S multiplies input r of
+// butterfly j (j = t + b*T, k = j mod Ns) by w_(Ns*R)^(r*k), read from the
+// stage table at twOff(S) + k*R + r.
+//   TwMem  reads the table (L1/L2 resident) at every use.
+//   TwReg  loads each thread's entries once into registers; persistent
+//          kernels then reuse them for every transform they process, and no
+//          table load competes with the streaming data loads.
+// ---------------------------------------------------------------------------
+template <class SC>
+struct TwMem {
+    const float2* __restrict__ p;
+    __device__ __forceinline__ explicit TwMem(const float2* q) : p(q) {}
+    __device__ __forceinline__ void init(int) {}
+
+    template <int S, int R>
+    __device__ __forceinline__ void apply(float2 (&u)[R], int /*b*/, int j) const {
+        constexpr int LNS = SC::log2NS(S);
+        const int k = j & ((1 << LNS) - 1);
+        const float2* q = p + SC::twOff(S) + k * R;
+        if constexpr (R == 2) {
+            u[1] = c_mul(u[1], q[1]);
+        } else {
+            const float4* q4 = reinterpret_cast<const float4*>(q);
+#pragma unroll
+            for (int h = 0; h < R / 2; ++h) {
+                const float4 w = q4[h];
+                if (h > 0) u[2 * h] = c_mul(u[2 * h], make_float2(w.x, w.y));
+                u[2 * h + 1] = c_mul(u[2 * h + 1], make_float2(w.z, w.w));
+            }
+        }
+    }
+};
+
+template <class SC>
+struct TwReg {
+    static constexpr int E = SC::E;
+    const float2* __restrict__ p;
+    float2 w[SC::NST > 1 ? SC::NST : 1][E];  // w[S][b*R + r]
+    __device__ __forceinline__ explicit TwReg(const float2* q) : p(q) {}
+
+    template <int S>
+    __device__ __forceinline__ void load_stage(int t) {
+        if constexpr (S < SC::NST) {
+            if constexpr (S > 0) {
+                constexpr int R = 1 << SC::log2R(S);
+                constexpr int B = E / R;
+                constexpr int LNS = SC::log2NS(S);
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const int k = (t + b * SC::T) & ((1 << LNS) - 1);
+                    const float2* q = p + SC::twOff(S) + k * R;
+#pragma unroll
+                    for (int r = 1; r < R; ++r) w[S][b * R + r] = q[r];
+                }
+            }
+            load_stage<S + 1>(t);
+        }
+    }
+    __device__ __forceinline__ void init(int t) { load_stage<0>(t); }
+
+    template <int S, int R>
+    __device__ __forceinline__ void apply(float2 (&u)[R], int b, int /*j*/) const {
+#pragma unroll
+        for (int r = 1; r < R; ++r) u[r] = c_mul(u[r], w[S][b * R + r]);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Block engine: G independent L-point sub-FFTs per workgroup, T threads each.
 // Thread -> (g, t) mapping per stage: "g-fast" (g = tid % G) or "t-fast"
 // (t = tid % T).  The first stage uses FIRST_GFAST, the last LAST_GFAST, the
@@ -218,34 +284,18 @@ struct Engine {
     }
 
     // butterflies of stage S on registers; j = t + b*T
-    template <int S>
-    __device__ __forceinline__ static void compute(float2 (&v)[E], int t, const float2* __restrict__ tw) {
+    template <int S, class TW>
+    __device__ __forceinline__ static void compute(float2 (&v)[E], int t, const TW& tw) {
         constexpr int LR = SC::log2R(S);
         constexpr int R = 1 << LR;
         constexpr int B = E / R;
-        constexpr int LNS = SC::log2NS(S);
-        constexpr int NS = 1 << LNS;
+        constexpr int NS = 1 << SC::log2NS(S);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            const int j = t + b * T;
             float2 u[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) u[r] = v[b + r * B];
-            if constexpr (NS > 1) {
-                const int k = j & (NS - 1);
-                const float2* p = tw + SC::twOff(S) + k * R;
-                if constexpr (R == 2) {
-                    u[1] = c_mul(u[1], p[1]);
-                } else {
-                    const float4* p4 = reinterpret_cast<const float4*>(p);
-#pragma unroll
-                    for (int h = 0; h < R / 2; ++h) {
-                        float4 w = p4[h];
-                        if (h > 0) u[2 * h] = c_mul(u[2 * h], make_float2(w.x, w.y));
-                        u[2 * h + 1] = c_mul(u[2 * h + 1], make_float2(w.z, w.w));
-                    }
-                }
-            }
+            if constexpr (NS > 1) tw.template apply<S, R>(u, b, t + b * T);
             Dft<R>::run(u);
 #pragma unroll
             for (int r = 0; r < R; ++r) v[b + r * B] = u[r];
@@ -275,8 +325,8 @@ struct Engine {
         for (int m = 0; m < E; ++m) v[m] = lds[lds_at<GS>(g, t + T * m)];
     }
 
-    template <int S>
-    __device__ __forceinline__ static void stage(float2 (&v)[E], float2* lds, const float2* __restrict__ tw, int tid) {
+    template <int S, class TW>
+    __device__ __forceinline__ static void stage(float2 (&v)[E], float2* lds, const TW& tw, int tid) {
         int g, t;
         map<S>(tid, g, t);
         if constexpr (S > 0) read(v, g, t, lds);
@@ -289,8 +339,12 @@ struct Engine {
         }
     }
 
-    __device__ __forceinline__ static void run(float2 (&v)[E], float2* lds, const float2* __restrict__ tw, int tid) {
+    template <class TW>
+    __device__ __forceinline__ static void run(float2 (&v)[E], float2* lds, const TW& tw, int tid) {
         stage<0>(v, lds, tw, tid);
+    }
+    __device__ __forceinline__ static void run(float2 (&v)[E], float2* lds, const float2* __restrict__ tw, int tid) {
+        stage<0>(v, lds, TwMem<SC>(tw), tid);
     }
 };
 
@@ -319,6 +373,40 @@ __device__ __forceinline__ void gstore(float* a, float* b, int64_t i, float2 v) 
     } else {
         reinterpret_cast<float2*>(a)[i] = v;
     }
+}
+
+// Streaming (nontemporal) variants for data that is read once and written
+// once: the loads and stores carry the streaming cache hint.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+template <bool SPLIT>
+__device__ __forceinline__ float2 gload_nt(const float* a, const float* b, int64_t i) {
+    if constexpr (SPLIT) {
+        return make_float2(__builtin_nontemporal_load(a + i), __builtin_nontemporal_load(b + i));
+    } else {
+        const f32x2_t x = __builtin_nontemporal_load(reinterpret_cast<const f32x2_t*>(a) + i);
+        return make_float2(x.x, x.y);
+    }
+}
+
+template <bool SPLIT>
+__device__ __forceinline__ void gstore_nt(float* a, float* b, int64_t i, float2 v) {
+    if constexpr (SPLIT) {
+        __builtin_nontemporal_store(v.x, a + i);
+        __builtin_nontemporal_store(v.y, b + i);
+    } else {
+        f32x2_t x;
+        x.x = v.x;
+        x.y = v.y;
+        __builtin_nontemporal_store(x, reinterpret_cast<f32x2_t*>(a) + i);
+    }
+}
+
+// real/imaginary swap S of the inverse (free: a register renaming)
+template <bool SWAP>
+__device__ __forceinline__ float2 swap_if(float2 a) {
+    if constexpr (SWAP) return make_float2(a.y, a.x);
+    else return a;
 }
 
 // workgroup index -> tile index such that the workgroups one XCD receives

@@ -1,12 +1,17 @@
 // Instances of the single-pass kernel: every N = 2^1 .. 2^14, both layouts,
-// 8 or 16 elements per thread, 64- or 256-thread workgroups for the sizes
-// where several transforms share a workgroup.
+// both directions, stage twiddles in registers or read from the table, 8 or 16
+// elements per thread, 64- or 256-thread workgroups for the sizes where
+// several transforms share a workgroup.
 #include "kernels.hpp"
 
 namespace fftk {
 
-#define FFT_S(n, e, w)                                                           \
-    single_entry<n, e, w, false>(), single_entry<n, e, w, true>()
+// interleaved forward, interleaved inverse (re/im swapped), split (the inverse
+// swaps the caller's pointers instead)
+#define FFT_S1(n, e, w, r)                                                                   \
+    single_entry<n, e, w, false, false, r>(), single_entry<n, e, w, false, true, r>(),       \
+        single_entry<n, e, w, true, false, r>()
+#define FFT_S(n, e, w) FFT_S1(n, e, w, false), FFT_S1(n, e, w, true)
 
 static const SingleKernel kSingle[] = {
     // N <= 8: one thread per transform (E = N)
@@ -24,10 +29,11 @@ static const SingleKernel kSingle[] = {
     FFT_S(11, 4, 256), FFT_S(11, 3, 256),
     FFT_S(12, 4, 256), FFT_S(12, 3, 256),
     FFT_S(13, 4, 256), FFT_S(13, 3, 256),
-    FFT_S(14, 4, 256),
+    FFT_S1(14, 4, 256, false),
 };
 
 #undef FFT_S
+#undef FFT_S1
 
 const SingleKernel* single_kernels(int* count) {
     *count = static_cast<int>(sizeof(kSingle) / sizeof(kSingle[0]));

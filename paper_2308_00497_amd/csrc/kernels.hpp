@@ -14,6 +14,8 @@
 //  k_gen_*   FP64 twiddle generation on the GPU, rounded once to FP32.
 #pragma once
 
+#include <type_traits>
+
 #include "fft_device.hpp"
 #include "registry.hpp"
 
@@ -44,42 +46,67 @@ struct SingleShape {
     static constexpr bool WAVE = SC::T <= 64;
 };
 
-template <int LOG2N, int LOG2E, int WGT, bool SPLIT>
+// Persistent: each workgroup loops over groups of G transforms
+// (grp = blockIdx.x, blockIdx.x + gridDim.x, ...), so per-thread state such as
+// register-resident twiddles is loaded once per workgroup.  Data is read and
+// written with streaming (nontemporal) accesses.  SWAP exchanges the real and
+// imaginary halves of each interleaved element on load and store (the inverse
+// transform; split arrays get the same effect from swapped pointers).
+template <int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG>
 __global__ void __launch_bounds__((SingleShape<LOG2N, LOG2E, WGT>::THREADS))
-k_single(const float* ia, const float* ib, float* oa, float* ob, const float2* __restrict__ tw,
-         int64_t batch, uint32_t conj_in, uint32_t conj_out) {
+k_single(const float* ia, const float* ib, float* oa, float* ob, const float2* __restrict__ tw, int64_t batch) {
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
     using SC = typename SH::SC;
-    constexpr int E = SC::E, T = SC::T, L = SC::L;
+    constexpr int E = SC::E, T = SC::T, L = SC::L, G = SH::G;
     __shared__ float2 lds[SH::LDS];
 
     const int tid = threadIdx.x;
-    const int t = tid % T, g = tid / T;
-    const int64_t tr = static_cast<int64_t>(blockIdx.x) * SH::G + g;
-    const bool active = tr < batch;
-    const int64_t base = tr * L + t;
+    TwReg<SC> twr(tw);
+    if constexpr (TWREG) twr.init(tid % T);
 
-    float2 v[E];
+    const int64_t groups = (batch + G - 1) / G;
+    for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+        // table reads stay inside the loop unless the registers were asked for:
+        // the empty asm hides the pointer's loop invariance from the compiler
+        const float2* twl = tw;
+        int tidl = tid;
+        if constexpr (!TWREG) {
+            // also recompute thread-derived addresses each iteration instead of
+            // holding them in registers across the loop (register budget of the
+            // 1024-thread shapes)
+            asm volatile("" : "+s"(twl));
+            asm volatile("" : "+v"(tidl));
+        }
+        const int tl = tidl % T, gl = tidl / T;
+        const int64_t tr = grp * G + gl;
+        const bool active = tr < batch;
+        const int64_t base = tr * L + tl;
+        float2 v[E];
+        if (active) {
 #pragma unroll
-    for (int m = 0; m < E; ++m)
-        v[m] = active ? c_conj_mask(gload<SPLIT>(ia, ib, base + T * m), conj_in) : make_float2(0.f, 0.f);
-
-    Engine<SC, SH::G, SH::GS, false, false, SH::WAVE>::run(v, lds, tw, tid);
-
-    if (active) {
+            for (int m = 0; m < E; ++m) v[m] = swap_if<SWAP>(gload_nt<SPLIT>(ia, ib, base + T * m));
+        } else {
 #pragma unroll
-        for (int m = 0; m < E; ++m) gstore<SPLIT>(oa, ob, base + T * m, c_conj_mask(v[m], conj_out));
+            for (int m = 0; m < E; ++m) v[m] = make_float2(0.f, 0.f);
+        }
+        if constexpr (TWREG) Engine<SC, G, SH::GS, false, false, SH::WAVE>::run(v, lds, twr, tidl);
+        else Engine<SC, G, SH::GS, false, false, SH::WAVE>::run(v, lds, TwMem<SC>(twl), tidl);
+        if (active) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) gstore_nt<SPLIT>(oa, ob, base + T * m, swap_if<SWAP>(v[m]));
+        }
     }
 }
 
-template <int LOG2N, int LOG2E, int WGT, bool SPLIT>
+template <int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG>
 hipError_t launch_single(const float* ia, const float* ib, float* oa, float* ob, const float2* tw,
-                         int64_t batch, uint32_t conj_in, uint32_t conj_out, hipStream_t s) {
+                         int64_t batch, int grid, hipStream_t s) {
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
-    const int64_t blocks = (batch + SH::G - 1) / SH::G;
-    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_single<LOG2N, LOG2E, WGT, SPLIT>), dim3(static_cast<unsigned>(blocks)),
-                       dim3(SH::THREADS), 0, s, ia, ib, oa, ob, tw, batch, conj_in, conj_out);
+    const int64_t groups = (batch + SH::G - 1) / SH::G;
+    const int64_t blocks = groups < grid ? groups : grid;
+    if (blocks < 1) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_single<LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG>), dim3(static_cast<unsigned>(blocks)),
+                       dim3(SH::THREADS), 0, s, ia, ib, oa, ob, tw, batch);
     return hipGetLastError();
 }
 
@@ -99,7 +126,7 @@ EngineInfo engine_info() {
     return e;
 }
 
-template <int LOG2N, int LOG2E, int WGT, bool SPLIT>
+template <int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG>
 SingleKernel single_entry() {
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
     SingleKernel k{};
@@ -107,7 +134,9 @@ SingleKernel single_entry() {
     k.log2e = SH::SC::LE;
     k.wgt = WGT;
     k.split = SPLIT;
-    k.fn = &launch_single<LOG2N, LOG2E, WGT, SPLIT>;
+    k.swap = SWAP;
+    k.twreg = TWREG;
+    k.fn = &launch_single<LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG>;
     k.eng = engine_info<typename SH::SC>();
     k.threads = SH::THREADS;
     k.per_wg = SH::G;
@@ -129,25 +158,19 @@ struct PassShape {
     static constexpr int LDS = C * GS;
 };
 
-template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT>
-__global__ void __launch_bounds__((PassShape<LOG2L, LOG2E, LOG2C>::THREADS))
-k_pass(const float* ia, const float* ib, float* oa, float* ob, const float2* __restrict__ tw,
-       const double2* __restrict__ ta, const double2* __restrict__ tb, int log2N, int log2Ns, int hbits,
-       int64_t tiles, uint32_t conj_in, uint32_t conj_out) {
+// One tile of one pass: C consecutive butterfly columns j0 .. j0+C-1 of the
+// transform starting at element tbase.  Shared by the pass kernel and the
+// ragged persistent kernel.  `lds` holds PassShape::LDS float2.
+template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN, bool SWAP_OUT>
+__device__ __forceinline__ void pass_tile(const float* ia, const float* ib, float* oa, float* ob,
+                                          const float2* __restrict__ tw, const double2* __restrict__ ta,
+                                          const double2* __restrict__ tb, int log2N, int log2Ns, int hbits,
+                                          int64_t tbase, int64_t j0, float2* lds, int tid) {
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     using SC = typename SH::SC;
     constexpr int E = SC::E, T = SC::T, C = SH::C;
     static_assert(SC::NST >= 2, "a pass needs at least two stages to change the thread mapping");
-    __shared__ float2 lds[SH::LDS];
-
-    const int tid = threadIdx.x;
-    const int64_t N = int64_t(1) << log2N;
-    const int64_t stride = N >> LOG2L;                   // distance between the L inputs of a column
-    const int log2TilesPerT = log2N - LOG2L - LOG2C;     // tiles per transform (power of two)
-    const int64_t tile = xcd_tile(blockIdx.x, tiles);
-    const int64_t b = tile >> log2TilesPerT;
-    const int64_t j0 = (tile & ((int64_t(1) << log2TilesPerT) - 1)) << LOG2C;
-    const int64_t tbase = b * N;
+    const int64_t stride = int64_t(1) << (log2N - LOG2L);  // distance between the L inputs of a column
     const int64_t NsMask = (int64_t(1) << log2Ns) - 1;
 
     // load: column-fast mapping, C consecutive columns form one contiguous run
@@ -159,7 +182,7 @@ k_pass(const float* ia, const float* ib, float* oa, float* ob, const float2* __r
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int r = tp + T * m;
-            float2 x = c_conj_mask(gload<SPLIT_IN>(ia, ib, tbase + j + r * stride), conj_in);
+            float2 x = swap_if<SWAP_IN>(gload<SPLIT_IN>(ia, ib, tbase + j + r * stride));
             if constexpr (!FIRST) x = c_mul(x, twiddle_2level(ta, tb, static_cast<int64_t>(r) * k, hbits));
             v[m] = x;
         }
@@ -174,7 +197,7 @@ k_pass(const float* ia, const float* ib, float* oa, float* ob, const float2* __r
         const int64_t j = j0 + c;
         const int64_t obase = tbase + (j << LOG2L) + t;
 #pragma unroll
-        for (int m = 0; m < E; ++m) gstore<SPLIT_OUT>(oa, ob, obase + T * m, c_conj_mask(v[m], conj_out));
+        for (int m = 0; m < E; ++m) gstore<SPLIT_OUT>(oa, ob, obase + T * m, swap_if<SWAP_OUT>(v[m]));
     } else {
         const int c = tid & (C - 1), tp = tid >> LOG2C;
         const int64_t j = j0 + c;
@@ -183,25 +206,41 @@ k_pass(const float* ia, const float* ib, float* oa, float* ob, const float2* __r
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int64_t q = tp + T * m;
-            gstore<SPLIT_OUT>(oa, ob, obase + (q << log2Ns), c_conj_mask(v[m], conj_out));
+            gstore<SPLIT_OUT>(oa, ob, obase + (q << log2Ns), swap_if<SWAP_OUT>(v[m]));
         }
     }
 }
 
-template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT>
+template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN, bool SWAP_OUT>
+__global__ void __launch_bounds__((PassShape<LOG2L, LOG2E, LOG2C>::THREADS))
+k_pass(const float* ia, const float* ib, float* oa, float* ob, const float2* __restrict__ tw,
+       const double2* __restrict__ ta, const double2* __restrict__ tb, int log2N, int log2Ns, int hbits,
+       int64_t tiles) {
+    using SH = PassShape<LOG2L, LOG2E, LOG2C>;
+    __shared__ float2 lds[SH::LDS];
+    const int log2TilesPerT = log2N - LOG2L - LOG2C;  // tiles per transform (power of two)
+    const int64_t tile = xcd_tile(blockIdx.x, tiles);
+    const int64_t b = tile >> log2TilesPerT;
+    const int64_t j0 = (tile & ((int64_t(1) << log2TilesPerT) - 1)) << LOG2C;
+    pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>(
+        ia, ib, oa, ob, tw, ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, threadIdx.x);
+}
+
+template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN, bool SWAP_OUT>
 hipError_t launch_pass(const float* ia, const float* ib, float* oa, float* ob, const float2* tw,
                        const double2* ta, const double2* tb, int log2N, int log2Ns, int hbits,
-                       int64_t batch, uint32_t conj_in, uint32_t conj_out, hipStream_t s) {
+                       int64_t batch, hipStream_t s) {
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     const int64_t tiles = (int64_t(1) << (log2N - LOG2L - LOG2C)) * batch;
     if (tiles > 0x7fffffff || log2N < LOG2L + LOG2C) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_pass<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT>),
+    hipLaunchKernelGGL((k_pass<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>),
                        dim3(static_cast<unsigned>(tiles)), dim3(SH::THREADS), 0, s, ia, ib, oa, ob, tw, ta, tb,
-                       log2N, log2Ns, hbits, tiles, conj_in, conj_out);
+                       log2N, log2Ns, hbits, tiles);
     return hipGetLastError();
 }
 
-template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT>
+template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN = false,
+          bool SWAP_OUT = false>
 PassKernel pass_entry() {
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     PassKernel k{};
@@ -211,7 +250,9 @@ PassKernel pass_entry() {
     k.first = FIRST;
     k.split_in = SPLIT_IN;
     k.split_out = SPLIT_OUT;
-    k.fn = &launch_pass<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT>;
+    k.swap_in = SWAP_IN;
+    k.swap_out = SWAP_OUT;
+    k.fn = &launch_pass<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>;
     k.eng = engine_info<typename SH::SC>();
     k.threads = SH::THREADS;
     k.lds_bytes = SH::LDS * sizeof(float2);

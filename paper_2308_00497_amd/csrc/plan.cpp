@@ -27,7 +27,7 @@ std::string Decomp::str() const {
         case COPY:
             return "copy";
         case SINGLE:
-            snprintf(buf, sizeof buf, "single:e%d:w%d", log2e, wgt);
+            snprintf(buf, sizeof buf, "single:e%d:w%d:g%d:r%d", log2e, wgt, gmul, twreg ? 1 : 0);
             return buf;
         case MULTI: {
             std::string s = "multi:";
@@ -48,11 +48,14 @@ bool Decomp::parse(const std::string& s, Decomp* out) {
         *out = d;
         return true;
     }
-    int e = 0, w = 0;
-    if (sscanf(s.c_str(), "single:e%d:w%d", &e, &w) == 2) {
+    int e = 0, w = 0, g = 0, r = 0, used = 0;
+    if (sscanf(s.c_str(), "single:e%d:w%d:g%d:r%d%n", &e, &w, &g, &r, &used) == 4 && used == (int)s.size()) {
+        if (g < 1 || g > 64 || (r != 0 && r != 1)) return false;
         d.kind = SINGLE;
         d.log2e = e;
         d.wgt = w;
+        d.gmul = g;
+        d.twreg = r == 1;
         *out = d;
         return true;
     }
@@ -75,23 +78,36 @@ bool Decomp::parse(const std::string& s, Decomp* out) {
     return false;
 }
 
-const SingleKernel* find_single(int log2n, int log2e, int wgt, bool split) {
+const SingleKernel* find_single(int log2n, int log2e, int wgt, bool split, bool swap, bool twreg) {
     int cnt = 0;
     const SingleKernel* t = single_kernels(&cnt);
     const int le = log2e < log2n ? log2e : log2n;
     for (int i = 0; i < cnt; ++i)
-        if (t[i].log2n == log2n && t[i].log2e == le && t[i].wgt == wgt && t[i].split == split) return &t[i];
+        if (t[i].log2n == log2n && t[i].log2e == le && t[i].wgt == wgt && t[i].split == split && t[i].swap == swap &&
+            t[i].twreg == twreg)
+            return &t[i];
     return nullptr;
 }
 
-const PassKernel* find_pass(int log2l, int log2c, bool first, bool split_in, bool split_out) {
+const PassKernel* find_pass(int log2l, int log2c, bool first, bool split_in, bool split_out, bool swap_in,
+                            bool swap_out) {
     int cnt = 0;
     const PassKernel* t = pass_kernels(&cnt);
     for (int i = 0; i < cnt; ++i)
         if (t[i].log2l == log2l && t[i].log2c == log2c && t[i].first == first && t[i].split_in == split_in &&
-            t[i].split_out == split_out)
+            t[i].split_out == split_out && t[i].swap_in == swap_in && t[i].swap_out == swap_out)
             return &t[i];
     return nullptr;
+}
+
+const PassKernel* pass_kernel_for(int log2l, int log2c, size_t p, size_t P, bool split, bool inverse) {
+    const bool first = p == 0, last = p + 1 == P;
+    return find_pass(log2l, log2c, first, first && split, last && split, first && inverse && !split,
+                     last && inverse && !split);
+}
+
+const SingleKernel* single_kernel_for(int log2n, const Decomp& d, bool split, bool inverse) {
+    return find_single(log2n, d.log2e, d.wgt, split, inverse && !split, d.twreg);
 }
 
 // column tile for a sub-FFT length: the widest compiled one up to 16 columns
@@ -113,12 +129,9 @@ static bool pass_chain_available(const std::vector<int>& ls, const std::vector<i
     const bool split = layout == FFT_LAYOUT_SPLIT;
     const size_t P = ls.size();
     if (P < 2) return false;
-    for (size_t p = 0; p < P; ++p) {
-        const bool first = p == 0;
-        const bool sin = first && split;
-        const bool sout = (p == P - 1) && split;
-        if (!find_pass(ls[p], cs[p], first, sin, sout)) return false;
-    }
+    for (size_t p = 0; p < P; ++p)
+        for (bool inv : {false, true})
+            if (!pass_kernel_for(ls[p], cs[p], p, P, split, inv)) return false;
     return true;
 }
 
@@ -126,8 +139,11 @@ bool decomposition_available(const Decomp& d, int log2n, fft_layout layout) {
     switch (d.kind) {
         case Decomp::COPY:
             return log2n == 0;
-        case Decomp::SINGLE:
-            return log2n >= 1 && find_single(log2n, d.log2e, d.wgt, layout == FFT_LAYOUT_SPLIT) != nullptr;
+        case Decomp::SINGLE: {
+            const bool split = layout == FFT_LAYOUT_SPLIT;
+            return log2n >= 1 && single_kernel_for(log2n, d, split, false) != nullptr &&
+                   single_kernel_for(log2n, d, split, true) != nullptr;
+        }
         case Decomp::MULTI: {
             int sum = 0;
             for (int l : d.log2l) sum += l;
@@ -155,9 +171,18 @@ Decomp default_decomposition(int log2n) {
         return d;
     }
     if (log2n <= 14) {
+        // single-pass shapes measured fastest on MI355X (batches of 2^25
+        // elements, both layouts); the autotuner refines them per device
+        static const struct { int log2e, gmul, twreg; } table[15] = {
+            {4, 1, 1}, {4, 8, 1}, {4, 8, 1}, {4, 8, 1}, {3, 8, 1},  // 2^0 .. 2^4
+            {3, 8, 1}, {3, 8, 1}, {3, 2, 1}, {3, 2, 1}, {3, 2, 1},  // 2^5 .. 2^9
+            {3, 2, 1}, {3, 2, 1}, {4, 2, 1}, {3, 1, 1}, {4, 8, 0},  // 2^10 .. 2^14
+        };
         d.kind = Decomp::SINGLE;
-        d.log2e = 4;
+        d.log2e = table[log2n].log2e;
         d.wgt = 256;
+        d.gmul = table[log2n].gmul;
+        d.twreg = table[log2n].twreg == 1;
         return d;
     }
     // passes of at most 2^9 points keep 16-column tiles (128-byte runs)
@@ -177,20 +202,27 @@ std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout) {
         out.push_back(d);
         return out;
     }
-    // single-pass variants
+    // single-pass variants: kernel shape x grid size x twiddle source
+    std::vector<const SingleKernel*> shapes;
     for (int e : {4, 3})
-        for (int w : {256, 64}) {
-            Decomp d;
-            d.kind = Decomp::SINGLE;
-            d.log2e = e;
-            d.wgt = w;
-            if (decomposition_available(d, log2n, layout)) {
+        for (int w : {256, 64})
+            for (int r : {1, 0}) {
+                const SingleKernel* k = find_single(log2n, e, w, false, false, r == 1);
+                if (!k) continue;
                 bool dup = false;
-                for (auto& o : out) dup |= (find_single(log2n, o.log2e, o.wgt, false) ==
-                                            find_single(log2n, d.log2e, d.wgt, false));
-                if (!dup) out.push_back(d);
+                for (auto* o : shapes) dup |= (o == k);
+                if (dup) continue;
+                shapes.push_back(k);
+                for (int g : {1, 2, 3, 4, 8}) {
+                    Decomp d;
+                    d.kind = Decomp::SINGLE;
+                    d.log2e = e;
+                    d.wgt = w;
+                    d.gmul = g;
+                    d.twreg = r == 1;
+                    if (decomposition_available(d, log2n, layout)) out.push_back(d);
+                }
             }
-        }
     // multi-pass chains with 2 or 3 passes, every sub-length and tile compiled
     int cnt = 0;
     const PassKernel* t = pass_kernels(&cnt);

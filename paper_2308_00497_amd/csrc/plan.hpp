@@ -14,18 +14,21 @@ namespace fftk {
 
 // How one transform size is computed.
 //   copy     N = 1
-//   single   one single-pass kernel (E = 2^log2e elements per thread,
-//            workgroups of at least `wgt` threads)
+//   single   one persistent single-pass kernel (E = 2^log2e elements per
+//            thread, workgroups of at least `wgt` threads, gmul workgroups per
+//            compute unit, stage twiddles in registers when twreg)
 //   multi    P passes of sub-FFT lengths 2^log2l[p] with 2^log2c[p] columns per
 //            workgroup, sum of log2l = log2 N (Stockham radix-L passes)
 struct Decomp {
     enum Kind { COPY = 0, SINGLE = 1, MULTI = 2 } kind = COPY;
     int log2e = 4;
     int wgt = 256;
+    int gmul = 2;
+    bool twreg = true;
     std::vector<int> log2l;
     std::vector<int> log2c;
 
-    std::string str() const;                           // "copy" | "single:e4:w256" | "multi:8c4,8c4,8c4"
+    std::string str() const;  // "copy" | "single:e4:w256:g2:r1" | "multi:8c4,8c4,8c4"
     static bool parse(const std::string& s, Decomp* out);
     bool operator==(const Decomp& o) const { return str() == o.str(); }
 };
@@ -38,8 +41,14 @@ Decomp default_decomposition(int log2n);
 std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout);
 
 // kernel lookup; nullptr when no such instance was compiled
-const SingleKernel* find_single(int log2n, int log2e, int wgt, bool split);
-const PassKernel* find_pass(int log2l, int log2c, bool first, bool split_in, bool split_out);
+const SingleKernel* find_single(int log2n, int log2e, int wgt, bool split, bool swap, bool twreg);
+const PassKernel* find_pass(int log2l, int log2c, bool first, bool split_in, bool split_out, bool swap_in,
+                            bool swap_out);
+
+// kernel of pass p (of P) for a layout and direction: the inverse swaps re/im
+// (interleaved data in the kernel, split data by exchanging the pointers)
+const PassKernel* pass_kernel_for(int log2l, int log2c, size_t p, size_t P, bool split, bool inverse);
+const SingleKernel* single_kernel_for(int log2n, const Decomp& d, bool split, bool inverse);
 
 // true when every kernel the decomposition needs exists for this layout
 bool decomposition_available(const Decomp& d, int log2n, fft_layout layout);

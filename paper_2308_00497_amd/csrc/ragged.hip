@@ -1,11 +1,656 @@
+// Ragged batches: transforms of different power-of-two sizes packed back to
+// back, computed by persistent work-queue kernels captured in ONE HIP graph
+// (one host launch for the whole batch).
+//
+// The work is cut into tiles of (at most) 4096 complex elements, one tile per
+// workgroup visit:
+//   copy tile     up to 256 transforms of size 1
+//   single tile   G = 256/T whole transforms of size N <= 4096 (T = N/16
+//                 threads each), the single-pass Stockham engine
+//   pass tile     C = 4096/L columns of one pass of a transform with N > 4096,
+//                 split into P = ceil(log2 N / 8) passes of L <= 256 points
+//                 (the multi-pass scheme of Eq. 1 with M, K the pass lengths)
+// Tiles are grouped in levels: level 0 holds every first-pass tile and then
+// every single/copy tile (the small tiles even out the end of the level),
+// level p > 0 the p-th pass tiles.  Each level is one launch of the persistent
+// kernel, whose workgroups take tiles from that level's queue with an atomic
+// counter; the kernel boundary between levels orders pass p - 1 before pass p,
+// so no workgroup ever waits for another.  A small kernel at the head of the
+// graph clears the queue counters.
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
 #include "ragged.hpp"
+
 namespace fftk {
-struct RaggedPlan { int dummy; };
-fft_status ragged_create(const int64_t*, int64_t, fft_layout, RaggedPlan** out, std::string* detail) {
-    *out = nullptr; *detail = "ragged plans not built yet"; return FFT_ERR_NOT_SUPPORTED; }
-fft_status ragged_execute(RaggedPlan*, const float*, const float*, float*, float*, uint32_t, hipStream_t, std::string*) { return FFT_ERR_NOT_SUPPORTED; }
-void ragged_destroy(RaggedPlan*) {}
-size_t ragged_workspace_bytes(const RaggedPlan*) { return 0; }
-fft_status ragged_set_workspace(RaggedPlan*, void*, std::string*) { return FFT_ERR_NOT_SUPPORTED; }
-std::string ragged_describe(const RaggedPlan*) { return ""; }
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kTileLog2 = 12;  // 4096 elements per tile
+constexpr int kMinPassLog2 = 5, kMaxPassLog2 = 8;
+
+enum : uint32_t { CODE_COPY = 0, CODE_PASS_FIRST = 16, CODE_PASS_MID = 20, CODE_PASS_LAST = 24 };
+
+struct RaggedTile {
+    uint32_t code;    // CODE_COPY, log2 N (single, 1..12) or CODE_PASS_* + (log2 L - 5)
+    uint32_t first;   // copy/single: index into the item-id list; pass: item index
+    uint32_t count;   // copy/single: transforms in the tile
+    uint32_t col;     // pass: first butterfly column j0
+    int32_t log2n, log2ns, hbits;
+    uint32_t tw_eng;  // float2 offset of the engine stage table
+    uint32_t ta, tb;  // double2 offsets of the pass twiddle tables
+    uint32_t src, dst;  // 0 input, 1 workspace A, 2 workspace B, 3 output
+    uint32_t pad[4];
+};
+
+struct RaggedArgs {
+    const float* ia;
+    const float* ib;
+    float* oa;
+    float* ob;
+    float* wsa;  // interleaved workspaces
+    float* wsb;
+    const RaggedTile* tiles;  // this level's tiles
+    uint32_t ntiles;
+    const uint32_t* ids;
+    const int64_t* offs;
+    const int64_t* wsoff;
+    const float2* tw32;
+    const double2* tw64;
+    uint32_t* head;  // this level's queue counter
+};
+
+template <int LOG2N>
+using RSingle = SingleShape<LOG2N, 4, kThreads>;
+
+template <int LOG2L>
+using RPass = PassShape<LOG2L, 4, kTileLog2 - LOG2L>;
+
+constexpr int lds_max() {
+    int m = 1;
+    m = std::max(m, RSingle<12>::LDS);
+    m = std::max(m, RSingle<11>::LDS);
+    m = std::max(m, RSingle<5>::LDS);
+    m = std::max(m, RPass<5>::LDS);
+    m = std::max(m, RPass<6>::LDS);
+    m = std::max(m, RPass<7>::LDS);
+    m = std::max(m, RPass<8>::LDS);
+    return m;
 }
+constexpr int kLds = lds_max();
+
+template <int LOG2N, bool SPLIT, bool SWAP>
+__device__ __forceinline__ void ragged_single(const RaggedArgs& a, const RaggedTile& d, float2* lds, int tid) {
+    using SH = RSingle<LOG2N>;
+    using SC = typename SH::SC;
+    static_assert(SH::THREADS == kThreads, "single tiles use the whole workgroup");
+    constexpr int E = SC::E, T = SC::T;
+    const int t = tid % T, g = tid / T;
+    const bool active = static_cast<uint32_t>(g) < d.count;
+    const int64_t base = (active ? a.offs[a.ids[d.first + g]] : 0) + t;
+    float2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+        v[m] = active ? swap_if<SWAP>(gload<SPLIT>(a.ia, a.ib, base + T * m)) : make_float2(0.f, 0.f);
+    if constexpr (SC::NST >= 1) Engine<SC, SH::G, SH::GS, false, false, SH::WAVE>::run(v, lds, a.tw32 + d.tw_eng, tid);
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) gstore<SPLIT>(a.oa, a.ob, base + T * m, swap_if<SWAP>(v[m]));
+    }
+}
+
+__device__ __forceinline__ void ragged_copy(const RaggedArgs& a, const RaggedTile& d, bool split, int tid) {
+    // size-1 transforms are the identity in both directions
+    if (static_cast<uint32_t>(tid) >= d.count) return;
+    const int64_t i = a.offs[a.ids[d.first + tid]];
+    if (split) {
+        a.oa[i] = a.ia[i];
+        a.ob[i] = a.ib[i];
+    } else {
+        reinterpret_cast<float2*>(a.oa)[i] = reinterpret_cast<const float2*>(a.ia)[i];
+    }
+}
+
+// pass tile: interleaved workspace between passes, caller layout at the ends
+template <int LOG2L, uint32_t KIND, bool SPLIT, bool SWAP>
+__device__ __forceinline__ void ragged_pass(const RaggedArgs& a, const RaggedTile& d, float2* lds, int tid) {
+    constexpr int LOG2C = kTileLog2 - LOG2L;
+    constexpr bool FIRST = KIND == CODE_PASS_FIRST, LAST = KIND == CODE_PASS_LAST;
+    const int64_t uoff = a.offs[d.first];
+    const int64_t woff = a.wsoff[d.first];
+    // element offsets folded into the base pointers (interleaved: 2 floats each)
+    const int64_t u = SPLIT ? uoff : 2 * uoff;
+    const float* ia = a.ia + u;
+    const float* ib = SPLIT ? a.ib + uoff : nullptr;
+    float* oa = a.oa + u;
+    float* ob = SPLIT ? a.ob + uoff : nullptr;
+    float* wsrc = (d.src == 2 ? a.wsb : a.wsa) + 2 * woff;
+    float* wdst = (d.dst == 2 ? a.wsb : a.wsa) + 2 * woff;
+    const double2* ta = a.tw64 + d.ta;
+    const double2* tb = a.tw64 + d.tb;
+    const float2* tw = a.tw32 + d.tw_eng;
+    if constexpr (FIRST) {
+        pass_tile<LOG2L, 4, LOG2C, true, SPLIT, false, SWAP, false>(ia, ib, wdst, nullptr, tw, ta, tb, d.log2n,
+                                                                     d.log2ns, d.hbits, 0, d.col, lds, tid);
+    } else if constexpr (LAST) {
+        pass_tile<LOG2L, 4, LOG2C, false, false, SPLIT, false, SWAP>(wsrc, nullptr, oa, ob, tw, ta, tb, d.log2n,
+                                                                      d.log2ns, d.hbits, 0, d.col, lds, tid);
+    } else {
+        pass_tile<LOG2L, 4, LOG2C, false, false, false, false, false>(wsrc, nullptr, wdst, nullptr, tw, ta, tb,
+                                                                       d.log2n, d.log2ns, d.hbits, 0, d.col, lds,
+                                                                       tid);
+    }
+}
+
+template <bool SPLIT, bool SWAP>
+__device__ __forceinline__ void dispatch(const RaggedArgs& a, const RaggedTile& d, float2* lds, int tid) {
+    switch (d.code) {
+        case CODE_COPY: ragged_copy(a, d, SPLIT, tid); break;
+        case 1: ragged_single<1, SPLIT, SWAP>(a, d, lds, tid); break;
+        case 2: ragged_single<2, SPLIT, SWAP>(a, d, lds, tid); break;
+        case 3: ragged_single<3, SPLIT, SWAP>(a, d, lds, tid); break;
+        case 4: ragged_single<4, SPLIT, SWAP>(a, d, lds, tid); break;
+        case 5: ragged_single<5, SPLIT, SWAP>(a, d, lds, tid); break;
+        case 6: ragged_single<6, SPLIT, SWAP>(a, d, lds, tid); break;
+        case 7: ragged_single<7, SPLIT, SWAP>(a, d, lds, tid); break;
+        case 8: ragged_single<8, SPLIT, SWAP>(a, d, lds, tid); break;
+        case 9: ragged_single<9, SPLIT, SWAP>(a, d, lds, tid); break;
+        case 10: ragged_single<10, SPLIT, SWAP>(a, d, lds, tid); break;
+        case 11: ragged_single<11, SPLIT, SWAP>(a, d, lds, tid); break;
+        case 12: ragged_single<12, SPLIT, SWAP>(a, d, lds, tid); break;
+#define FFT_RP(kind)                                                              \
+    case kind + 0: ragged_pass<5, kind, SPLIT, SWAP>(a, d, lds, tid); break;      \
+    case kind + 1: ragged_pass<6, kind, SPLIT, SWAP>(a, d, lds, tid); break;      \
+    case kind + 2: ragged_pass<7, kind, SPLIT, SWAP>(a, d, lds, tid); break;      \
+    case kind + 3: ragged_pass<8, kind, SPLIT, SWAP>(a, d, lds, tid); break;
+        FFT_RP(CODE_PASS_FIRST)
+        FFT_RP(CODE_PASS_MID)
+        FFT_RP(CODE_PASS_LAST)
+#undef FFT_RP
+        default: break;
+    }
+}
+
+template <bool SPLIT, bool SWAP>
+__global__ void __launch_bounds__(kThreads, 4) k_ragged(RaggedArgs a) {
+    __shared__ float2 lds[kLds];
+    __shared__ uint32_t s_tile;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_tile = __hip_atomic_fetch_add(a.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t ti = s_tile;
+        __syncthreads();  // s_tile is rewritten only after everyone has read it
+        if (ti >= a.ntiles) break;
+        const RaggedTile d = a.tiles[ti];
+        // thread-derived addresses of every code path are recomputed per tile
+        // rather than hoisted out of the loop (they would all stay live)
+        int tidl = tid;
+        asm volatile("" : "+v"(tidl));
+        dispatch<SPLIT, SWAP>(a, d, lds, tidl);
+    }
+}
+
+// queue counters to zero (a graph node, no memset)
+__global__ void k_ragged_reset(uint32_t* heads, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) heads[i] = 0;
+}
+
+template <class SC>
+int engine_tw_size() {
+    return (SC::TW_SIZE + 1) & ~1;
+}
+
+}  // namespace
+
+struct RaggedPlan {
+    int64_t count = 0, total = 0;
+    fft_layout layout = FFT_LAYOUT_INTERLEAVED;
+    int device = 0;
+    int grid = 0;
+    std::vector<RaggedTile> htiles;
+    RaggedTile* tiles = nullptr;
+    uint32_t* ids = nullptr;
+    int64_t* offs = nullptr;
+    int64_t* wsoff = nullptr;
+    float2* tw32 = nullptr;
+    double2* tw64 = nullptr;
+    uint32_t* heads = nullptr;     // one queue counter per level
+    void* ws_own = nullptr;
+    void* ws_user = nullptr;
+    size_t ws_half = 0;            // bytes of one workspace region
+    int ws_regions = 0;
+    hipStream_t cap = nullptr;     // capture stream
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    static constexpr int kMaxLevels = 3;
+    int nlevels = 0;
+    uint32_t level_begin[kMaxLevels + 1] = {};     // tile index ranges of the levels
+    int level_grid[kMaxLevels] = {};
+    hipGraphNode_t node[2][kMaxLevels] = {};
+    RaggedArgs args[2][kMaxLevels];
+    int nsingle_tiles = 0, npass_tiles = 0, ncopy_tiles = 0, nmulti = 0;
+    std::string classes;
+
+    void* ws() const { return ws_user ? ws_user : ws_own; }
+};
+
+namespace {
+
+fft_status hip_err(hipError_t e, const char* what, std::string* detail) {
+    *detail = std::string(what) + ": " + hipGetErrorString(e);
+    (void)hipGetLastError();
+    return FFT_ERR_HIP;
+}
+
+void free_all(RaggedPlan* r) {
+    for (int i = 0; i < 2; ++i) {
+        if (r->exec[i]) (void)hipGraphExecDestroy(r->exec[i]);
+        if (r->graph[i]) (void)hipGraphDestroy(r->graph[i]);
+    }
+    if (r->cap) (void)hipStreamDestroy(r->cap);
+    void* bufs[] = {r->tiles, r->ids, r->offs, r->wsoff, r->tw32, r->tw64, r->heads, r->ws_own};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+}
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& src) {
+    const size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), bytes);
+    if (e != hipSuccess) return e;
+    if (src.empty()) return hipSuccess;
+    return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+std::vector<int> even_parts(int log2n, int parts) {
+    std::vector<int> v(parts, log2n / parts);
+    for (int i = 0; i < log2n % parts; ++i) v[i] += 1;
+    return v;
+}
+
+void* kernel_for(bool split, bool swap) {
+    if (split) return reinterpret_cast<void*>(&k_ragged<true, false>);
+    return swap ? reinterpret_cast<void*>(&k_ragged<false, true>) : reinterpret_cast<void*>(&k_ragged<false, false>);
+}
+
+// Capture the counter reset and one persistent launch per level into a graph.
+fft_status build_graph(RaggedPlan* r, int variant, std::string* detail) {
+    const bool split = r->layout == FFT_LAYOUT_SPLIT;
+    const bool swap = variant == 1;
+    void* fn = kernel_for(split, swap);
+    hipError_t e = hipStreamBeginCapture(r->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_err(e, "graph capture begin", detail);
+    hipLaunchKernelGGL(k_ragged_reset, dim3(1), dim3(64), 0, r->cap, r->heads, static_cast<uint32_t>(r->nlevels));
+    for (int l = 0; l < r->nlevels && e == hipSuccess; ++l) {
+        RaggedArgs& a = r->args[variant][l];
+        void* kparams[] = {&a};
+        e = hipLaunchKernel(fn, dim3(r->level_grid[l]), dim3(kThreads), kparams, 0, r->cap);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(r->cap, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_err(e, "ragged launch capture", detail);
+    }
+    if (e2 != hipSuccess) return hip_err(e2, "graph capture end", detail);
+    r->graph[variant] = g;
+    size_t nn = 0;
+    e = hipGraphGetNodes(g, nullptr, &nn);
+    std::vector<hipGraphNode_t> nodes(nn);
+    if (e == hipSuccess) e = hipGraphGetNodes(g, nodes.data(), &nn);
+    if (e != hipSuccess) return hip_err(e, "graph nodes", detail);
+    // match each persistent-kernel node to its level by the tile pointer it carries
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType ty;
+        if (hipGraphNodeGetType(nd, &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp;
+        if (hipGraphKernelNodeGetParams(nd, &kp) != hipSuccess || kp.func != fn || !kp.kernelParams) continue;
+        const RaggedArgs* ka = static_cast<const RaggedArgs*>(kp.kernelParams[0]);
+        for (int l = 0; l < r->nlevels; ++l)
+            if (ka->tiles == r->args[variant][l].tiles && ka->head == r->args[variant][l].head) r->node[variant][l] = nd;
+    }
+    for (int l = 0; l < r->nlevels; ++l)
+        if (!r->node[variant][l]) {
+            *detail = "persistent kernel node not found in the captured graph";
+            return FFT_ERR_HIP;
+        }
+    e = hipGraphInstantiate(&r->exec[variant], g, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_err(e, "graph instantiate", detail);
+    return FFT_OK;
+}
+
+}  // namespace
+
+fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout, RaggedPlan** out,
+                         std::string* detail) {
+    *out = nullptr;
+    RaggedPlan* r = new (std::nothrow) RaggedPlan;
+    if (!r) return FFT_ERR_ALLOC;
+    r->count = count;
+    r->layout = layout;
+    hipError_t e = hipGetDevice(&r->device);
+    int cus = 256;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, r->device);
+    if (e != hipSuccess) {
+        delete r;
+        return hip_err(e, "device query", detail);
+    }
+
+    // ---- items and classes ------------------------------------------------
+    std::vector<int> lg(count);
+    std::vector<int64_t> offs(count);
+    int64_t total = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        lg[i] = ilog2_exact(sizes[i]);
+        offs[i] = total;
+        total += sizes[i];
+    }
+    r->total = total;
+
+    // engine tables: single classes 1..12 and pass lengths 5..8
+    EngineInfo eng_single[kTileLog2 + 1] = {};
+    eng_single[1] = engine_info<RSingle<1>::SC>();
+    eng_single[2] = engine_info<RSingle<2>::SC>();
+    eng_single[3] = engine_info<RSingle<3>::SC>();
+    eng_single[4] = engine_info<RSingle<4>::SC>();
+    eng_single[5] = engine_info<RSingle<5>::SC>();
+    eng_single[6] = engine_info<RSingle<6>::SC>();
+    eng_single[7] = engine_info<RSingle<7>::SC>();
+    eng_single[8] = engine_info<RSingle<8>::SC>();
+    eng_single[9] = engine_info<RSingle<9>::SC>();
+    eng_single[10] = engine_info<RSingle<10>::SC>();
+    eng_single[11] = engine_info<RSingle<11>::SC>();
+    eng_single[12] = engine_info<RSingle<12>::SC>();
+    EngineInfo eng_pass[kMaxPassLog2 + 1] = {};
+    eng_pass[5] = engine_info<RPass<5>::SC>();
+    eng_pass[6] = engine_info<RPass<6>::SC>();
+    eng_pass[7] = engine_info<RPass<7>::SC>();
+    eng_pass[8] = engine_info<RPass<8>::SC>();
+    uint32_t off_single[kTileLog2 + 1] = {}, off_pass[kMaxPassLog2 + 1] = {};
+    size_t tw32_n = 0;
+    for (int n = 1; n <= kTileLog2; ++n) {
+        off_single[n] = static_cast<uint32_t>(tw32_n);
+        tw32_n += (eng_single[n].tw_size + 1) & ~1;
+    }
+    for (int l = kMinPassLog2; l <= kMaxPassLog2; ++l) {
+        off_pass[l] = static_cast<uint32_t>(tw32_n);
+        tw32_n += (eng_pass[l].tw_size + 1) & ~1;
+    }
+
+    // multi-pass items: passes, workspace offsets, FP64 pass tables per (size, pass)
+    struct PassTab {
+        int log2m, hbits;
+        uint32_t ta, tb;
+    };
+    std::vector<std::vector<int>> parts(kMaxLog2N + 1);
+    std::vector<std::vector<PassTab>> ptab(kMaxLog2N + 1);
+    size_t tw64_n = 0;
+    std::vector<int64_t> wsoff(count, 0);
+    int64_t ws_elems = 0;
+    int max_passes = 0;
+    std::vector<int64_t> multi;
+    for (int64_t i = 0; i < count; ++i) {
+        if (lg[i] <= kTileLog2) continue;
+        multi.push_back(i);
+        wsoff[i] = ws_elems;
+        ws_elems += sizes[i];
+        const int n = lg[i];
+        if (parts[n].empty()) {
+            parts[n] = even_parts(n, (n + kMaxPassLog2 - 1) / kMaxPassLog2);
+            int log2ns = 0;
+            for (size_t p = 0; p < parts[n].size(); ++p) {
+                PassTab t{};
+                if (p > 0) {
+                    t.log2m = log2ns + parts[n][p];
+                    t.hbits = (t.log2m + 1) / 2;
+                    t.ta = static_cast<uint32_t>(tw64_n);
+                    tw64_n += size_t(1) << (t.log2m - t.hbits);
+                    t.tb = static_cast<uint32_t>(tw64_n);
+                    tw64_n += size_t(1) << t.hbits;
+                }
+                ptab[n].push_back(t);
+                log2ns += parts[n][p];
+            }
+        }
+        max_passes = std::max<int>(max_passes, static_cast<int>(parts[n].size()));
+    }
+    r->nmulti = static_cast<int>(multi.size());
+
+    // ---- tiles in queue order ------------------------------------------------
+    std::vector<RaggedTile>& tiles = r->htiles;
+    std::vector<uint32_t> ids;
+    // largest transforms first within each phase
+    std::stable_sort(multi.begin(), multi.end(), [&](int64_t a, int64_t b) { return lg[a] > lg[b]; });
+    auto pass_tiles = [&](size_t p) {
+        for (int64_t i : multi) {
+            const int n = lg[i];
+            if (p >= parts[n].size()) continue;
+            const int l = parts[n][p];
+            const size_t P = parts[n].size();
+            int log2ns = 0;
+            for (size_t q = 0; q < p; ++q) log2ns += parts[n][q];
+            const uint32_t kind = p == 0 ? CODE_PASS_FIRST : (p + 1 == P ? CODE_PASS_LAST : CODE_PASS_MID);
+            const int64_t ntile = int64_t(1) << (n - kTileLog2);  // columns / C = N / 4096
+            const int log2c = kTileLog2 - l;
+            for (int64_t c = 0; c < ntile; ++c) {
+                RaggedTile t{};
+                t.code = kind + static_cast<uint32_t>(l - kMinPassLog2);
+                t.first = static_cast<uint32_t>(i);
+                t.col = static_cast<uint32_t>(c << log2c);
+                t.log2n = n;
+                t.log2ns = log2ns;
+                t.hbits = ptab[n][p].hbits;
+                t.tw_eng = off_pass[l];
+                t.ta = ptab[n][p].ta;
+                t.tb = ptab[n][p].tb;
+                t.src = p == 0 ? 0u : ((p - 1) % 2 == 0 ? 1u : 2u);
+                t.dst = p + 1 == P ? 3u : (p % 2 == 0 ? 1u : 2u);
+                tiles.push_back(t);
+                ++r->npass_tiles;
+            }
+        }
+    };
+    // level 0: first passes, then the whole small transforms
+    r->level_begin[0] = 0;
+    pass_tiles(0);
+    for (int n = kTileLog2; n >= 0; --n) {
+        std::vector<uint32_t> cls;
+        for (int64_t i = 0; i < count; ++i)
+            if (lg[i] == n) cls.push_back(static_cast<uint32_t>(i));
+        if (cls.empty()) continue;
+        const int T = n <= 4 ? 1 : (1 << (n - 4));
+        const int G = kThreads / T;
+        for (size_t s = 0; s < cls.size(); s += G) {
+            RaggedTile t{};
+            t.code = n == 0 ? CODE_COPY : static_cast<uint32_t>(n);
+            t.first = static_cast<uint32_t>(ids.size() + s);
+            t.count = static_cast<uint32_t>(std::min<size_t>(G, cls.size() - s));
+            t.log2n = n;
+            t.tw_eng = n >= 1 ? off_single[n] : 0;
+            tiles.push_back(t);
+            if (n == 0) ++r->ncopy_tiles;
+            else ++r->nsingle_tiles;
+        }
+        ids.insert(ids.end(), cls.begin(), cls.end());
+        char buf[48];
+        snprintf(buf, sizeof buf, "%s\"2^%d\": %zu", r->classes.empty() ? "" : ", ", n, cls.size());
+        r->classes += buf;
+    }
+    r->nlevels = 1;
+    for (int p = 1; p < max_passes; ++p) {
+        r->level_begin[p] = static_cast<uint32_t>(tiles.size());
+        pass_tiles(p);
+        r->nlevels = p + 1;
+    }
+    r->level_begin[r->nlevels] = static_cast<uint32_t>(tiles.size());
+    for (int n = kTileLog2 + 1; n <= kMaxLog2N; ++n) {
+        int64_t c = 0;
+        for (int64_t i : multi) c += lg[i] == n;
+        if (!c) continue;
+        char buf[48];
+        snprintf(buf, sizeof buf, "%s\"2^%d\": %lld", r->classes.empty() ? "" : ", ", n, (long long)c);
+        r->classes += buf;
+    }
+
+    // ---- device state ---------------------------------------------------------
+    fft_status st = FFT_OK;
+    e = upload(&r->tiles, tiles);
+    if (e == hipSuccess) e = upload(&r->ids, ids);
+    if (e == hipSuccess) e = upload(&r->offs, offs);
+    if (e == hipSuccess) e = upload(&r->wsoff, wsoff);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&r->tw32), std::max<size_t>(2, tw32_n) * sizeof(float2));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&r->tw64), std::max<size_t>(2, tw64_n) * sizeof(double2));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&r->heads), RaggedPlan::kMaxLevels * sizeof(uint32_t));
+    r->ws_half = size_t(ws_elems) * sizeof(float2);
+    r->ws_regions = max_passes >= 3 ? 2 : (max_passes == 2 ? 1 : 0);
+    if (e == hipSuccess && r->ws_half) e = hipMalloc(&r->ws_own, r->ws_half * r->ws_regions);
+    if (e != hipSuccess) {
+        *detail = std::string("ragged plan allocation: ") + hipGetErrorString(e);
+        (void)hipGetLastError();
+        free_all(r);
+        delete r;
+        return FFT_ERR_ALLOC;
+    }
+    for (int n = 1; n <= kTileLog2 && e == hipSuccess; ++n) e = launch_gen_engine_tw(eng_single[n], r->tw32 + off_single[n], nullptr);
+    for (int l = kMinPassLog2; l <= kMaxPassLog2 && e == hipSuccess; ++l)
+        e = launch_gen_engine_tw(eng_pass[l], r->tw32 + off_pass[l], nullptr);
+    for (int n = kTileLog2 + 1; n <= kMaxLog2N && e == hipSuccess; ++n)
+        for (size_t p = 1; p < ptab[n].size() && e == hipSuccess; ++p) {
+            const PassTab& t = ptab[n][p];
+            e = launch_gen_pow64(r->tw64 + t.ta, t.log2m, int64_t(1) << t.hbits, int64_t(1) << (t.log2m - t.hbits),
+                                 nullptr);
+            if (e == hipSuccess) e = launch_gen_pow64(r->tw64 + t.tb, t.log2m, 1, int64_t(1) << t.hbits, nullptr);
+        }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        st = hip_err(e, "ragged twiddle generation", detail);
+        free_all(r);
+        delete r;
+        return st;
+    }
+
+    // persistent grids: as many workgroups as can be resident, at most one per tile
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel_for(layout == FFT_LAYOUT_SPLIT, false)),
+                                                     kThreads, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    const int64_t want = int64_t(per_cu) * cus;
+    for (int l = 0; l < r->nlevels; ++l) {
+        const int64_t nt = int64_t(r->level_begin[l + 1]) - r->level_begin[l];
+        r->level_grid[l] = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, nt)));
+    }
+    r->grid = r->level_grid[0];
+    e = hipStreamCreateWithFlags(&r->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        st = hip_err(e, "capture stream", detail);
+        free_all(r);
+        delete r;
+        return st;
+    }
+    for (int v = 0; v < 2; ++v)
+        for (int l = 0; l < r->nlevels; ++l) {
+            RaggedArgs& a = r->args[v][l];
+            a = RaggedArgs{};
+            a.tiles = r->tiles + r->level_begin[l];
+            a.ntiles = r->level_begin[l + 1] - r->level_begin[l];
+            a.ids = r->ids;
+            a.offs = r->offs;
+            a.wsoff = r->wsoff;
+            a.tw32 = r->tw32;
+            a.tw64 = r->tw64;
+            a.head = r->heads + l;
+        }
+    *out = r;
+    return FFT_OK;
+}
+
+fft_status ragged_execute(RaggedPlan* r, const float* ia, const float* ib, float* oa, float* ob, bool swap,
+                          hipStream_t s, std::string* detail) {
+    const int v = swap ? 1 : 0;
+    if (r->ws_half && !r->ws()) {
+        *detail = "no workspace";
+        return FFT_ERR_INVALID_ARG;
+    }
+    if (!r->exec[v]) {
+        fft_status st = build_graph(r, v, detail);
+        if (st != FFT_OK) return st;
+    }
+    float* wsa = static_cast<float*>(r->ws());
+    float* wsb = r->ws_regions == 2 ? reinterpret_cast<float*>(static_cast<char*>(r->ws()) + r->ws_half) : wsa;
+    for (int l = 0; l < r->nlevels; ++l) {
+        RaggedArgs& a = r->args[v][l];
+        if (a.ia == ia && a.ib == ib && a.oa == oa && a.ob == ob && a.wsa == wsa && a.wsb == wsb) continue;
+        a.ia = ia;
+        a.ib = ib;
+        a.oa = oa;
+        a.ob = ob;
+        a.wsa = wsa;
+        a.wsb = wsb;
+        hipKernelNodeParams kp;
+        hipError_t e = hipGraphKernelNodeGetParams(r->node[v][l], &kp);
+        void* kparams[] = {&a};
+        kp.kernelParams = kparams;
+        kp.extra = nullptr;
+        if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(r->exec[v], r->node[v][l], &kp);
+        if (e != hipSuccess) return hip_err(e, "graph parameter update", detail);
+    }
+    hipError_t e = hipGraphLaunch(r->exec[v], s);
+    if (e != hipSuccess) return hip_err(e, "graph launch", detail);
+    return FFT_OK;
+}
+
+void ragged_destroy(RaggedPlan* r) {
+    if (!r) return;
+    (void)hipDeviceSynchronize();
+    free_all(r);
+    delete r;
+}
+
+size_t ragged_workspace_bytes(const RaggedPlan* r) { return r->ws_half * r->ws_regions; }
+
+fft_status ragged_set_workspace(RaggedPlan* r, void* dev_ptr, std::string* detail) {
+    if (dev_ptr) {
+        if (r->ws_own) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(r->ws_own);
+            r->ws_own = nullptr;
+        }
+        r->ws_user = dev_ptr;
+        return FFT_OK;
+    }
+    r->ws_user = nullptr;
+    if (!r->ws_own && r->ws_half) {
+        hipError_t e = hipMalloc(&r->ws_own, r->ws_half * r->ws_regions);
+        if (e != hipSuccess) {
+            *detail = "workspace allocation failed";
+            (void)hipGetLastError();
+            return FFT_ERR_ALLOC;
+        }
+    }
+    return FFT_OK;
+}
+
+std::string ragged_describe(const RaggedPlan* r) {
+    char buf[512];
+    snprintf(buf, sizeof buf,
+             "\"kernel\": \"ragged persistent\", \"transforms\": %lld, \"elements\": %lld, \"tiles\": %zu, "
+             "\"single_tiles\": %d, \"pass_tiles\": %d, \"copy_tiles\": %d, \"multi_pass_transforms\": %d, "
+             "\"levels\": %d, \"workgroups\": %d, \"threads\": %d, \"lds_bytes\": %zu, \"workspace_bytes\": %zu, "
+             "\"classes\": {",
+             (long long)r->count, (long long)r->total, r->htiles.size(), r->nsingle_tiles, r->npass_tiles,
+             r->ncopy_tiles, r->nmulti, r->nlevels, r->grid, kThreads, size_t(kLds) * sizeof(float2),
+             r->ws_half * r->ws_regions);
+    return std::string(buf) + r->classes + "}";
+}
+
+}  // namespace fftk

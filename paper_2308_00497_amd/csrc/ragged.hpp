@@ -15,7 +15,9 @@ struct RaggedPlan;
 
 fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout, RaggedPlan** out,
                          std::string* detail);
-fft_status ragged_execute(RaggedPlan* r, const float* ia, const float* ib, float* oa, float* ob, uint32_t conj_mask,
+// swap: exchange re/im of interleaved data in the kernel (the inverse); split
+// callers already exchanged their pointers
+fft_status ragged_execute(RaggedPlan* r, const float* ia, const float* ib, float* oa, float* ob, bool swap,
                           hipStream_t s, std::string* detail);
 void ragged_destroy(RaggedPlan* r);
 size_t ragged_workspace_bytes(const RaggedPlan* r);

@@ -23,14 +23,17 @@ struct EngineInfo {
     int tw_off[kMaxStages];
 };
 
+// grid = number of persistent workgroups (clamped to the number of groups)
 using single_fn = hipError_t (*)(const float* ia, const float* ib, float* oa, float* ob, const float2* tw,
-                                 int64_t batch, uint32_t conj_in, uint32_t conj_out, hipStream_t s);
+                                 int64_t batch, int grid, hipStream_t s);
 
 struct SingleKernel {
     int log2n;
     int log2e;
     int wgt;        // target threads per workgroup
     bool split;
+    bool swap;      // swaps re/im of interleaved data on load and store (inverse)
+    bool twreg;     // stage twiddles held in registers
     single_fn fn;
     EngineInfo eng;
     int threads;    // actual threads per workgroup
@@ -40,7 +43,7 @@ struct SingleKernel {
 
 using pass_fn = hipError_t (*)(const float* ia, const float* ib, float* oa, float* ob, const float2* tw,
                                const double2* ta, const double2* tb, int log2N, int log2Ns, int hbits,
-                               int64_t batch, uint32_t conj_in, uint32_t conj_out, hipStream_t s);
+                               int64_t batch, hipStream_t s);
 
 struct PassKernel {
     int log2l;
@@ -49,6 +52,8 @@ struct PassKernel {
     bool first;
     bool split_in;
     bool split_out;
+    bool swap_in;   // swap re/im of the interleaved input (inverse, first pass)
+    bool swap_out;  // swap re/im of the interleaved output (inverse, last pass)
     pass_fn fn;
     EngineInfo eng;
     int threads;

@@ -75,7 +75,10 @@ def test_explicit_decomposition_validation(lib):
     h = ctypes.c_void_p()
     assert lib.fft_plan_create_explicit(ctypes.byref(h), 4096, 1, 0, -1, b"garbage") == 2
     assert lib.fft_plan_create_explicit(ctypes.byref(h), 4096, 1, 0, -1, b"multi:8c4,5c4") == 7
-    assert lib.fft_plan_create_explicit(ctypes.byref(h), 4096, 1, 0, -1, b"single:e5:w256") == 7
+    assert lib.fft_plan_create_explicit(ctypes.byref(h), 4096, 1, 0, -1, b"single:e5:w256:g2:r1") == 7
+    assert lib.fft_plan_create_explicit(ctypes.byref(h), 4096, 1, 0, -1, b"single:e4:w256") == 2
+    assert lib.fft_plan_create_explicit(ctypes.byref(h), 4096, 1, 0, -1, b"single:e4:w256:g0:r1") == 2
+    assert lib.fft_plan_create_explicit(ctypes.byref(h), 4096, 1, 0, -1, b"single:e4:w256:g2:r1x") == 2
     assert lib.fft_plan_create_explicit(ctypes.byref(h), 4096, 1, 0, -1, None) == 3
 
 

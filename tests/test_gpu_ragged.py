@@ -1,0 +1,158 @@
+"""GPU parity of ragged batches: one persistent, graph-replayed launch over
+transforms of mixed power-of-two sizes, against the FP64 oracle and against
+plain per-size launches of the same data."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from fftcheck import SIGN, TOL, from_device, to_device
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fftlib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2308_00497_amd as m
+    return m
+
+
+def ragged_oracle(sizes, offsets, re, im, direction):
+    """Oracle transform of every item, grouped by size into batched calls."""
+    x = re.astype(np.float64) + 1j * im.astype(np.float64)
+    out = np.empty_like(x)
+    for n in np.unique(sizes):
+        idx = np.nonzero(sizes == n)[0]
+        rows = np.stack([x[offsets[i]:offsets[i] + n] for i in idx])
+        y = oracle.fft(rows, SIGN[direction], threads=8)
+        for r, i in enumerate(idx):
+            out[offsets[i]:offsets[i] + n] = y[r]
+    return out
+
+
+def per_item_errors(y, ref, sizes, offsets):
+    errs = np.empty(len(sizes))
+    for i, (n, o) in enumerate(zip(sizes, offsets)):
+        errs[i] = oracle.rel_l2(y[o:o + n], ref[o:o + n])
+    return errs
+
+
+def run_ragged(fftlib, sizes, re, im, layout, direction, out=None):
+    x = to_device(re, im, layout)
+    with fftlib.RaggedPlan(sizes, layout, direction) as plan:
+        y = plan.execute(x, out=out)
+        desc = plan.describe()
+        return from_device(y, layout), desc
+
+
+def make(sizes, seed):
+    sizes = np.asarray(sizes, dtype=np.int64)
+    offsets = np.zeros(len(sizes), dtype=np.int64)
+    offsets[1:] = np.cumsum(sizes)[:-1]
+    re, im = workloads.uniform_complex((int(sizes.sum()),), seed)
+    return sizes, offsets, re, im
+
+
+@pytest.mark.parametrize("layout", ["interleaved", "split"])
+@pytest.mark.parametrize("direction", ["forward", "inverse"])
+def test_c4_against_oracle(fftlib, layout, direction):
+    """4096 transforms, sizes 2^k with k ~ U{6..16} (seed 4), one launch."""
+    sizes, offsets, re, im = workloads.c4()
+    y, desc = run_ragged(fftlib, sizes, re, im, layout, direction)
+    ref = ragged_oracle(sizes, offsets, re, im, direction)
+    errs = per_item_errors(y, ref, sizes, offsets)
+    print(f"[parity] C4 ragged {layout} {direction}: max rel-L2 {errs.max():.3e} "
+          f"({desc['tiles']} tiles, {desc['workgroups']} workgroups)")
+    assert errs.max() <= TOL
+
+
+def test_c4_matches_per_size_launches(fftlib):
+    """The same transforms computed by plain batched plans, one per size, on size-grouped copies."""
+    sizes, offsets, re, im = workloads.c4()
+    y, _ = run_ragged(fftlib, sizes, re, im, "interleaved", "forward")
+    ref = ragged_oracle(sizes, offsets, re, im, "forward")
+    for n in np.unique(sizes):
+        idx = np.nonzero(sizes == n)[0]
+        gr = np.stack([re[offsets[i]:offsets[i] + n] for i in idx])
+        gi = np.stack([im[offsets[i]:offsets[i] + n] for i in idx])
+        with fftlib.Plan(int(n), len(idx), "interleaved", "forward") as p:
+            yp = from_device(p.execute(to_device(gr, gi, "interleaved")), "interleaved").reshape(len(idx), n)
+        for r, i in enumerate(idx):
+            assert oracle.rel_l2(yp[r], ref[offsets[i]:offsets[i] + n]) <= TOL
+            assert oracle.rel_l2(y[offsets[i]:offsets[i] + n], yp[r]) <= 2 * TOL
+
+
+@pytest.mark.parametrize("layout", ["interleaved", "split"])
+def test_every_size_class(fftlib, layout):
+    """Every size from 1 to 2^20 (single-pass classes, two- and three-pass transforms), shuffled."""
+    rng = np.random.default_rng(41)
+    sizes = [1 << k for k in range(0, 21)] + [1 << k for k in rng.integers(0, 14, size=60)]
+    sizes = list(rng.permutation(sizes))
+    sizes, offsets, re, im = make(sizes, 42)
+    for direction in ("forward", "inverse"):
+        y, _ = run_ragged(fftlib, sizes, re, im, layout, direction)
+        ref = ragged_oracle(sizes, offsets, re, im, direction)
+        errs = per_item_errors(y, ref, sizes, offsets)
+        worst = int(np.argmax(errs))
+        assert errs.max() <= TOL, (layout, direction, int(sizes[worst]), errs.max())
+
+
+def test_largest_size(fftlib):
+    """2^24 among small transforms: three passes with two workspaces."""
+    sizes, offsets, re, im = make([64, 1 << 24, 4096, 2], 43)
+    y, desc = run_ragged(fftlib, sizes, re, im, "split", "forward")
+    ref = ragged_oracle(sizes, offsets, re, im, "forward")
+    assert per_item_errors(y, ref, sizes, offsets).max() <= TOL
+    assert desc["multi_pass_transforms"] == 1
+
+
+def test_single_item_and_uniform(fftlib):
+    for sizes in ([4096], [256] * 100, [1] * 7, [1 << 16]):
+        s, o, re, im = make(sizes, 44)
+        y, _ = run_ragged(fftlib, s, re, im, "interleaved", "forward")
+        assert per_item_errors(y, ragged_oracle(s, o, re, im, "forward"), s, o).max() <= TOL
+
+
+def test_graph_replays_and_buffer_changes(fftlib):
+    """Replays of the captured graph with eager work and syncs between them, new
+    buffers between replays, and in place: every result equals the first."""
+    sizes, offsets, re, im = make([1 << k for k in (6, 13, 9, 16, 12, 7, 15)] * 5, 45)
+    ref = ragged_oracle(sizes, offsets, re, im, "forward")
+    with fftlib.RaggedPlan(sizes, "interleaved", "forward") as plan:
+        x = to_device(re, im, "interleaved")
+        first = from_device(plan.execute(x), "interleaved")
+        assert per_item_errors(first, ref, sizes, offsets).max() <= TOL
+        for k in range(4):
+            junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+            torch.cuda.synchronize()
+            x2 = x.clone() if k % 2 else x
+            out = torch.empty_like(x2)
+            y = from_device(plan.execute(x2, out=out), "interleaved")
+            assert np.array_equal(y, first), k
+            del junk
+        xi = x.clone()
+        y = from_device(plan.execute(xi, out=xi), "interleaved")
+        assert np.array_equal(y, first)
+
+
+def test_ragged_backward_is_adjoint(fftlib):
+    sizes, offsets, re, im = make([64, 4096, 1 << 14, 128], 46)
+    x = to_device(re, im, "split")
+    with fftlib.RaggedPlan(sizes, "split", "forward") as plan:
+        y = from_device(plan.backward(x), "split")
+    ref = ragged_oracle(sizes, offsets, re, im, "inverse")
+    assert per_item_errors(y, ref, sizes, offsets).max() <= TOL
+
+
+def test_ragged_workspace_override(fftlib):
+    sizes, offsets, re, im = make([1 << 14, 64, 1 << 18], 47)
+    with fftlib.RaggedPlan(sizes, "interleaved", "forward") as plan:
+        nb = plan.workspace_bytes
+        assert nb >= ((1 << 14) + (1 << 18)) * 8
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        plan.set_workspace(ws)
+        y = from_device(plan.execute(to_device(re, im, "interleaved")), "interleaved")
+    assert per_item_errors(y, ragged_oracle(sizes, offsets, re, im, "forward"), sizes, offsets).max() <= TOL
