@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "GFLOP/s (5N log2 N) and % of peak HBM GB/s, FP32 C2C, rel-L2 ≤1e-5 vs FP64"
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E peak, GB/s
 BYTES_PER_ELEM_PASS = 16       # 8 B read + 8 B written per complex element per HBM pass
-PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "c2_single_n4096_counters.json")
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "c2_single_n4096_counters.txt")
 KERNEL_SOURCES = ["paper_2308_00497_amd/csrc/fft_device.hpp", "paper_2308_00497_amd/csrc/kernels.hpp",
                   "paper_2308_00497_amd/csrc/k_single.hip"]
 
@@ -45,9 +45,10 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic(bytes_alg: float):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+def counter_traffic(variant: str):
+    """HBM bytes per launch of one kernel variant from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known
+    size), if it was taken on the current kernel source; else None."""
     try:
         with open(PROFILE_COUNTERS) as f:
             c = json.load(f)
@@ -55,7 +56,8 @@ def counter_traffic(bytes_alg: float):
         return None
     if c.get("kernel_source_sha") != kernel_source_sha():
         return None
-    return float(c["hbm_bytes_per_launch"])
+    v = c.get("per_variant", {}).get(variant)
+    return None if v is None else float(v["hbm_bytes_per_launch"])
 
 
 def main() -> int:
@@ -64,6 +66,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=250)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip the supplementary workloads")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
 
@@ -136,7 +139,7 @@ def main() -> int:
     dom = max(per_variant, key=lambda k: per_variant[k]["avg_ms"])
     dom_v = per_variant[dom]
     achieved = dom_v["gbs"]
-    traffic = counter_traffic(bytes_per_launch)
+    traffic = counter_traffic(dom)
 
     # practical ceiling: streaming copy of the same bytes (256 MiB read + 256 MiB written)
     nbytes = xi.numel() * xi.element_size()
@@ -180,8 +183,14 @@ def main() -> int:
                          "bytes": 2 * nbytes},
     }
 
+    if not args.no_extras:
+        for v in variants:
+            v["plan"].close()
+        result["extras"] = extras(fftlib, torch, workloads, dev)
+
     if not args.no_cpu:
         # fresh interleaved forward result for the accuracy check on the sample rows
+        variants[0]["plan"] = fftlib.Plan(n, batch, "interleaved", "forward")
         variants[0]["plan"].execute(xi, out=yi)
         torch.cuda.synchronize()
         result["cpu_baseline"] = cpu_baseline(re, im, yi, n, args.cpu_seconds)
@@ -190,6 +199,91 @@ def main() -> int:
     for v in variants:
         v["plan"].close()
     return 0
+
+
+def _time(torch, fn, reps):
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def extras(fftlib, torch, workloads, dev):
+    """Supplementary timings on the other workloads (not the headline value):
+    the single 2^24 transform, the ragged batch against per-size launches, and
+    the autograd forward+backward against the same two kernels called directly."""
+    out = {}
+    # --- single large transform, split, noise + 8 cosines ---------------------
+    n = 1 << 24
+    re, im, _, _, _ = workloads.c3(n)
+    x = (torch.from_numpy(re).to(dev), torch.from_numpy(im).to(dev))
+    y = (torch.empty_like(x[0]), torch.empty_like(x[1]))
+    with fftlib.Plan(n, 1, "split", "forward") as p:
+        d = p.describe()
+        ms = _time(torch, lambda: p.execute(x, out=y), 50)
+        passes = len(d.get("passes", [])) or 1
+        out["n2^24_split_forward"] = {"ms": round(ms, 4), "gflops": round(p.nominal_flops / (ms * 1e-3) / 1e9, 1),
+                                      "decomposition": d["decomposition"], "passes": passes,
+                                      "hbm_gbs_algorithmic": round(n * 16 * passes / (ms * 1e-3) / 1e9, 1)}
+    del x, y
+    # --- ragged batch: one graph launch vs one plain launch per size ---------
+    sizes, offsets, re, im = workloads.c4()
+    z = torch.from_numpy(workloads.interleave(re, im)).to(dev)
+    zo = torch.empty_like(z)
+    with fftlib.RaggedPlan(sizes, "interleaved", "forward") as rp:
+        rd = rp.describe()
+        ms_r = _time(torch, lambda: rp.execute(z, out=zo), 20)
+        flops = rp.nominal_flops
+    groups = []
+    for sz in np.unique(sizes):
+        idx = np.nonzero(sizes == sz)[0]
+        gz = torch.stack([z[int(offsets[i]):int(offsets[i] + sz)] for i in idx]).contiguous()
+        groups.append((fftlib.Plan(int(sz), len(idx), "interleaved", "forward"), gz, torch.empty_like(gz)))
+
+    def per_size():
+        for p, gi, go in groups:
+            p.execute(gi, out=go)
+    ms_p = _time(torch, per_size, 20)
+    for p, _, _ in groups:
+        p.close()
+    out["ragged_4096_sizes_2^6..2^16"] = {
+        "graph_launch_ms": round(ms_r, 4), "per_size_launches_ms": round(ms_p, 4),
+        "speedup_vs_per_size": round(ms_p / ms_r, 3), "gflops_graph": round(flops / (ms_r * 1e-3) / 1e9, 1),
+        "per_size_launch_count": len(groups), "tiles": rd["tiles"], "levels": rd["levels"],
+        "elements": int(sizes.sum())}
+    del z, zo, groups
+    # --- autograd: batch 1024 x 4096 split, loss = sum(w |FFT(x)|^2) ---------
+    re, im, w = workloads.c5()
+    xr = torch.from_numpy(re).to(dev)
+    xi = torch.from_numpy(im).to(dev)
+    wt = torch.from_numpy(w).to(dev)
+
+    def autograd_step():
+        a = xr.detach().requires_grad_(True)
+        b = xi.detach().requires_grad_(True)
+        yr, yi = fftlib.FFTFunction.apply(a, b)
+        (wt * (yr * yr + yi * yi)).sum().backward()
+        return a.grad
+    plan = fftlib.Plan(re.shape[1], re.shape[0], "split", "forward")
+
+    def direct_step():
+        yr, yi = plan.execute((xr, xi))
+        gr, gi = plan.backward((2 * wt * yr, 2 * wt * yi))
+        return gr
+    ms_a = _time(torch, autograd_step, 50)
+    ms_d = _time(torch, direct_step, 50)
+    ms_k = _time(torch, lambda: plan.execute((xr, xi)), 50)
+    plan.close()
+    out["autograd_1024x4096_split"] = {"autograd_fwd_bwd_ms": round(ms_a, 4), "direct_fwd_bwd_ms": round(ms_d, 4),
+                                       "overhead_ms": round(ms_a - ms_d, 4), "single_fft_ms": round(ms_k, 4)}
+    return out
 
 
 def cpu_baseline(re, im, y_gpu, n, seconds):
