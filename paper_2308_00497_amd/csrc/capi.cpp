@@ -57,6 +57,7 @@ struct PassStep {
     size_t tb_off;
     int src;  // 0 = caller input, 1 = workspace A, 2 = workspace B
     int dst;  // 3 = caller output, 1, 2 as above
+    int grid; // persistent workgroups: resident per CU x CUs
 };
 
 bool valid_layout(int l) { return l == FFT_LAYOUT_INTERLEAVED || l == FFT_LAYOUT_SPLIT; }
@@ -136,6 +137,12 @@ fft_status resolve(fft_plan p, const Decomp& dec) {
                 st.k = fftk::pass_kernel_for(dec.log2l[i], dec.log2c[i], i, P, split, false);
                 st.k_inv = fftk::pass_kernel_for(dec.log2l[i], dec.log2c[i], i, P, split, true);
                 if (!st.k || !st.k_inv) return FFT_ERR_NOT_SUPPORTED;
+                int per_cu = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, st.k->kernel, st.k->threads, 0) !=
+                        hipSuccess ||
+                    per_cu < 1)
+                    per_cu = 1;
+                st.grid = per_cu * p->cus;
                 st.log2ns = log2ns;
                 st.tw32_off = p->tw32_n;
                 p->tw32_n += (st.k->eng.tw_size + 1) & ~size_t(1);  // keep 16-byte alignment
@@ -307,7 +314,8 @@ fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, v
                 }
                 const fftk::PassKernel* k = inverse ? stp.k_inv : stp.k;
                 e = k->fn(sa, sb, da, db, p->tw32 + stp.tw32_off, p->tw64 ? p->tw64 + stp.ta_off : nullptr,
-                          p->tw64 ? p->tw64 + stp.tb_off : nullptr, p->log2n, stp.log2ns, stp.hbits, p->batch, s);
+                          p->tw64 ? p->tw64 + stp.tb_off : nullptr, p->log2n, stp.log2ns, stp.hbits, p->batch,
+                          stp.grid, s);
                 if (e != hipSuccess) return fail_hip(e, "pass launch");
             }
             (void)split;

@@ -244,6 +244,31 @@ struct TwReg {
     }
     __device__ __forceinline__ void init(int t) { load_stage<0>(t); }
 
+    // variant for engines whose stages map threads differently: stage S takes
+    // its t from ENG::map<S>(tid)
+    template <class ENG, int S>
+    __device__ __forceinline__ void load_stage_mapped(int tid) {
+        if constexpr (S < SC::NST) {
+            if constexpr (S > 0) {
+                int g, t;
+                ENG::template map<S>(tid, g, t);
+                constexpr int R = 1 << SC::log2R(S);
+                constexpr int B = E / R;
+                constexpr int LNS = SC::log2NS(S);
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const int k = (t + b * SC::T) & ((1 << LNS) - 1);
+                    const float2* q = p + SC::twOff(S) + k * R;
+#pragma unroll
+                    for (int r = 1; r < R; ++r) w[S][b * R + r] = q[r];
+                }
+            }
+            load_stage_mapped<ENG, S + 1>(tid);
+        }
+    }
+    template <class ENG>
+    __device__ __forceinline__ void init_engine(int tid) { load_stage_mapped<ENG, 0>(tid); }
+
     template <int S, int R>
     __device__ __forceinline__ void apply(float2 (&u)[R], int b, int /*j*/) const {
 #pragma unroll
@@ -416,6 +441,16 @@ __device__ __forceinline__ float2 swap_if(float2 a) {
 __device__ __forceinline__ int64_t xcd_tile(int64_t wg, int64_t count) {
     if (count & 7) return wg;
     return (wg & 7) * (count >> 3) + (wg >> 3);
+}
+
+__device__ __forceinline__ double2 z_mul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
+}
+
+// w_M^e in FP64 from the two tables below (not rounded)
+__device__ __forceinline__ double2 twiddle_2level64(const double2* __restrict__ ta, const double2* __restrict__ tb,
+                                                    int64_t e, int hbits) {
+    return z_mul(ta[e >> hbits], tb[e & ((int64_t(1) << hbits) - 1)]);
 }
 
 // w_M^e = exp(-2 pi i e / M) from two FP64 tables, A[i] = w_M^(i << hbits) and

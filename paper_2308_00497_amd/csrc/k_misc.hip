@@ -51,21 +51,35 @@ hipError_t launch_gen_pow64(double2* dst, int log2M, int64_t step, int64_t count
     return hipGetLastError();
 }
 
-// Grid-stride copy of 16-byte vectors.
-__global__ void __launch_bounds__(256) k_copy16(const float4* __restrict__ src, float4* __restrict__ dst,
+// Streaming copy: each thread moves four 16-byte vectors spaced one
+// workgroup-width apart (a 4 KiB block per workgroup) with nontemporal loads
+// and stores - the same access style as the FFT kernels; a grid-stride loop
+// finishes the remainder.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_copy16(const f32x4_t* __restrict__ src, f32x4_t* __restrict__ dst,
                                                 int64_t n16) {
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride)
+    const int64_t full = n16 / 1024;  // complete 4 KiB blocks
+    const int64_t tid = threadIdx.x;
+    for (int64_t blk = blockIdx.x; blk < full; blk += gridDim.x) {
+        const int64_t b = blk * 1024 + tid;
+        f32x4_t a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = __builtin_nontemporal_load(src + b + 256 * i);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) __builtin_nontemporal_store(a[i], dst + b + 256 * i);
+    }
+    for (int64_t i = full * 1024 + int64_t(blockIdx.x) * 256 + tid; i < n16; i += int64_t(gridDim.x) * 256)
         dst[i] = src[i];
 }
 
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
     const int64_t n16 = static_cast<int64_t>(bytes / 16);
     if (n16 == 0) return hipSuccess;
-    int64_t blocks = (n16 + 255) / 256;
-    if (blocks > 256 * 64) blocks = 256 * 64;  // enough resident waves on 256 CUs
+    int64_t blocks = (n16 + 1023) / 1024;
+    if (blocks > 0x7fffffff) blocks = 0x7fffffff;
     hipLaunchKernelGGL(k_copy16, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
-                       static_cast<const float4*>(src), static_cast<float4*>(dst), n16);
+                       static_cast<const f32x4_t*>(src), static_cast<f32x4_t*>(dst), n16);
     return hipGetLastError();
 }
 

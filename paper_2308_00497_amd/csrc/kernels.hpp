@@ -137,6 +137,7 @@ SingleKernel single_entry() {
     k.swap = SWAP;
     k.twreg = TWREG;
     k.fn = &launch_single<LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG>;
+    k.kernel = reinterpret_cast<const void*>(&k_single<LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG>);
     k.eng = engine_info<typename SH::SC>();
     k.threads = SH::THREADS;
     k.per_wg = SH::G;
@@ -160,12 +161,19 @@ struct PassShape {
 
 // One tile of one pass: C consecutive butterfly columns j0 .. j0+C-1 of the
 // transform starting at element tbase.  Shared by the pass kernel and the
-// ragged persistent kernel.  `lds` holds PassShape::LDS float2.
-template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN, bool SWAP_OUT>
-__device__ __forceinline__ void pass_tile(const float* ia, const float* ib, float* oa, float* ob,
-                                          const float2* __restrict__ tw, const double2* __restrict__ ta,
-                                          const double2* __restrict__ tb, int log2N, int log2Ns, int hbits,
-                                          int64_t tbase, int64_t j0, float2* lds, int tid) {
+// ragged persistent kernel.  `lds` holds PassShape::LDS float2; TW supplies the
+// sub-FFT's stage twiddles.  NT selects streaming (nontemporal) data access.
+//
+// The pass twiddle of input r of column j (k = j mod Ns) is w_M^(r k), M = Ns L.
+// A thread holds r = tp + T m (m < E), so w_M^(r k) = w_M^(tp k) (w_M^(T k))^m:
+// two table lookups per thread and an FP64 running product, rounded once per
+// element (the FP64 recurrence error over E <= 16 steps stays near 1e-15,
+// far below the single rounding to FP32).
+template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN, bool SWAP_OUT,
+          bool NT = false, class TW = TwMem<Sched<LOG2L, LOG2E, false>>>
+__device__ __forceinline__ void pass_tile(const float* ia, const float* ib, float* oa, float* ob, const TW& tw,
+                                          const double2* __restrict__ ta, const double2* __restrict__ tb, int log2N,
+                                          int log2Ns, int hbits, int64_t tbase, int64_t j0, float2* lds, int tid) {
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     using SC = typename SH::SC;
     constexpr int E = SC::E, T = SC::T, C = SH::C;
@@ -181,10 +189,17 @@ __device__ __forceinline__ void pass_tile(const float* ia, const float* ib, floa
         const int64_t k = j & NsMask;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
-            const int r = tp + T * m;
-            float2 x = swap_if<SWAP_IN>(gload<SPLIT_IN>(ia, ib, tbase + j + r * stride));
-            if constexpr (!FIRST) x = c_mul(x, twiddle_2level(ta, tb, static_cast<int64_t>(r) * k, hbits));
-            v[m] = x;
+            const int64_t i = tbase + j + (tp + T * m) * stride;
+            v[m] = swap_if<SWAP_IN>(NT ? gload_nt<SPLIT_IN>(ia, ib, i) : gload<SPLIT_IN>(ia, ib, i));
+        }
+        if constexpr (!FIRST) {
+            double2 w = twiddle_2level64(ta, tb, k * tp, hbits);
+            const double2 step = twiddle_2level64(ta, tb, k * T, hbits);
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                if (m > 0) w = z_mul(w, step);
+                v[m] = c_mul(v[m], make_float2(static_cast<float>(w.x), static_cast<float>(w.y)));
+            }
         }
     }
 
@@ -197,7 +212,11 @@ __device__ __forceinline__ void pass_tile(const float* ia, const float* ib, floa
         const int64_t j = j0 + c;
         const int64_t obase = tbase + (j << LOG2L) + t;
 #pragma unroll
-        for (int m = 0; m < E; ++m) gstore<SPLIT_OUT>(oa, ob, obase + T * m, swap_if<SWAP_OUT>(v[m]));
+        for (int m = 0; m < E; ++m) {
+            const float2 o = swap_if<SWAP_OUT>(v[m]);
+            if constexpr (NT) gstore_nt<SPLIT_OUT>(oa, ob, obase + T * m, o);
+            else gstore<SPLIT_OUT>(oa, ob, obase + T * m, o);
+        }
     } else {
         const int c = tid & (C - 1), tp = tid >> LOG2C;
         const int64_t j = j0 + c;
@@ -206,35 +225,60 @@ __device__ __forceinline__ void pass_tile(const float* ia, const float* ib, floa
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int64_t q = tp + T * m;
-            gstore<SPLIT_OUT>(oa, ob, obase + (q << log2Ns), swap_if<SWAP_OUT>(v[m]));
+            const float2 o = swap_if<SWAP_OUT>(v[m]);
+            if constexpr (NT) gstore_nt<SPLIT_OUT>(oa, ob, obase + (q << log2Ns), o);
+            else gstore<SPLIT_OUT>(oa, ob, obase + (q << log2Ns), o);
         }
     }
 }
 
+// Persistent pass kernel: workgroup w takes tiles w, w + grid, ... (mapped
+// so that the tiles one XCD works on are consecutive), with the sub-FFT's stage
+// twiddles held in registers across tiles and streaming data access.
 template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN, bool SWAP_OUT>
 __global__ void __launch_bounds__((PassShape<LOG2L, LOG2E, LOG2C>::THREADS))
 k_pass(const float* ia, const float* ib, float* oa, float* ob, const float2* __restrict__ tw,
        const double2* __restrict__ ta, const double2* __restrict__ tb, int log2N, int log2Ns, int hbits,
        int64_t tiles) {
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
+    using SC = typename SH::SC;
+    using ENG = Engine<SC, SH::C, SH::GS, true, !FIRST, false>;
+    // stage twiddles in registers unless the workgroup is so large (1024
+    // threads: at most 128 registers per lane) that they would spill
+    constexpr bool REGTW = SH::THREADS <= 512;
     __shared__ float2 lds[SH::LDS];
+    const int tid = threadIdx.x;
+    TwReg<SC> twr(tw);
+    if constexpr (REGTW) twr.template init_engine<ENG>(tid);
     const int log2TilesPerT = log2N - LOG2L - LOG2C;  // tiles per transform (power of two)
-    const int64_t tile = xcd_tile(blockIdx.x, tiles);
-    const int64_t b = tile >> log2TilesPerT;
-    const int64_t j0 = (tile & ((int64_t(1) << log2TilesPerT) - 1)) << LOG2C;
-    pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>(
-        ia, ib, oa, ob, tw, ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, threadIdx.x);
+    const int64_t slots = static_cast<int64_t>(gridDim.x);
+    for (int64_t lin = blockIdx.x; lin < tiles; lin += slots) {
+        // consecutive tiles to the workgroups of one XCD (8 XCDs, dealt in turn)
+        const int64_t tile = (slots & 7) ? lin : xcd_tile(lin, tiles);
+        int tidl = tid;
+        asm volatile("" : "+v"(tidl));  // keep per-tile addresses out of the loop-invariant set
+        const int64_t b = tile >> log2TilesPerT;
+        const int64_t j0 = (tile & ((int64_t(1) << log2TilesPerT) - 1)) << LOG2C;
+        if constexpr (REGTW)
+            pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT, true>(
+                ia, ib, oa, ob, twr, ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl);
+        else
+            pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT, true>(
+                ia, ib, oa, ob, TwMem<SC>(tw), ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl);
+    }
 }
 
 template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN, bool SWAP_OUT>
 hipError_t launch_pass(const float* ia, const float* ib, float* oa, float* ob, const float2* tw,
                        const double2* ta, const double2* tb, int log2N, int log2Ns, int hbits,
-                       int64_t batch, hipStream_t s) {
+                       int64_t batch, int grid, hipStream_t s) {
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
+    if (log2N < LOG2L + LOG2C) return hipErrorInvalidConfiguration;
     const int64_t tiles = (int64_t(1) << (log2N - LOG2L - LOG2C)) * batch;
-    if (tiles > 0x7fffffff || log2N < LOG2L + LOG2C) return hipErrorInvalidConfiguration;
+    const int64_t blocks = tiles < grid ? tiles : grid;
+    if (blocks < 1) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((k_pass<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>),
-                       dim3(static_cast<unsigned>(tiles)), dim3(SH::THREADS), 0, s, ia, ib, oa, ob, tw, ta, tb,
+                       dim3(static_cast<unsigned>(blocks)), dim3(SH::THREADS), 0, s, ia, ib, oa, ob, tw, ta, tb,
                        log2N, log2Ns, hbits, tiles);
     return hipGetLastError();
 }
@@ -253,6 +297,7 @@ PassKernel pass_entry() {
     k.swap_in = SWAP_IN;
     k.swap_out = SWAP_OUT;
     k.fn = &launch_pass<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>;
+    k.kernel = reinterpret_cast<const void*>(&k_pass<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>);
     k.eng = engine_info<typename SH::SC>();
     k.threads = SH::THREADS;
     k.lds_bytes = SH::LDS * sizeof(float2);

@@ -99,11 +99,11 @@ __device__ __forceinline__ void ragged_single(const RaggedArgs& a, const RaggedT
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m)
-        v[m] = active ? swap_if<SWAP>(gload<SPLIT>(a.ia, a.ib, base + T * m)) : make_float2(0.f, 0.f);
+        v[m] = active ? swap_if<SWAP>(gload_nt<SPLIT>(a.ia, a.ib, base + T * m)) : make_float2(0.f, 0.f);
     if constexpr (SC::NST >= 1) Engine<SC, SH::G, SH::GS, false, false, SH::WAVE>::run(v, lds, a.tw32 + d.tw_eng, tid);
     if (active) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) gstore<SPLIT>(a.oa, a.ob, base + T * m, swap_if<SWAP>(v[m]));
+        for (int m = 0; m < E; ++m) gstore_nt<SPLIT>(a.oa, a.ob, base + T * m, swap_if<SWAP>(v[m]));
     }
 }
 
@@ -136,17 +136,18 @@ __device__ __forceinline__ void ragged_pass(const RaggedArgs& a, const RaggedTil
     float* wdst = (d.dst == 2 ? a.wsb : a.wsa) + 2 * woff;
     const double2* ta = a.tw64 + d.ta;
     const double2* tb = a.tw64 + d.tb;
-    const float2* tw = a.tw32 + d.tw_eng;
+    const TwMem<typename RPass<LOG2L>::SC> tw(a.tw32 + d.tw_eng);
     if constexpr (FIRST) {
-        pass_tile<LOG2L, 4, LOG2C, true, SPLIT, false, SWAP, false>(ia, ib, wdst, nullptr, tw, ta, tb, d.log2n,
-                                                                     d.log2ns, d.hbits, 0, d.col, lds, tid);
+        pass_tile<LOG2L, 4, LOG2C, true, SPLIT, false, SWAP, false, true>(ia, ib, wdst, nullptr, tw, ta, tb, d.log2n,
+                                                                           d.log2ns, d.hbits, 0, d.col, lds, tid);
     } else if constexpr (LAST) {
-        pass_tile<LOG2L, 4, LOG2C, false, false, SPLIT, false, SWAP>(wsrc, nullptr, oa, ob, tw, ta, tb, d.log2n,
-                                                                      d.log2ns, d.hbits, 0, d.col, lds, tid);
+        pass_tile<LOG2L, 4, LOG2C, false, false, SPLIT, false, SWAP, true>(wsrc, nullptr, oa, ob, tw, ta, tb,
+                                                                            d.log2n, d.log2ns, d.hbits, 0, d.col,
+                                                                            lds, tid);
     } else {
-        pass_tile<LOG2L, 4, LOG2C, false, false, false, false, false>(wsrc, nullptr, wdst, nullptr, tw, ta, tb,
-                                                                       d.log2n, d.log2ns, d.hbits, 0, d.col, lds,
-                                                                       tid);
+        pass_tile<LOG2L, 4, LOG2C, false, false, false, false, false, true>(wsrc, nullptr, wdst, nullptr, tw, ta,
+                                                                             tb, d.log2n, d.log2ns, d.hbits, 0, d.col,
+                                                                             lds, tid);
     }
 }
 

@@ -35,15 +35,17 @@ struct SingleKernel {
     bool swap;      // swaps re/im of interleaved data on load and store (inverse)
     bool twreg;     // stage twiddles held in registers
     single_fn fn;
+    const void* kernel;  // the __global__ function (occupancy queries)
     EngineInfo eng;
     int threads;    // actual threads per workgroup
     int per_wg;     // transforms per workgroup
     size_t lds_bytes;
 };
 
+// grid = number of persistent workgroups (clamped to the number of tiles)
 using pass_fn = hipError_t (*)(const float* ia, const float* ib, float* oa, float* ob, const float2* tw,
                                const double2* ta, const double2* tb, int log2N, int log2Ns, int hbits,
-                               int64_t batch, hipStream_t s);
+                               int64_t batch, int grid, hipStream_t s);
 
 struct PassKernel {
     int log2l;
@@ -55,6 +57,7 @@ struct PassKernel {
     bool swap_in;   // swap re/im of the interleaved input (inverse, first pass)
     bool swap_out;  // swap re/im of the interleaved output (inverse, last pass)
     pass_fn fn;
+    const void* kernel;  // the __global__ function (occupancy queries)
     EngineInfo eng;
     int threads;
     size_t lds_bytes;
