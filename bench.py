@@ -217,8 +217,9 @@ def _time(torch, fn, reps):
 
 def extras(fftlib, torch, workloads, dev):
     """Supplementary timings on the other workloads (not the headline value):
-    the single 2^24 transform, the ragged batch against per-size launches, and
-    the autograd forward+backward against the same two kernels called directly."""
+    the single 2^24 transform, the ragged batch against per-size launches, the
+    autograd forward+backward against the same two kernels called directly, and
+    the FP64 path on the batched shape and on 2^24."""
     out = {}
     # --- single large transform, split, noise + 8 cosines ---------------------
     n = 1 << 24
@@ -283,6 +284,27 @@ def extras(fftlib, torch, workloads, dev):
     plan.close()
     out["autograd_1024x4096_split"] = {"autograd_fwd_bwd_ms": round(ms_a, 4), "direct_fwd_bwd_ms": round(ms_d, 4),
                                        "overhead_ms": round(ms_a - ms_d, 4), "single_fft_ms": round(ms_k, 4)}
+    del xr, xi, wt
+    # --- FP64: the same batched shape and the 2^24 transform in double -------
+    for n, batch in ((4096, 8192), (1 << 24, 1)):
+        re, im = workloads.normal_complex((batch, n), seed=workloads.SEEDS["c2"], dtype=np.float64)
+        for layout in ("interleaved", "split"):
+            if layout == "split":
+                x = (torch.from_numpy(re).to(dev), torch.from_numpy(im).to(dev))
+                y = (torch.empty_like(x[0]), torch.empty_like(x[1]))
+            else:
+                x = torch.from_numpy(workloads.interleave(re, im)).to(dev)
+                y = torch.empty_like(x)
+            with fftlib.Plan(n, batch, layout, "forward", precision="fp64") as p:
+                d = p.describe()
+                ms = _time(torch, lambda: p.execute(x, out=y), 20)
+                passes = len(d.get("passes", [])) or 1
+                gbs = n * batch * 32 * passes / (ms * 1e-3) / 1e9
+                out[f"fp64_n{n}_b{batch}_{layout}_forward"] = {
+                    "ms": round(ms, 4), "gflops": round(p.nominal_flops / (ms * 1e-3) / 1e9, 1),
+                    "decomposition": d["decomposition"], "passes": passes,
+                    "hbm_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 3)}
+            del x, y
     return out
 
 

@@ -16,10 +16,11 @@
  * Conventions for every function below
  *  - All functions return fft_status and never throw or abort.
  *  - Data pointers are DEVICE pointers (hipMalloc'd or torch CUDA tensors on
- *    the current HIP device).  Arrays are float32; a transform occupies N
+ *    the current HIP device).  Arrays hold the plan's real type (float32, or
+ *    float64 for FFT_PRECISION_FP64 plans); a transform occupies N
  *    consecutive elements and transform b starts at element b*N ("[batch][N]").
- *    Interleaved: one array of 2*N*batch floats (re0, im0, re1, im1, ...).
- *    Split: two arrays of N*batch floats each (re, im).
+ *    Interleaved: one array of 2*N*batch reals (re0, im0, re1, im1, ...).
+ *    Split: two arrays of N*batch reals each (re, im).
  *  - Pointers must be 16-byte aligned (FFT_ERR_MISALIGNED otherwise) and
  *    non-null (FFT_ERR_NULL_POINTER); split layout needs both arrays.
  *  - In-place (input pointers equal to output pointers) is allowed; a partial
@@ -52,6 +53,14 @@ typedef enum {
     FFT_LAYOUT_SPLIT = 1
 } fft_layout;
 
+/* Real type of the data.  FP32 is the default everywhere; FP64 is the
+ * precision of the paper's evaluation (section 4).  Twiddles of FP64 plans are
+ * evaluated in FP64 and used unrounded. */
+typedef enum {
+    FFT_PRECISION_FP32 = 0,
+    FFT_PRECISION_FP64 = 1
+} fft_precision;
+
 /* Sign of the exponent. */
 typedef enum {
     FFT_FORWARD = -1,
@@ -83,8 +92,9 @@ fft_status fft_plan_create(fft_plan *out, int64_t n, int64_t batch,
                            fft_layout layout, fft_direction dir);
 
 /* As fft_plan_create, with the decomposition given explicitly instead of
- * chosen: "single:e<log2 E>:w<threads>" (single-pass kernel, 2^E elements per
- * thread, workgroups of at least <threads> threads) or
+ * chosen: "single:e<log2 E>:w<threads>:g<G>:r<0|1>" (persistent single-pass
+ * kernel, 2^E elements per thread, workgroups of at least <threads> threads,
+ * G workgroups per compute unit, stage twiddles in registers if r1) or
  * "multi:<log2 L1>c<log2 C1>,<log2 L2>c<log2 C2>,..." (one pass per sub-FFT
  * length L_p with C_p columns per workgroup; the log2 L_p sum to log2 n), or
  * "copy" for n = 1 - the strings fft_plan_describe and
@@ -93,6 +103,18 @@ fft_status fft_plan_create(fft_plan *out, int64_t n, int64_t batch,
 fft_status fft_plan_create_explicit(fft_plan *out, int64_t n, int64_t batch,
                                     fft_layout layout, fft_direction dir,
                                     const char *decomposition);
+
+/* General form of the two above: `precision` selects float32 or float64
+ * data (and twiddles), `decomposition` is an explicit decomposition string
+ * or NULL to let the library choose (default table, autotune cache, or the
+ * autotuner as for fft_plan_create).  FP64 plans run the same kernels over
+ * double2 elements: single-pass up to n = 2^13 (the LDS holds 2^13 FP64
+ * complex elements per workgroup), multi-pass above.  FFT_ERR_INVALID_ARG for
+ * an unknown precision. */
+fft_status fft_plan_create_ex(fft_plan *out, int64_t n, int64_t batch,
+                              fft_layout layout, fft_direction dir,
+                              fft_precision precision,
+                              const char *decomposition);
 
 /* Apply the plan's transform to `batch` transforms: in -> out.
  * in_re_or_z / out_re_or_z: interleaved array, or the real array (split).
@@ -116,13 +138,13 @@ fft_status fft_execute_backward(fft_plan p, const void *grad_out_re_or_z,
  * still use the plan's memory. */
 fft_status fft_plan_destroy(fft_plan p);
 
-/* Ragged plan: `count` transforms of sizes sizes[0..count) (each a power of
- * two in [1, 2^24]) packed back to back, transform i starting at element
- * sum_{j<i} sizes[j].  Executed as ONE HIP graph launch: persistent
- * work-queue kernels over fixed-size tiles (whole small transforms, or one
- * pass of a large one), one launch per pass level so that pass p - 1 of a
- * large transform finishes before pass p starts, plus the queue reset.
- * `sizes` is a host array, read during the call only. */
+/* Ragged plan (FP32): `count` transforms of sizes sizes[0..count) (each a
+ * power of two in [1, 2^24]) packed back to back, transform i starting at
+ * element sum_{j<i} sizes[j].  Executed as ONE HIP graph launch: persistent
+ * kernels over fixed-size tiles (whole small transforms, or one pass of a
+ * large one), one launch per pass level so that pass p - 1 of a large
+ * transform finishes before pass p starts.  `sizes` is a host array, read
+ * during the call only. */
 fft_status fft_plan_create_ragged(fft_plan *out, const int64_t *sizes,
                                   int64_t count, fft_layout layout,
                                   fft_direction dir);
@@ -145,9 +167,12 @@ fft_status fft_plan_sizes(fft_plan p, int64_t *transforms, int64_t *elements,
  * radices, passes, tiles) into buf (NUL-terminated, truncated to len). */
 fft_status fft_plan_describe(fft_plan p, char *buf, size_t len);
 
-/* Decomposition that fft_plan_create would choose for (n, layout), computed
- * on the host only (no GPU needed), as JSON into buf. */
-fft_status fft_query_decomposition(int64_t n, fft_layout layout, char *buf, size_t len);
+/* Decomposition that fft_plan_create_ex would choose by default for
+ * (n, layout, precision), and the autotuner's candidates, computed on the
+ * host only (no GPU needed), as JSON into buf. */
+fft_status fft_query_decomposition(int64_t n, fft_layout layout,
+                                   fft_precision precision, char *buf,
+                                   size_t len);
 
 /* Plain streaming copy of `bytes` bytes (multiple of 16, 16-byte aligned
  * pointers) with the same access width as the FFT kernels: the practical HBM

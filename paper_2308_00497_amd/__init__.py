@@ -1,4 +1,4 @@
-"""Batched 1D complex-to-complex FP32 FFT for the AMD MI355X (gfx950).
+"""Batched 1D complex-to-complex FFT (FP32 and FP64) for the AMD MI355X (gfx950).
 
 Python binding over the C ABI of ``include/fft.h`` (the HIP library in
 ``lib/libfft_mi355x.so``).  Torch tensors supply device memory and the HIP
@@ -7,11 +7,12 @@ the library's kernels.  Conventions follow the paper's DFT (section 3, Eq. 1;
 signs as the FFTW comparison of section 4): forward exp(-2 pi i k n / N),
 inverse exp(+2 pi i k n / N), neither scaled.
 
-    Plan(n, batch, layout="interleaved" | "split", direction="forward" | "inverse")
-    RaggedPlan(sizes, layout, direction)
-    fft(x), ifft(x)                 complex64 tensors or (re, im) float32 tuples
+    Plan(n, batch, layout="interleaved" | "split", direction="forward" | "inverse",
+         precision="fp32" | "fp64")
+    RaggedPlan(sizes, layout, direction)          (FP32)
+    fft(x), ifft(x)                 complex64/complex128 tensors or (re, im) float32/float64 tuples
     FFTFunction.apply(re, im)       differentiable split-layout forward FFT
-    fft_autograd(z)                 differentiable complex64 forward FFT
+    fft_autograd(z)                 differentiable complex forward FFT
 """
 from __future__ import annotations
 
@@ -20,14 +21,25 @@ import json
 
 import torch
 
-from ._lib import (FFT_FORWARD, FFT_INVERSE, FFT_LAYOUT_INTERLEAVED, FFT_LAYOUT_SPLIT, FFTError, check,
-                   lib)
+from ._lib import (FFT_FORWARD, FFT_INVERSE, FFT_LAYOUT_INTERLEAVED, FFT_LAYOUT_SPLIT, FFT_PRECISION_FP32,
+                   FFT_PRECISION_FP64, FFTError, check, lib)
 
 __all__ = ["Plan", "RaggedPlan", "fft", "ifft", "FFTFunction", "fft_autograd", "copy_device",
            "query_decomposition", "FFTError"]
 
 _LAYOUTS = {"interleaved": FFT_LAYOUT_INTERLEAVED, "split": FFT_LAYOUT_SPLIT}
 _DIRS = {"forward": FFT_FORWARD, "inverse": FFT_INVERSE}
+_PRECISIONS = {"fp32": FFT_PRECISION_FP32, "fp64": FFT_PRECISION_FP64}
+# precision -> (real dtype, complex dtype)
+_DTYPES = {"fp32": (torch.float32, torch.complex64), "fp64": (torch.float64, torch.complex128)}
+
+
+def _precision_of(dtype: torch.dtype) -> str:
+    if dtype in (torch.float32, torch.complex64):
+        return "fp32"
+    if dtype in (torch.float64, torch.complex128):
+        return "fp64"
+    raise TypeError(f"unsupported dtype {dtype}: float32/complex64 or float64/complex128")
 
 
 def _stream_handle(stream=None) -> int:
@@ -42,13 +54,16 @@ def _ptr(t: torch.Tensor | None) -> int | None:
 class _PlanBase:
     _handle: ctypes.c_void_p | None = None
 
-    def __init__(self, layout: str, direction: str):
+    def __init__(self, layout: str, direction: str, precision: str = "fp32"):
         if layout not in _LAYOUTS:
             raise ValueError(f"layout must be one of {sorted(_LAYOUTS)}")
         if direction not in _DIRS:
             raise ValueError(f"direction must be one of {sorted(_DIRS)}")
+        if precision not in _PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(_PRECISIONS)}")
         self.layout = layout
         self.direction = direction
+        self.precision = precision
         self.split = layout == "split"
 
     # --- introspection -------------------------------------------------
@@ -87,21 +102,22 @@ class _PlanBase:
 
     # --- execution -------------------------------------------------------
     def _io(self, x, out):
+        rdt, cdt = _DTYPES[self.precision]
         if self.split:
             if not (isinstance(x, (tuple, list)) and len(x) == 2):
-                raise TypeError("split layout takes (re, im) float32 tensors")
+                raise TypeError(f"split layout takes (re, im) {rdt} tensors")
             re, im = x
             for t in (re, im):
-                if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
-                    raise TypeError("split inputs must be contiguous float32 CUDA tensors")
+                if t.dtype != rdt or not t.is_cuda or not t.is_contiguous():
+                    raise TypeError(f"split inputs must be contiguous {rdt} CUDA tensors")
                 if t.numel() != self.elements:
                     raise ValueError(f"expected {self.elements} elements, got {t.numel()}")
             if out is None:
                 out = (torch.empty_like(re), torch.empty_like(im))
             ore, oim = out
             return _ptr(re), _ptr(im), _ptr(ore), _ptr(oim), out
-        if x.dtype != torch.complex64 or not x.is_cuda or not x.is_contiguous():
-            raise TypeError("interleaved input must be a contiguous complex64 CUDA tensor")
+        if x.dtype != cdt or not x.is_cuda or not x.is_contiguous():
+            raise TypeError(f"interleaved input must be a contiguous {cdt} CUDA tensor")
         if x.numel() != self.elements:
             raise ValueError(f"expected {self.elements} elements, got {x.numel()}")
         if out is None:
@@ -142,19 +158,17 @@ class _PlanBase:
 
 
 class Plan(_PlanBase):
-    """`batch` contiguous transforms of size n (a power of two up to 2^24)."""
+    """`batch` contiguous transforms of size n (a power of two up to 2^24), in
+    FP32 (float32 / complex64 data) or FP64 (float64 / complex128 data)."""
 
     def __init__(self, n: int, batch: int = 1, layout: str = "interleaved", direction: str = "forward",
-                 decomposition: str | None = None):
-        super().__init__(layout, direction)
+                 decomposition: str | None = None, precision: str = "fp32"):
+        super().__init__(layout, direction, precision)
         h = ctypes.c_void_p()
-        if decomposition is None:
-            check(lib.fft_plan_create(ctypes.byref(h), int(n), int(batch), _LAYOUTS[layout], _DIRS[direction]),
-                  "fft_plan_create")
-        else:
-            check(lib.fft_plan_create_explicit(ctypes.byref(h), int(n), int(batch), _LAYOUTS[layout],
-                                               _DIRS[direction], decomposition.encode()),
-                  "fft_plan_create_explicit")
+        check(lib.fft_plan_create_ex(ctypes.byref(h), int(n), int(batch), _LAYOUTS[layout], _DIRS[direction],
+                                     _PRECISIONS[precision],
+                                     None if decomposition is None else decomposition.encode()),
+              "fft_plan_create_ex")
         self._handle = h
         self.n = int(n)
         self.batch = int(batch)
@@ -177,11 +191,11 @@ class RaggedPlan(_PlanBase):
 _plan_cache: dict = {}
 
 
-def _cached_plan(n: int, batch: int, layout: str, direction: str) -> Plan:
-    key = (n, batch, layout, direction, torch.cuda.current_device())
+def _cached_plan(n: int, batch: int, layout: str, direction: str, precision: str = "fp32") -> Plan:
+    key = (n, batch, layout, direction, precision, torch.cuda.current_device())
     p = _plan_cache.get(key)
     if p is None:
-        p = Plan(n, batch, layout, direction)
+        p = Plan(n, batch, layout, direction, precision=precision)
         _plan_cache[key] = p
     return p
 
@@ -190,9 +204,10 @@ def _transform(x, direction: str):
     if isinstance(x, (tuple, list)):
         re, im = x
         n = re.shape[-1]
-        return _cached_plan(n, re.numel() // n, "split", direction).execute((re.contiguous(), im.contiguous()))
+        plan = _cached_plan(n, re.numel() // n, "split", direction, _precision_of(re.dtype))
+        return plan.execute((re.contiguous(), im.contiguous()))
     n = x.shape[-1]
-    return _cached_plan(n, x.numel() // n, "interleaved", direction).execute(x.contiguous())
+    return _cached_plan(n, x.numel() // n, "interleaved", direction, _precision_of(x.dtype)).execute(x.contiguous())
 
 
 def fft(x):
@@ -216,7 +231,7 @@ class FFTFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, re: torch.Tensor, im: torch.Tensor):
         n = re.shape[-1]
-        plan = _cached_plan(n, re.numel() // n, "split", "forward")
+        plan = _cached_plan(n, re.numel() // n, "split", "forward", _precision_of(re.dtype))
         ctx.plan = plan
         yre, yim = plan.execute((re.contiguous(), im.contiguous()))
         return yre, yim
@@ -235,7 +250,7 @@ class _ComplexFFTFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, z: torch.Tensor):
         n = z.shape[-1]
-        plan = _cached_plan(n, z.numel() // n, "interleaved", "forward")
+        plan = _cached_plan(n, z.numel() // n, "interleaved", "forward", _precision_of(z.dtype))
         ctx.plan = plan
         return plan.execute(z.contiguous())
 
@@ -245,7 +260,7 @@ class _ComplexFFTFunction(torch.autograd.Function):
 
 
 def fft_autograd(z: torch.Tensor) -> torch.Tensor:
-    """Differentiable forward FFT of a complex64 tensor [..., N]."""
+    """Differentiable forward FFT of a complex64 or complex128 tensor [..., N]."""
     return _ComplexFFTFunction.apply(z)
 
 
@@ -257,8 +272,11 @@ def copy_device(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
     check(lib.fft_copy_device(_ptr(src), _ptr(dst), nbytes, _stream_handle(stream)), "fft_copy_device")
 
 
-def query_decomposition(n: int, layout: str = "interleaved") -> dict:
+def query_decomposition(n: int, layout: str = "interleaved", precision: str = "fp32") -> dict:
     """Decomposition a plan for n would use, and the autotuner's candidates (host only)."""
+    if precision not in _PRECISIONS:
+        raise ValueError(f"precision must be one of {sorted(_PRECISIONS)}")
     buf = ctypes.create_string_buffer(1 << 16)
-    check(lib.fft_query_decomposition(int(n), _LAYOUTS[layout], buf, len(buf)), "fft_query_decomposition")
+    check(lib.fft_query_decomposition(int(n), _LAYOUTS[layout], _PRECISIONS[precision], buf, len(buf)),
+          "fft_query_decomposition")
     return json.loads(buf.value.decode())

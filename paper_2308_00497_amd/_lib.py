@@ -16,6 +16,8 @@ FFT_LAYOUT_INTERLEAVED = 0
 FFT_LAYOUT_SPLIT = 1
 FFT_FORWARD = -1
 FFT_INVERSE = 1
+FFT_PRECISION_FP32 = 0
+FFT_PRECISION_FP64 = 1
 
 STATUS = {
     0: "FFT_OK",
@@ -32,6 +34,7 @@ STATUS = {
 EXPORTS = [
     "fft_plan_create",
     "fft_plan_create_explicit",
+    "fft_plan_create_ex",
     "fft_execute",
     "fft_execute_backward",
     "fft_plan_destroy",
@@ -63,6 +66,7 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     lib.fft_plan_create.argtypes = [ctypes.POINTER(vp), i64, i64, ci, ci]
     lib.fft_plan_create_explicit.argtypes = [ctypes.POINTER(vp), i64, i64, ci, ci, ctypes.c_char_p]
+    lib.fft_plan_create_ex.argtypes = [ctypes.POINTER(vp), i64, i64, ci, ci, ci, ctypes.c_char_p]
     lib.fft_execute.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.fft_execute_backward.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.fft_plan_destroy.argtypes = [vp]
@@ -71,7 +75,7 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.fft_plan_set_workspace.argtypes = [vp, vp]
     lib.fft_plan_sizes.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
     lib.fft_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
-    lib.fft_query_decomposition.argtypes = [i64, ci, ctypes.c_char_p, ctypes.c_size_t]
+    lib.fft_query_decomposition.argtypes = [i64, ci, ci, ctypes.c_char_p, ctypes.c_size_t]
     lib.fft_copy_device.argtypes = [vp, vp, ctypes.c_size_t, vp]
     lib.fft_status_string.argtypes = [ci]
     lib.fft_status_string.restype = ctypes.c_char_p

@@ -27,6 +27,8 @@ ARCH = "gfx950"
 SOURCES = [
     "k_single.hip",
     "k_pass.hip",
+    "k_single64.hip",
+    "k_pass64.hip",
     "k_misc.hip",
     "ragged.hip",
     "plan.cpp",

@@ -120,7 +120,7 @@ std::string format_cache_text(const std::vector<std::pair<std::string, std::stri
     return s;
 }
 
-TuneKey make_key(int device, int log2n, int64_t batch, fft_layout layout) {
+TuneKey make_key(int device, int log2n, int64_t batch, fft_layout layout, int rb) {
     hipDeviceProp_t prop;
     char arch[64] = "unknown";
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
@@ -133,8 +133,8 @@ TuneKey make_key(int device, int log2n, int64_t batch, fft_layout layout) {
     int bclass = 0;
     while ((int64_t(1) << bclass) < batch) ++bclass;
     char buf[160];
-    snprintf(buf, sizeof buf, "%s|hip%d|n%d|b%d|%s", arch, rt, log2n, bclass,
-             layout == FFT_LAYOUT_SPLIT ? "split" : "interleaved");
+    snprintf(buf, sizeof buf, "%s|hip%d|n%d|b%d|%s|%s", arch, rt, log2n, bclass,
+             layout == FFT_LAYOUT_SPLIT ? "split" : "interleaved", rb == 8 ? "fp64" : "fp32");
     return TuneKey{buf};
 }
 
@@ -182,10 +182,10 @@ void autotune_store(const TuneKey& key, const Decomp& d) {
 
 fft_status autotune_run(fft_plan p, const TuneKey& key, Decomp* best, std::string* detail) {
     const int log2n = plan_log2n(p);
-    const auto cands = candidate_decompositions(log2n, plan_layout(p));
+    const auto cands = candidate_decompositions(log2n, plan_layout(p), plan_real_bytes(p));
     *best = plan_decomposition(p);
     if (cands.size() <= 1) return FFT_OK;
-    const size_t bytes = size_t(plan_elements(p)) * 8;
+    const size_t bytes = size_t(plan_elements(p)) * 2 * size_t(plan_real_bytes(p));
     void *in = nullptr, *out = nullptr;
     if (hipMalloc(&in, bytes) != hipSuccess || hipMalloc(&out, bytes) != hipSuccess) {
         if (in) (void)hipFree(in);

@@ -1,6 +1,6 @@
 // Autotuner: times every compiled decomposition of a size on the device and
 // remembers the fastest in a JSON cache keyed by (GPU architecture, HIP
-// runtime version, log2 N, batch class, layout).
+// runtime version, log2 N, batch class, layout, precision).
 #pragma once
 
 #include <string>
@@ -14,7 +14,7 @@ struct TuneKey {
     std::string s;
 };
 
-TuneKey make_key(int device, int log2n, int64_t batch, fft_layout layout);
+TuneKey make_key(int device, int log2n, int64_t batch, fft_layout layout, int rb);
 bool autotune_enabled();                                   // FFT_AUTOTUNE=1
 std::string autotune_cache_path();                         // FFT_AUTOTUNE_CACHE or the default
 bool autotune_lookup(const TuneKey& key, Decomp* out);     // in-memory copy of the cache file
@@ -27,6 +27,7 @@ const Decomp& plan_decomposition(fft_plan p);
 int64_t plan_elements(fft_plan p);
 fft_layout plan_layout(fft_plan p);
 int plan_log2n(fft_plan p);
+int plan_real_bytes(fft_plan p);
 
 // cache text <-> entries (exposed for tests through the C ABI helpers)
 bool parse_cache_text(const std::string& text, std::vector<std::pair<std::string, std::string>>* entries);

@@ -52,7 +52,7 @@ struct PassStep {
     const fftk::PassKernel* k_inv;  // inverse (re/im swapped at the ends)
     int log2ns;
     int hbits;
-    size_t tw32_off;  // engine table (float2 entries)
+    size_t twe_off;   // engine stage table (complex entries of the plan's precision)
     size_t ta_off;    // FP64 tables (double2 entries)
     size_t tb_off;
     int src;  // 0 = caller input, 1 = workspace A, 2 = workspace B
@@ -74,13 +74,14 @@ struct fft_plan_s {
     int log2n = 0;
     fft_layout layout = FFT_LAYOUT_INTERLEAVED;
     fft_direction dir = FFT_FORWARD;
+    int rb = 4;                                      // bytes per real: 4 (FP32) or 8 (FP64)
     Decomp dec;
     int cus = 256;                                   // compute units of the device
     const fftk::SingleKernel* single = nullptr;      // forward kernel
     const fftk::SingleKernel* single_inv = nullptr;  // inverse kernel
     std::vector<PassStep> steps;
-    float2* tw32 = nullptr;
-    size_t tw32_n = 0;
+    void* twe = nullptr;   // engine stage tables (float2 or double2)
+    size_t twe_n = 0;
     double2* tw64 = nullptr;
     size_t tw64_n = 0;
     void* ws_own = nullptr;
@@ -92,6 +93,7 @@ struct fft_plan_s {
     std::string source;  // "default" | "cache" | "autotune"
 
     void* ws() const { return ws_user ? ws_user : ws_own; }
+    size_t cbytes() const { return 2 * size_t(rb); }  // bytes per complex element
 };
 
 namespace {
@@ -99,10 +101,10 @@ namespace {
 bool plan_ok(fft_plan p) { return p && p->magic == kPlanMagic; }
 
 void free_plan_memory(fft_plan p) {
-    if (p->tw32) (void)hipFree(p->tw32);
+    if (p->twe) (void)hipFree(p->twe);
     if (p->tw64) (void)hipFree(p->tw64);
     if (p->ws_own) (void)hipFree(p->ws_own);
-    p->tw32 = nullptr;
+    p->twe = nullptr;
     p->tw64 = nullptr;
     p->ws_own = nullptr;
     if (p->ragged) fftk::ragged_destroy(p->ragged);
@@ -116,17 +118,17 @@ fft_status resolve(fft_plan p, const Decomp& dec) {
     p->single = nullptr;
     p->single_inv = nullptr;
     p->steps.clear();
-    p->tw32_n = 0;
+    p->twe_n = 0;
     p->tw64_n = 0;
     p->ws_bytes = 0;
     switch (dec.kind) {
         case Decomp::COPY:
             break;
         case Decomp::SINGLE:
-            p->single = fftk::single_kernel_for(p->log2n, dec, split, false);
-            p->single_inv = fftk::single_kernel_for(p->log2n, dec, split, true);
+            p->single = fftk::single_kernel_for(p->rb, p->log2n, dec, split, false);
+            p->single_inv = fftk::single_kernel_for(p->rb, p->log2n, dec, split, true);
             if (!p->single || !p->single_inv) return FFT_ERR_NOT_SUPPORTED;
-            p->tw32_n = p->single->eng.tw_size;
+            p->twe_n = p->single->eng.tw_size;
             break;
         case Decomp::MULTI: {
             const size_t P = dec.log2l.size();
@@ -134,8 +136,8 @@ fft_status resolve(fft_plan p, const Decomp& dec) {
             for (size_t i = 0; i < P; ++i) {
                 PassStep st{};
                 const bool first = i == 0, last = i == P - 1;
-                st.k = fftk::pass_kernel_for(dec.log2l[i], dec.log2c[i], i, P, split, false);
-                st.k_inv = fftk::pass_kernel_for(dec.log2l[i], dec.log2c[i], i, P, split, true);
+                st.k = fftk::pass_kernel_for(p->rb, dec.log2l[i], dec.log2c[i], i, P, split, false);
+                st.k_inv = fftk::pass_kernel_for(p->rb, dec.log2l[i], dec.log2c[i], i, P, split, true);
                 if (!st.k || !st.k_inv) return FFT_ERR_NOT_SUPPORTED;
                 int per_cu = 0;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, st.k->kernel, st.k->threads, 0) !=
@@ -144,8 +146,8 @@ fft_status resolve(fft_plan p, const Decomp& dec) {
                     per_cu = 1;
                 st.grid = per_cu * p->cus;
                 st.log2ns = log2ns;
-                st.tw32_off = p->tw32_n;
-                p->tw32_n += (st.k->eng.tw_size + 1) & ~size_t(1);  // keep 16-byte alignment
+                st.twe_off = p->twe_n;
+                p->twe_n += (st.k->eng.tw_size + 1) & ~size_t(1);  // keep 16-byte alignment
                 if (!first) {
                     const int log2m = log2ns + dec.log2l[i];
                     st.hbits = (log2m + 1) / 2;
@@ -160,7 +162,7 @@ fft_status resolve(fft_plan p, const Decomp& dec) {
                 p->steps.push_back(st);
                 log2ns += dec.log2l[i];
             }
-            const size_t half = size_t(p->n) * size_t(p->batch) * sizeof(float2);
+            const size_t half = size_t(p->n) * size_t(p->batch) * p->cbytes();
             p->ws_bytes = (P >= 3 ? 2 : 1) * half;
             break;
         }
@@ -168,11 +170,12 @@ fft_status resolve(fft_plan p, const Decomp& dec) {
     return FFT_OK;
 }
 
-// Allocate and fill the twiddle tables (FP64 on the GPU, rounded once).
+// Allocate and fill the twiddle tables (FP64 on the GPU, rounded once to the
+// plan's precision).
 fft_status build_tables(fft_plan p, hipStream_t s) {
     hipError_t e;
-    if (p->tw32_n) {
-        e = dev_malloc(reinterpret_cast<void**>(&p->tw32), p->tw32_n * sizeof(float2));
+    if (p->twe_n) {
+        e = dev_malloc(&p->twe, p->twe_n * p->cbytes());
         if (e != hipSuccess) {
             g_detail = "twiddle table allocation failed";
             return FFT_ERR_ALLOC;
@@ -186,12 +189,13 @@ fft_status build_tables(fft_plan p, hipStream_t s) {
         }
     }
     if (p->single && p->single->eng.tw_size) {
-        e = fftk::launch_gen_engine_tw(p->single->eng, p->tw32, s);
+        e = fftk::launch_gen_engine_tw(p->single->eng, p->twe, p->rb, s);
         if (e != hipSuccess) return fail_hip(e, "twiddle generation");
     }
     for (const PassStep& st : p->steps) {
         if (st.k->eng.tw_size) {
-            e = fftk::launch_gen_engine_tw(st.k->eng, p->tw32 + st.tw32_off, s);
+            e = fftk::launch_gen_engine_tw(st.k->eng, static_cast<char*>(p->twe) + st.twe_off * p->cbytes(), p->rb,
+                                           s);
             if (e != hipSuccess) return fail_hip(e, "twiddle generation");
         }
         if (st.log2ns > 0) {
@@ -237,7 +241,7 @@ fft_status check_buffers(fft_plan p, const void* ia, const void* ib, const void*
     auto mis = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) != 0; };
     if (mis(ia) || mis(oa) || (split && (mis(ib) || mis(ob)))) return FFT_ERR_MISALIGNED;
     const size_t elems = size_t(p->elements);
-    const size_t bytes = split ? elems * sizeof(float) : elems * sizeof(float2);
+    const size_t bytes = split ? elems * size_t(p->rb) : elems * p->cbytes();
     const uintptr_t ua = uintptr_t(ia), ub = split ? uintptr_t(ib) : 0, va = uintptr_t(oa),
                     vb = split ? uintptr_t(ob) : 0;
     const size_t nb = split ? bytes : 0;
@@ -260,22 +264,25 @@ fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, v
     // out: split arrays by exchanging the pointers, interleaved data in-kernel
     const bool inverse = (p->dir == FFT_INVERSE) != adjoint;
     const bool split = p->layout == FFT_LAYOUT_SPLIT;
-    const float* fa = static_cast<const float*>(ia);
-    const float* fb = static_cast<const float*>(ib);
-    float* ga = static_cast<float*>(oa);
-    float* gb = static_cast<float*>(ob);
+    const void* fa = ia;
+    const void* fb = ib;
+    void* ga = oa;
+    void* gb = ob;
     if (inverse && split) {
         std::swap(fa, fb);
         std::swap(ga, gb);
     }
     hipError_t e = hipSuccess;
 
-    if (p->ragged) return fftk::ragged_execute(p->ragged, fa, fb, ga, gb, inverse && !split, s, &g_detail);
+    if (p->ragged)
+        return fftk::ragged_execute(p->ragged, static_cast<const float*>(fa), static_cast<const float*>(fb),
+                                    static_cast<float*>(ga), static_cast<float*>(gb), inverse && !split, s,
+                                    &g_detail);
 
     switch (p->dec.kind) {
         case Decomp::COPY: {
             if (ia == oa && (!split || ib == ob)) return FFT_OK;
-            const size_t bytes = size_t(p->elements) * (split ? sizeof(float) : sizeof(float2));
+            const size_t bytes = size_t(p->elements) * (split ? size_t(p->rb) : p->cbytes());
             e = hipMemcpyAsync(oa, ia, bytes, hipMemcpyDeviceToDevice, s);
             if (e == hipSuccess && split) e = hipMemcpyAsync(ob, ib, bytes, hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) return fail_hip(e, "copy");
@@ -283,7 +290,7 @@ fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, v
         }
         case Decomp::SINGLE: {
             const fftk::SingleKernel* k = inverse ? p->single_inv : p->single;
-            e = k->fn(fa, fb, ga, gb, p->tw32, p->batch, p->dec.gmul * p->cus, s);
+            e = k->fn(fa, fb, ga, gb, p->twe, p->batch, p->dec.gmul * p->cus, s);
             if (e != hipSuccess) return fail_hip(e, "single-pass launch");
             return FFT_OK;
         }
@@ -292,14 +299,14 @@ fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, v
                 g_detail = "no workspace";
                 return FFT_ERR_INVALID_ARG;
             }
-            const size_t half = size_t(p->n) * size_t(p->batch) * sizeof(float2);
-            float* wsa = static_cast<float*>(p->ws());
-            float* wsb = reinterpret_cast<float*>(static_cast<char*>(p->ws()) + half);
+            const size_t half = size_t(p->n) * size_t(p->batch) * p->cbytes();
+            void* wsa = p->ws();
+            void* wsb = static_cast<char*>(p->ws()) + half;
             const size_t P = p->steps.size();
             for (size_t i = 0; i < P; ++i) {
                 const PassStep& stp = p->steps[i];
-                const float *sa = nullptr, *sb = nullptr;
-                float *da = nullptr, *db = nullptr;
+                const void *sa = nullptr, *sb = nullptr;
+                void *da = nullptr, *db = nullptr;
                 if (stp.src == 0) {
                     sa = fa;
                     sb = fb;
@@ -313,7 +320,8 @@ fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, v
                     da = stp.dst == 1 ? wsa : wsb;
                 }
                 const fftk::PassKernel* k = inverse ? stp.k_inv : stp.k;
-                e = k->fn(sa, sb, da, db, p->tw32 + stp.tw32_off, p->tw64 ? p->tw64 + stp.ta_off : nullptr,
+                e = k->fn(sa, sb, da, db, static_cast<const char*>(p->twe) + stp.twe_off * p->cbytes(),
+                          p->tw64 ? p->tw64 + stp.ta_off : nullptr,
                           p->tw64 ? p->tw64 + stp.tb_off : nullptr, p->log2n, stp.log2ns, stp.hbits, p->batch,
                           stp.grid, s);
                 if (e != hipSuccess) return fail_hip(e, "pass launch");
@@ -328,9 +336,10 @@ fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, v
 std::string describe(fft_plan p) {
     char buf[512];
     std::string s = "{";
-    snprintf(buf, sizeof buf, "\"n\": %lld, \"batch\": %lld, \"layout\": \"%s\", \"direction\": \"%s\", ",
+    snprintf(buf, sizeof buf,
+             "\"n\": %lld, \"batch\": %lld, \"layout\": \"%s\", \"direction\": \"%s\", \"precision\": \"%s\", ",
              (long long)p->n, (long long)p->batch, p->layout == FFT_LAYOUT_SPLIT ? "split" : "interleaved",
-             p->dir == FFT_FORWARD ? "forward" : "inverse");
+             p->dir == FFT_FORWARD ? "forward" : "inverse", p->rb == 8 ? "fp64" : "fp32");
     s += buf;
     if (p->ragged) {
         s += fftk::ragged_describe(p->ragged);
@@ -387,17 +396,18 @@ double nominal_flops(int64_t n) {
 extern "C" {
 
 static fft_status create_impl(fft_plan* out, int64_t n, int64_t batch, fft_layout layout, fft_direction dir,
-                              const char* explicit_dec) {
+                              fft_precision precision, const char* explicit_dec) {
     if (!out) return FFT_ERR_NULL_POINTER;
     *out = nullptr;
     const int log2n = fftk::ilog2_exact(n);
     if (log2n < 0 || log2n > fftk::kMaxLog2N) return FFT_ERR_INVALID_SIZE;
-    if (batch < 1 || !valid_layout(layout) || !valid_dir(dir)) return FFT_ERR_INVALID_ARG;
+    const int rb = fftk::real_bytes_of(precision);
+    if (batch < 1 || !valid_layout(layout) || !valid_dir(dir) || rb == 0) return FFT_ERR_INVALID_ARG;
     if (batch > (int64_t(1) << 40) / n) return FFT_ERR_INVALID_ARG;  // element count bound
     Decomp forced;
     if (explicit_dec) {
         if (!Decomp::parse(explicit_dec, &forced)) return FFT_ERR_INVALID_ARG;
-        if (!fftk::decomposition_available(forced, log2n, layout)) return FFT_ERR_NOT_SUPPORTED;
+        if (!fftk::decomposition_available(forced, log2n, layout, rb)) return FFT_ERR_NOT_SUPPORTED;
     }
 
     fft_plan p = new (std::nothrow) fft_plan_s;
@@ -407,6 +417,7 @@ static fft_status create_impl(fft_plan* out, int64_t n, int64_t batch, fft_layou
     p->log2n = log2n;
     p->layout = layout;
     p->dir = dir;
+    p->rb = rb;
     p->elements = n * batch;
     p->flops = nominal_flops(n) * double(batch);
     hipError_t e = hipGetDevice(&p->device);
@@ -416,14 +427,14 @@ static fft_status create_impl(fft_plan* out, int64_t n, int64_t batch, fft_layou
         return fail_hip(e, "hipGetDevice");
     }
 
-    Decomp dec = fftk::default_decomposition(log2n);
+    Decomp dec = fftk::default_decomposition(log2n, rb);
     p->source = "default";
-    fftk::TuneKey key = fftk::make_key(p->device, log2n, batch, layout);
+    fftk::TuneKey key = fftk::make_key(p->device, log2n, batch, layout, rb);
     Decomp cached;
     if (explicit_dec) {
         dec = forced;
         p->source = "explicit";
-    } else if (fftk::autotune_lookup(key, &cached) && fftk::decomposition_available(cached, log2n, layout)) {
+    } else if (fftk::autotune_lookup(key, &cached) && fftk::decomposition_available(cached, log2n, layout, rb)) {
         dec = cached;
         p->source = "cache";
     }
@@ -453,13 +464,18 @@ static fft_status create_impl(fft_plan* out, int64_t n, int64_t batch, fft_layou
 }
 
 fft_status fft_plan_create(fft_plan* out, int64_t n, int64_t batch, fft_layout layout, fft_direction dir) {
-    return create_impl(out, n, batch, layout, dir, nullptr);
+    return create_impl(out, n, batch, layout, dir, FFT_PRECISION_FP32, nullptr);
 }
 
 fft_status fft_plan_create_explicit(fft_plan* out, int64_t n, int64_t batch, fft_layout layout, fft_direction dir,
                                     const char* decomposition) {
     if (!decomposition) return FFT_ERR_NULL_POINTER;
-    return create_impl(out, n, batch, layout, dir, decomposition);
+    return create_impl(out, n, batch, layout, dir, FFT_PRECISION_FP32, decomposition);
+}
+
+fft_status fft_plan_create_ex(fft_plan* out, int64_t n, int64_t batch, fft_layout layout, fft_direction dir,
+                              fft_precision precision, const char* decomposition) {
+    return create_impl(out, n, batch, layout, dir, precision, decomposition);
 }
 
 fft_status fft_execute(fft_plan p, const void* in_re_or_z, const void* in_im, void* out_re_or_z, void* out_im,
@@ -561,14 +577,16 @@ fft_status fft_plan_describe(fft_plan p, char* buf, size_t len) {
     return copy_out(describe(p), buf, len);
 }
 
-fft_status fft_query_decomposition(int64_t n, fft_layout layout, char* buf, size_t len) {
+fft_status fft_query_decomposition(int64_t n, fft_layout layout, fft_precision precision, char* buf, size_t len) {
     const int log2n = fftk::ilog2_exact(n);
     if (log2n < 0 || log2n > fftk::kMaxLog2N) return FFT_ERR_INVALID_SIZE;
-    if (!valid_layout(layout)) return FFT_ERR_INVALID_ARG;
-    const Decomp d = fftk::default_decomposition(log2n);
-    std::string s = "{\"n\": " + std::to_string(n) + ", \"default\": \"" + d.str() + "\", \"available\": " +
-                    (fftk::decomposition_available(d, log2n, layout) ? "true" : "false") + ", \"candidates\": [";
-    const auto cands = fftk::candidate_decompositions(log2n, layout);
+    const int rb = fftk::real_bytes_of(precision);
+    if (!valid_layout(layout) || rb == 0) return FFT_ERR_INVALID_ARG;
+    const Decomp d = fftk::default_decomposition(log2n, rb);
+    std::string s = "{\"n\": " + std::to_string(n) + ", \"precision\": \"" + (rb == 8 ? "fp64" : "fp32") +
+                    "\", \"default\": \"" + d.str() + "\", \"available\": " +
+                    (fftk::decomposition_available(d, log2n, layout, rb) ? "true" : "false") + ", \"candidates\": [";
+    const auto cands = fftk::candidate_decompositions(log2n, layout, rb);
     for (size_t i = 0; i < cands.size(); ++i) s += (i ? ", \"" : "\"") + cands[i].str() + "\"";
     s += "]}";
     return copy_out(s, buf, len);
@@ -615,6 +633,7 @@ fft_status plan_time_decomposition(fft_plan p, const Decomp& d, void* in, void* 
     tmp.batch = p->batch;
     tmp.log2n = p->log2n;
     tmp.layout = p->layout;
+    tmp.rb = p->rb;
     tmp.dir = FFT_FORWARD;
     tmp.elements = p->elements;
     fft_status st = resolve(&tmp, d);
@@ -626,7 +645,7 @@ fft_status plan_time_decomposition(fft_plan p, const Decomp& d, void* in, void* 
         return st;
     }
     const bool split = p->layout == FFT_LAYOUT_SPLIT;
-    const size_t half = size_t(p->elements) * sizeof(float);
+    const size_t half = size_t(p->elements) * size_t(p->rb);
     void* ib = split ? static_cast<char*>(in) + half : nullptr;
     void* ob = split ? static_cast<char*>(out) + half : nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -659,5 +678,6 @@ const Decomp& plan_decomposition(fft_plan p) { return p->dec; }
 int64_t plan_elements(fft_plan p) { return p->elements; }
 fft_layout plan_layout(fft_plan p) { return p->layout; }
 int plan_log2n(fft_plan p) { return p->log2n; }
+int plan_real_bytes(fft_plan p) { return p->rb; }
 
 }  // namespace fftk

@@ -23,44 +23,75 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace fftk {
 
 // ---------------------------------------------------------------------------
-// complex helpers (float2 = (re, im))
+// complex helpers, generic over the vector type V = float2 (FP32) or double2
+// (FP64): (x, y) = (re, im)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+template <class V> struct RealOf;
+template <> struct RealOf<float2> { using type = float; };
+template <> struct RealOf<double2> { using type = double; };
+template <class R> struct CplxOf;
+template <> struct CplxOf<float> { using type = float2; };
+template <> struct CplxOf<double> { using type = double2; };
+template <class R> using cplx_t = typename CplxOf<R>::type;
+
+__device__ __forceinline__ float2 cmk(float x, float y) { return make_float2(x, y); }
+__device__ __forceinline__ double2 cmk(double x, double y) { return make_double2(x, y); }
+__device__ __forceinline__ float fmx(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmx(double a, double b, double c) { return fma(a, b, c); }
+
+template <class V> __device__ __forceinline__ V c_add(V a, V b) { return cmk(a.x + b.x, a.y + b.y); }
+template <class V> __device__ __forceinline__ V c_sub(V a, V b) { return cmk(a.x - b.x, a.y - b.y); }
 // a * w
-__device__ __forceinline__ float2 c_mul(float2 a, float2 w) {
-    return make_float2(fmaf(a.x, w.x, -(a.y * w.y)), fmaf(a.x, w.y, a.y * w.x));
+template <class V> __device__ __forceinline__ V c_mul(V a, V w) {
+    return cmk(fmx(a.x, w.x, -(a.y * w.y)), fmx(a.x, w.y, a.y * w.x));
 }
 // a * (-i)
-__device__ __forceinline__ float2 c_mul_mi(float2 a) { return make_float2(a.y, -a.x); }
+template <class V> __device__ __forceinline__ V c_mul_mi(V a) { return cmk(a.y, -a.x); }
+template <class V> __device__ __forceinline__ V c_zero() { return cmk(typename RealOf<V>::type(0), typename RealOf<V>::type(0)); }
 
-// exp(-2 pi i m / 16) for the register DFT_16 and DFT_8, correctly rounded
-// float literals of cos(pi/8), sin(pi/8) and sqrt(2)/2.
-constexpr float K_C1 = 0.923879532511286756128f;  // cos(pi/8)
-constexpr float K_S1 = 0.382683432365089771728f;  // sin(pi/8)
-constexpr float K_R2 = 0.707106781186547524401f;  // sqrt(2)/2
+// exp(-2 pi i m / 16) for the register DFT_16 and DFT_8: cos(pi/8), sin(pi/8)
+// and sqrt(2)/2 as correctly rounded literals of each precision.
+template <class R> struct K16;
+template <> struct K16<float> {
+    static constexpr float C1 = 0.923879532511286756128f;  // cos(pi/8)
+    static constexpr float S1 = 0.382683432365089771728f;  // sin(pi/8)
+    static constexpr float R2 = 0.707106781186547524401f;  // sqrt(2)/2
+};
+template <> struct K16<double> {
+    static constexpr double C1 = 0.923879532511286756128;
+    static constexpr double S1 = 0.382683432365089771728;
+    static constexpr double R2 = 0.707106781186547524401;
+};
 
 // a * exp(-2 pi i / 8) = a * (r, -r)
-__device__ __forceinline__ float2 c_mul_w8_1(float2 a) { return make_float2(K_R2 * (a.x + a.y), K_R2 * (a.y - a.x)); }
+template <class V> __device__ __forceinline__ V c_mul_w8_1(V a) {
+    constexpr auto r = K16<typename RealOf<V>::type>::R2;
+    return cmk(r * (a.x + a.y), r * (a.y - a.x));
+}
 // a * exp(-2 pi i 3 / 8) = a * (-r, -r)
-__device__ __forceinline__ float2 c_mul_w8_3(float2 a) { return make_float2(K_R2 * (a.y - a.x), -K_R2 * (a.x + a.y)); }
+template <class V> __device__ __forceinline__ V c_mul_w8_3(V a) {
+    constexpr auto r = K16<typename RealOf<V>::type>::R2;
+    return cmk(r * (a.y - a.x), -r * (a.x + a.y));
+}
 
 // ---------------------------------------------------------------------------
 // DFT_R in registers, forward, natural order in and out.
 // DFT_8 and DFT_16 are themselves one step of Eq. 1 (K = 2 or 4, M = 4).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void dft2(float2& a0, float2& a1) {
-    float2 t = a0;
+template <class V> __device__ __forceinline__ void dft2(V& a0, V& a1) {
+    V t = a0;
     a0 = c_add(t, a1);
     a1 = c_sub(t, a1);
 }
 
-__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
-    float2 t0 = c_add(a0, a2), t1 = c_sub(a0, a2);
-    float2 t2 = c_add(a1, a3), t3 = c_mul_mi(c_sub(a1, a3));
+template <class V> __device__ __forceinline__ void dft4(V& a0, V& a1, V& a2, V& a3) {
+    V t0 = c_add(a0, a2), t1 = c_sub(a0, a2);
+    V t2 = c_add(a1, a3), t3 = c_mul_mi(c_sub(a1, a3));
     a0 = c_add(t0, t2);
     a2 = c_sub(t0, t2);
     a1 = c_add(t1, t3);
@@ -70,16 +101,16 @@ __device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2&
 template <int R> struct Dft;
 
 template <> struct Dft<1> {
-    __device__ __forceinline__ static void run(float2*) {}
+    template <class V> __device__ __forceinline__ static void run(V*) {}
 };
 template <> struct Dft<2> {
-    __device__ __forceinline__ static void run(float2* v) { dft2(v[0], v[1]); }
+    template <class V> __device__ __forceinline__ static void run(V* v) { dft2(v[0], v[1]); }
 };
 template <> struct Dft<4> {
-    __device__ __forceinline__ static void run(float2* v) { dft4(v[0], v[1], v[2], v[3]); }
+    template <class V> __device__ __forceinline__ static void run(V* v) { dft4(v[0], v[1], v[2], v[3]); }
 };
 template <> struct Dft<8> {
-    __device__ __forceinline__ static void run(float2* v) {
+    template <class V> __device__ __forceinline__ static void run(V* v) {
         // K = 2 sub-sequences of stride 2, DFT_4 each
         dft4(v[0], v[2], v[4], v[6]);
         dft4(v[1], v[3], v[5], v[7]);
@@ -88,10 +119,10 @@ template <> struct Dft<8> {
         v[5] = c_mul_mi(v[5]);
         v[7] = c_mul_w8_3(v[7]);
         // DFT_2 across n2: X[k1 + 4 k2]
-        float2 o[8];
+        V o[8];
 #pragma unroll
         for (int k1 = 0; k1 < 4; ++k1) {
-            float2 a = v[2 * k1], b = v[2 * k1 + 1];
+            V a = v[2 * k1], b = v[2 * k1 + 1];
             o[k1] = c_add(a, b);
             o[k1 + 4] = c_sub(a, b);
         }
@@ -100,14 +131,15 @@ template <> struct Dft<8> {
     }
 };
 template <> struct Dft<16> {
-    __device__ __forceinline__ static void run(float2* v) {
+    template <class V> __device__ __forceinline__ static void run(V* v) {
         // K = 4 sub-sequences x[4 n1 + n2], DFT_4 over n1
 #pragma unroll
         for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
         // v[n2 + 4 k1] = A[n2][k1]; twiddle w_16^(n2 k1)
-        const float2 w1 = make_float2(K_C1, -K_S1);
-        const float2 w3 = make_float2(K_S1, -K_C1);
-        const float2 w9 = make_float2(-K_C1, K_S1);
+        using K = K16<typename RealOf<V>::type>;
+        const V w1 = cmk(K::C1, -K::S1);
+        const V w3 = cmk(K::S1, -K::C1);
+        const V w9 = cmk(-K::C1, K::S1);
         v[5] = c_mul(v[5], w1);     // n2=1 k1=1
         v[9] = c_mul_w8_1(v[9]);    // n2=1 k1=2 (w^2)
         v[13] = c_mul(v[13], w3);   // n2=1 k1=3
@@ -120,7 +152,7 @@ template <> struct Dft<16> {
         // DFT_4 across n2 for each k1 -> X[k1 + 4 k2] sits in v[4 k1 + k2]
 #pragma unroll
         for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
-        float2 o[16];
+        V o[16];
 #pragma unroll
         for (int k1 = 0; k1 < 4; ++k1)
 #pragma unroll
@@ -165,7 +197,7 @@ struct Sched {
     static constexpr int TW_SIZE = NST > 1 ? twOff(NST) : 0;
 };
 
-// LDS index of element i of group g: one float2 of padding every 16 elements
+// LDS index of element i of group g: one element of padding every 16 elements
 // breaks the power-of-two strides of the Stockham stores across banks.
 template <int GS>
 __device__ __forceinline__ int lds_at(int g, int i) { return g * GS + i + (i >> 4); }
@@ -192,20 +224,22 @@ __device__ __forceinline__ void stage_sync() {
 //          kernels then reuse them for every transform they process, and no
 //          table load competes with the streaming data loads.
 // ---------------------------------------------------------------------------
-template <class SC>
+template <class SC, class V = float2>
 struct TwMem {
-    const float2* __restrict__ p;
-    __device__ __forceinline__ explicit TwMem(const float2* q) : p(q) {}
+    const V* __restrict__ p;
+    __device__ __forceinline__ explicit TwMem(const V* q) : p(q) {}
     __device__ __forceinline__ void init(int) {}
 
     template <int S, int R>
-    __device__ __forceinline__ void apply(float2 (&u)[R], int /*b*/, int j) const {
+    __device__ __forceinline__ void apply(V (&u)[R], int /*b*/, int j) const {
         constexpr int LNS = SC::log2NS(S);
         const int k = j & ((1 << LNS) - 1);
-        const float2* q = p + SC::twOff(S) + k * R;
-        if constexpr (R == 2) {
-            u[1] = c_mul(u[1], q[1]);
+        const V* q = p + SC::twOff(S) + k * R;
+        if constexpr (R == 2 || !std::is_same<V, float2>::value) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) u[r] = c_mul(u[r], q[r]);
         } else {
+            // FP32: two twiddles per 16-byte load
             const float4* q4 = reinterpret_cast<const float4*>(q);
 #pragma unroll
             for (int h = 0; h < R / 2; ++h) {
@@ -217,28 +251,32 @@ struct TwMem {
     }
 };
 
-template <class SC>
+template <class SC, class V = float2>
 struct TwReg {
     static constexpr int E = SC::E;
-    const float2* __restrict__ p;
-    float2 w[SC::NST > 1 ? SC::NST : 1][E];  // w[S][b*R + r]
-    __device__ __forceinline__ explicit TwReg(const float2* q) : p(q) {}
+    const V* __restrict__ p;
+    V w[SC::NST > 1 ? SC::NST : 1][E];  // w[S][b*R + r]
+    __device__ __forceinline__ explicit TwReg(const V* q) : p(q) {}
+
+    // one stage's entries for the thread whose stage-S index is t (S > 0)
+    template <int S>
+    __device__ __forceinline__ void load_stage_only(int t) {
+        constexpr int R = 1 << SC::log2R(S);
+        constexpr int B = E / R;
+        constexpr int LNS = SC::log2NS(S);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int k = (t + b * SC::T) & ((1 << LNS) - 1);
+            const V* q = p + SC::twOff(S) + k * R;
+#pragma unroll
+            for (int r = 1; r < R; ++r) w[S][b * R + r] = q[r];
+        }
+    }
 
     template <int S>
     __device__ __forceinline__ void load_stage(int t) {
         if constexpr (S < SC::NST) {
-            if constexpr (S > 0) {
-                constexpr int R = 1 << SC::log2R(S);
-                constexpr int B = E / R;
-                constexpr int LNS = SC::log2NS(S);
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    const int k = (t + b * SC::T) & ((1 << LNS) - 1);
-                    const float2* q = p + SC::twOff(S) + k * R;
-#pragma unroll
-                    for (int r = 1; r < R; ++r) w[S][b * R + r] = q[r];
-                }
-            }
+            if constexpr (S > 0) load_stage_only<S>(t);
             load_stage<S + 1>(t);
         }
     }
@@ -252,16 +290,7 @@ struct TwReg {
             if constexpr (S > 0) {
                 int g, t;
                 ENG::template map<S>(tid, g, t);
-                constexpr int R = 1 << SC::log2R(S);
-                constexpr int B = E / R;
-                constexpr int LNS = SC::log2NS(S);
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    const int k = (t + b * SC::T) & ((1 << LNS) - 1);
-                    const float2* q = p + SC::twOff(S) + k * R;
-#pragma unroll
-                    for (int r = 1; r < R; ++r) w[S][b * R + r] = q[r];
-                }
+                load_stage_only<S>(t);
             }
             load_stage_mapped<ENG, S + 1>(tid);
         }
@@ -270,9 +299,27 @@ struct TwReg {
     __device__ __forceinline__ void init_engine(int tid) { load_stage_mapped<ENG, 0>(tid); }
 
     template <int S, int R>
-    __device__ __forceinline__ void apply(float2 (&u)[R], int b, int /*j*/) const {
+    __device__ __forceinline__ void apply(V (&u)[R], int b, int /*j*/) const {
 #pragma unroll
         for (int r = 1; r < R; ++r) u[r] = c_mul(u[r], w[S][b * R + r]);
+    }
+};
+
+// Registers for the last stage's twiddles (the largest table), the table for
+// the stages before it: half the register cost of TwReg for three-stage
+// schedules.  The earlier stages' tables are small and stay in L1.
+template <class SC, class V = float2>
+struct TwLast {
+    TwReg<SC, V> reg;
+    TwMem<SC, V> mem;
+    __device__ __forceinline__ explicit TwLast(const V* q) : reg(q), mem(q) {}
+    __device__ __forceinline__ void init(int t) {
+        if constexpr (SC::NST > 1) reg.template load_stage_only<SC::NST - 1>(t);
+    }
+    template <int S, int R>
+    __device__ __forceinline__ void apply(V (&u)[R], int b, int j) const {
+        if constexpr (S == SC::NST - 1) reg.template apply<S, R>(u, b, j);
+        else mem.template apply<S, R>(u, b, j);
     }
 };
 
@@ -309,15 +356,15 @@ struct Engine {
     }
 
     // butterflies of stage S on registers; j = t + b*T
-    template <int S, class TW>
-    __device__ __forceinline__ static void compute(float2 (&v)[E], int t, const TW& tw) {
+    template <int S, class V, class TW>
+    __device__ __forceinline__ static void compute(V (&v)[E], int t, const TW& tw) {
         constexpr int LR = SC::log2R(S);
         constexpr int R = 1 << LR;
         constexpr int B = E / R;
         constexpr int NS = 1 << SC::log2NS(S);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            float2 u[R];
+            V u[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) u[r] = v[b + r * B];
             if constexpr (NS > 1) tw.template apply<S, R>(u, b, t + b * T);
@@ -327,31 +374,50 @@ struct Engine {
         }
     }
 
-    // store stage S's outputs into LDS at their self-sorting positions
-    template <int S>
-    __device__ __forceinline__ static void write(const float2 (&v)[E], int g, int t, float2* lds) {
+    // store stage S's outputs into LDS at their self-sorting positions.  The
+    // padded index i + (i >> 4) of base + r*Ns splits into a per-butterfly part
+    // plus a constant whenever r*Ns is a multiple of 16 (Ns >= 16) or r < 16
+    // stays below the next multiple of 16 (Ns = 1, base a multiple of 16), so
+    // each butterfly costs one address computation instead of R.
+    template <int S, class V>
+    __device__ __forceinline__ static void write(const V (&v)[E], int g, int t, V* lds) {
         constexpr int LR = SC::log2R(S);
         constexpr int R = 1 << LR;
         constexpr int B = E / R;
         constexpr int LNS = SC::log2NS(S);
         constexpr int NS = 1 << LNS;
+        constexpr bool SPLITS = NS >= 16 || (NS == 1 && R == 16);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int j = t + b * T;
             const int k = j & (NS - 1);
             const int base = ((j >> LNS) << (LNS + LR)) + k;
+            if constexpr (SPLITS) {
+                V* p = lds + lds_at<GS>(g, base);
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[lds_at<GS>(g, base + r * NS)] = v[b + r * B];
+                for (int r = 0; r < R; ++r) p[NS >= 16 ? r * NS + ((r * NS) >> 4) : r] = v[b + r * B];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[lds_at<GS>(g, base + r * NS)] = v[b + r * B];
+            }
         }
     }
 
-    __device__ __forceinline__ static void read(float2 (&v)[E], int g, int t, const float2* lds) {
+    template <class V>
+    __device__ __forceinline__ static void read(V (&v)[E], int g, int t, const V* lds) {
+        if constexpr (T >= 16) {
+            // T*m is a multiple of 16: padding of t + T*m = padding of t + T*m/16
+            const V* p = lds + lds_at<GS>(g, t);
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = lds[lds_at<GS>(g, t + T * m)];
+            for (int m = 0; m < E; ++m) v[m] = p[T * m + ((T * m) >> 4)];
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = lds[lds_at<GS>(g, t + T * m)];
+        }
     }
 
-    template <int S, class TW>
-    __device__ __forceinline__ static void stage(float2 (&v)[E], float2* lds, const TW& tw, int tid) {
+    template <int S, class V, class TW>
+    __device__ __forceinline__ static void stage(V (&v)[E], V* lds, const TW& tw, int tid) {
         int g, t;
         map<S>(tid, g, t);
         if constexpr (S > 0) read(v, g, t, lds);
@@ -364,73 +430,76 @@ struct Engine {
         }
     }
 
-    template <class TW>
-    __device__ __forceinline__ static void run(float2 (&v)[E], float2* lds, const TW& tw, int tid) {
+    template <class V, class TW>
+    __device__ __forceinline__ static void run(V (&v)[E], V* lds, const TW& tw, int tid) {
         stage<0>(v, lds, tw, tid);
-    }
-    __device__ __forceinline__ static void run(float2 (&v)[E], float2* lds, const float2* __restrict__ tw, int tid) {
-        stage<0>(v, lds, TwMem<SC>(tw), tid);
     }
 };
 
-// LDS floats2 needed by an engine with G groups of stride GS (0 if one stage)
+// LDS complex elements needed by an engine with G groups of stride GS (0 if one stage)
 template <class SC, int G, int GS>
 constexpr int engine_lds_elems() { return SC::NST > 1 ? G * GS : 1; }
 
 // ---------------------------------------------------------------------------
 // Global memory access for the two layouts.  `a` is the interleaved array
-// (as float*) or the real array; `b` the imaginary array (split only).
+// (as R*) or the real array; `b` the imaginary array (split only).
 // ---------------------------------------------------------------------------
-template <bool SPLIT>
-__device__ __forceinline__ float2 gload(const float* a, const float* b, int64_t i) {
+template <bool SPLIT, class R>
+__device__ __forceinline__ cplx_t<R> gload(const R* a, const R* b, int64_t i) {
     if constexpr (SPLIT) {
-        return make_float2(a[i], b[i]);
+        return cmk(a[i], b[i]);
     } else {
-        return reinterpret_cast<const float2*>(a)[i];
+        return reinterpret_cast<const cplx_t<R>*>(a)[i];
     }
 }
 
-template <bool SPLIT>
-__device__ __forceinline__ void gstore(float* a, float* b, int64_t i, float2 v) {
+template <bool SPLIT, class R>
+__device__ __forceinline__ void gstore(R* a, R* b, int64_t i, cplx_t<R> v) {
     if constexpr (SPLIT) {
         a[i] = v.x;
         b[i] = v.y;
     } else {
-        reinterpret_cast<float2*>(a)[i] = v;
+        reinterpret_cast<cplx_t<R>*>(a)[i] = v;
     }
 }
 
 // Streaming (nontemporal) variants for data that is read once and written
 // once: the loads and stores carry the streaming cache hint.
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+template <class R> struct NtVec;
+template <> struct NtVec<float> { using type = f32x2_t; };
+template <> struct NtVec<double> { using type = f64x2_t; };
 
-template <bool SPLIT>
-__device__ __forceinline__ float2 gload_nt(const float* a, const float* b, int64_t i) {
+template <bool SPLIT, class R>
+__device__ __forceinline__ cplx_t<R> gload_nt(const R* a, const R* b, int64_t i) {
     if constexpr (SPLIT) {
-        return make_float2(__builtin_nontemporal_load(a + i), __builtin_nontemporal_load(b + i));
+        return cmk(__builtin_nontemporal_load(a + i), __builtin_nontemporal_load(b + i));
     } else {
-        const f32x2_t x = __builtin_nontemporal_load(reinterpret_cast<const f32x2_t*>(a) + i);
-        return make_float2(x.x, x.y);
+        using NV = typename NtVec<R>::type;
+        const NV x = __builtin_nontemporal_load(reinterpret_cast<const NV*>(a) + i);
+        return cmk(R(x.x), R(x.y));
     }
 }
 
-template <bool SPLIT>
-__device__ __forceinline__ void gstore_nt(float* a, float* b, int64_t i, float2 v) {
+template <bool SPLIT, class R>
+__device__ __forceinline__ void gstore_nt(R* a, R* b, int64_t i, cplx_t<R> v) {
     if constexpr (SPLIT) {
         __builtin_nontemporal_store(v.x, a + i);
         __builtin_nontemporal_store(v.y, b + i);
     } else {
-        f32x2_t x;
+        using NV = typename NtVec<R>::type;
+        NV x;
         x.x = v.x;
         x.y = v.y;
-        __builtin_nontemporal_store(x, reinterpret_cast<f32x2_t*>(a) + i);
+        __builtin_nontemporal_store(x, reinterpret_cast<NV*>(a) + i);
     }
 }
 
 // real/imaginary swap S of the inverse (free: a register renaming)
-template <bool SWAP>
-__device__ __forceinline__ float2 swap_if(float2 a) {
-    if constexpr (SWAP) return make_float2(a.y, a.x);
+template <bool SWAP, class V>
+__device__ __forceinline__ V swap_if(V a) {
+    if constexpr (SWAP) return cmk(a.y, a.x);
     else return a;
 }
 
@@ -454,14 +523,19 @@ __device__ __forceinline__ double2 twiddle_2level64(const double2* __restrict__ 
 }
 
 // w_M^e = exp(-2 pi i e / M) from two FP64 tables, A[i] = w_M^(i << hbits) and
-// B[i] = w_M^i (i < 2^hbits): the product is formed in FP64 and rounded once.
-__device__ __forceinline__ float2 twiddle_2level(const double2* __restrict__ ta, const double2* __restrict__ tb,
-                                                 int64_t e, int hbits) {
-    const double2 a = ta[e >> hbits];
-    const double2 c = tb[e & ((int64_t(1) << hbits) - 1)];
-    const double re = fma(a.x, c.x, -(a.y * c.y));
-    const double im = fma(a.x, c.y, a.y * c.x);
-    return make_float2(static_cast<float>(re), static_cast<float>(im));
+// B[i] = w_M^i (i < 2^hbits): the product is formed in FP64 and rounded once
+// to the working precision.
+__device__ __forceinline__ float2 round_to(double2 w, float2*) {
+    return make_float2(static_cast<float>(w.x), static_cast<float>(w.y));
+}
+__device__ __forceinline__ double2 round_to(double2 w, double2*) { return w; }
+template <class V>
+__device__ __forceinline__ V cvt_tw(double2 w) { return round_to(w, static_cast<V*>(nullptr)); }
+
+template <class V>
+__device__ __forceinline__ V twiddle_2level(const double2* __restrict__ ta, const double2* __restrict__ tb,
+                                           int64_t e, int hbits) {
+    return cvt_tw<V>(twiddle_2level64(ta, tb, e, hbits));
 }
 
 }  // namespace fftk

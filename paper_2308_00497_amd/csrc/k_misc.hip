@@ -7,8 +7,9 @@ namespace fftk {
 // The twiddle diagonal D^N_M of Eq. 1 (Table 1's TwiddleCoe): entries
 // w_M^m = exp(-2 pi i m / M).  sincospi takes the exact rational argument 2m/M
 // (M a power of two, m < M), so the only roundings are those of the FP64
-// sine/cosine and the single rounding to float.
-__global__ void k_gen_stage_tw(float2* dst, int log2NS, int log2R) {
+// sine/cosine and, for FP32 tables, the single rounding to float.
+template <class V>
+__global__ void k_gen_stage_tw(V* dst, int log2NS, int log2R) {
     const int64_t count = int64_t(1) << (log2NS + log2R);
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= count) return;
@@ -18,7 +19,7 @@ __global__ void k_gen_stage_tw(float2* dst, int log2NS, int log2R) {
     const double x = ldexp(static_cast<double>(m), 1 - (log2NS + log2R));  // 2m/M, exact
     double s, c;
     sincospi(x, &s, &c);
-    dst[i] = make_float2(static_cast<float>(c), static_cast<float>(-s));
+    dst[i] = cvt_tw<V>(make_double2(c, -s));
 }
 
 __global__ void k_gen_pow64(double2* dst, int log2M, int64_t step, int64_t count) {
@@ -32,12 +33,16 @@ __global__ void k_gen_pow64(double2* dst, int log2M, int64_t step, int64_t count
     dst[i] = make_double2(c, -s);
 }
 
-hipError_t launch_gen_engine_tw(const EngineInfo& e, float2* dst, hipStream_t s) {
+hipError_t launch_gen_engine_tw(const EngineInfo& e, void* dst, int real_bytes, hipStream_t s) {
     for (int st = 1; st < e.nst; ++st) {
         const int64_t count = int64_t(1) << (e.log2ns[st] + e.log2r[st]);
         const unsigned blocks = static_cast<unsigned>((count + 255) / 256);
-        hipLaunchKernelGGL(k_gen_stage_tw, dim3(blocks), dim3(256), 0, s, dst + e.tw_off[st], e.log2ns[st],
-                           e.log2r[st]);
+        if (real_bytes == 8)
+            hipLaunchKernelGGL(k_gen_stage_tw<double2>, dim3(blocks), dim3(256), 0, s,
+                               static_cast<double2*>(dst) + e.tw_off[st], e.log2ns[st], e.log2r[st]);
+        else
+            hipLaunchKernelGGL(k_gen_stage_tw<float2>, dim3(blocks), dim3(256), 0, s,
+                               static_cast<float2*>(dst) + e.tw_off[st], e.log2ns[st], e.log2r[st]);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }

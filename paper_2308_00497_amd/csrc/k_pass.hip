@@ -9,13 +9,13 @@ namespace fftk {
 // first pass: interleaved in (plain or re/im-swapped) or split in, interleaved
 // workspace out; later passes: interleaved workspace in, interleaved (plain or
 // swapped) or split out
-#define FFT_P(l, c)                                                                                     \
-    pass_entry<l, 4, c, true, false, false, false, false>(),                                            \
-        pass_entry<l, 4, c, true, false, false, true, false>(),                                         \
-        pass_entry<l, 4, c, true, true, false, false, false>(),                                         \
-        pass_entry<l, 4, c, false, false, false, false, false>(),                                       \
-        pass_entry<l, 4, c, false, false, false, false, true>(),                                        \
-        pass_entry<l, 4, c, false, false, true, false, false>()
+#define FFT_P(l, c)                                                                                        \
+    pass_entry<float, l, 4, c, true, false, false, false, false>(),                                        \
+        pass_entry<float, l, 4, c, true, false, false, true, false>(),                                     \
+        pass_entry<float, l, 4, c, true, true, false, false, false>(),                                     \
+        pass_entry<float, l, 4, c, false, false, false, false, false>(),                                   \
+        pass_entry<float, l, 4, c, false, false, false, false, true>(),                                    \
+        pass_entry<float, l, 4, c, false, false, true, false, false>()
 
 static const PassKernel kPass[] = {
     FFT_P(6, 4), FFT_P(6, 6), FFT_P(6, 7),

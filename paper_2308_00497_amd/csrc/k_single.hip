@@ -8,9 +8,9 @@ namespace fftk {
 
 // interleaved forward, interleaved inverse (re/im swapped), split (the inverse
 // swaps the caller's pointers instead)
-#define FFT_S1(n, e, w, r)                                                                   \
-    single_entry<n, e, w, false, false, r>(), single_entry<n, e, w, false, true, r>(),       \
-        single_entry<n, e, w, true, false, r>()
+#define FFT_S1(n, e, w, r)                                                                          \
+    single_entry<float, n, e, w, false, false, r>(), single_entry<float, n, e, w, false, true, r>(),   \
+        single_entry<float, n, e, w, true, false, r>()
 #define FFT_S(n, e, w) FFT_S1(n, e, w, false), FFT_S1(n, e, w, true)
 
 static const SingleKernel kSingle[] = {

@@ -11,7 +11,11 @@
 //            w_(Ns L_p)^(r k), transforms and writes
 //            y[(j div Ns) Ns L_p + k + q Ns].  With P = 2 this is the
 //            four-step scheme: Eq. 1 with M = L_1, K = L_2.
-//  k_gen_*   FP64 twiddle generation on the GPU, rounded once to FP32.
+//  k_gen_*   FP64 twiddle generation on the GPU, rounded once to the working
+//            precision.
+//
+// Every kernel is a template on the real type R (float or double); the FP64
+// instances are the same code over double2.
 #pragma once
 
 #include <type_traits>
@@ -27,8 +31,9 @@ namespace fftk {
 
 // dst[k*R + r] = w_(Ns*R)^(r*k), k < Ns, r < R, computed as
 // (cos, -sin)(2 pi m / M) = (cospi, -sinpi)(2m/M) with the exact rational
-// argument 2m/M (M a power of two), then rounded once to float.
-__global__ void k_gen_stage_tw(float2* dst, int log2NS, int log2R);
+// argument 2m/M (M a power of two), then rounded once to V's precision.
+template <class V>
+__global__ void k_gen_stage_tw(V* dst, int log2NS, int log2R);
 
 // dst[i] = w_M^(i*step) in FP64 for i < count.
 __global__ void k_gen_pow64(double2* dst, int log2M, int64_t step, int64_t count);
@@ -52,45 +57,44 @@ struct SingleShape {
 // written with streaming (nontemporal) accesses.  SWAP exchanges the real and
 // imaginary halves of each interleaved element on load and store (the inverse
 // transform; split arrays get the same effect from swapped pointers).
-template <int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG>
+template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG>
 __global__ void __launch_bounds__((SingleShape<LOG2N, LOG2E, WGT>::THREADS))
-k_single(const float* ia, const float* ib, float* oa, float* ob, const float2* __restrict__ tw, int64_t batch) {
+k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw, int64_t batch) {
+    using V = cplx_t<R>;
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
     using SC = typename SH::SC;
     constexpr int E = SC::E, T = SC::T, L = SC::L, G = SH::G;
-    __shared__ float2 lds[SH::LDS];
+    __shared__ V lds[SH::LDS];
 
     const int tid = threadIdx.x;
-    TwReg<SC> twr(tw);
+    TwReg<SC, V> twr(tw);
     if constexpr (TWREG) twr.init(tid % T);
 
     const int64_t groups = (batch + G - 1) / G;
     for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
         // table reads stay inside the loop unless the registers were asked for:
         // the empty asm hides the pointer's loop invariance from the compiler
-        const float2* twl = tw;
+        // thread-derived addresses are recomputed each iteration instead of
+        // being held in registers across the loop: the registers are worth more
+        // as occupancy (N = 4096 fits 4 workgroups per CU this way)
+        const V* twl = tw;
         int tidl = tid;
-        if constexpr (!TWREG) {
-            // also recompute thread-derived addresses each iteration instead of
-            // holding them in registers across the loop (register budget of the
-            // 1024-thread shapes)
-            asm volatile("" : "+s"(twl));
-            asm volatile("" : "+v"(tidl));
-        }
+        asm volatile("" : "+v"(tidl));
+        if constexpr (!TWREG) asm volatile("" : "+s"(twl));
         const int tl = tidl % T, gl = tidl / T;
         const int64_t tr = grp * G + gl;
         const bool active = tr < batch;
         const int64_t base = tr * L + tl;
-        float2 v[E];
+        V v[E];
         if (active) {
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = swap_if<SWAP>(gload_nt<SPLIT>(ia, ib, base + T * m));
         } else {
 #pragma unroll
-            for (int m = 0; m < E; ++m) v[m] = make_float2(0.f, 0.f);
+            for (int m = 0; m < E; ++m) v[m] = c_zero<V>();
         }
         if constexpr (TWREG) Engine<SC, G, SH::GS, false, false, SH::WAVE>::run(v, lds, twr, tidl);
-        else Engine<SC, G, SH::GS, false, false, SH::WAVE>::run(v, lds, TwMem<SC>(twl), tidl);
+        else Engine<SC, G, SH::GS, false, false, SH::WAVE>::run(v, lds, TwMem<SC, V>(twl), tidl);
         if (active) {
 #pragma unroll
             for (int m = 0; m < E; ++m) gstore_nt<SPLIT>(oa, ob, base + T * m, swap_if<SWAP>(v[m]));
@@ -98,15 +102,16 @@ k_single(const float* ia, const float* ib, float* oa, float* ob, const float2* _
     }
 }
 
-template <int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG>
-hipError_t launch_single(const float* ia, const float* ib, float* oa, float* ob, const float2* tw,
-                         int64_t batch, int grid, hipStream_t s) {
+template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG>
+hipError_t launch_single(const void* ia, const void* ib, void* oa, void* ob, const void* tw, int64_t batch, int grid,
+                         hipStream_t s) {
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
     const int64_t groups = (batch + SH::G - 1) / SH::G;
     const int64_t blocks = groups < grid ? groups : grid;
     if (blocks < 1) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_single<LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG>), dim3(static_cast<unsigned>(blocks)),
-                       dim3(SH::THREADS), 0, s, ia, ib, oa, ob, tw, batch);
+    hipLaunchKernelGGL((k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG>), dim3(static_cast<unsigned>(blocks)),
+                       dim3(SH::THREADS), 0, s, static_cast<const R*>(ia), static_cast<const R*>(ib),
+                       static_cast<R*>(oa), static_cast<R*>(ob), static_cast<const cplx_t<R>*>(tw), batch);
     return hipGetLastError();
 }
 
@@ -126,22 +131,23 @@ EngineInfo engine_info() {
     return e;
 }
 
-template <int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG>
+template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG>
 SingleKernel single_entry() {
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
     SingleKernel k{};
+    k.real_bytes = sizeof(R);
     k.log2n = LOG2N;
     k.log2e = SH::SC::LE;
     k.wgt = WGT;
     k.split = SPLIT;
     k.swap = SWAP;
     k.twreg = TWREG;
-    k.fn = &launch_single<LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG>;
-    k.kernel = reinterpret_cast<const void*>(&k_single<LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG>);
+    k.fn = &launch_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG>;
+    k.kernel = reinterpret_cast<const void*>(&k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG>);
     k.eng = engine_info<typename SH::SC>();
     k.threads = SH::THREADS;
     k.per_wg = SH::G;
-    k.lds_bytes = SH::LDS * sizeof(float2);
+    k.lds_bytes = SH::LDS * sizeof(cplx_t<R>);
     return k;
 }
 
@@ -161,19 +167,26 @@ struct PassShape {
 
 // One tile of one pass: C consecutive butterfly columns j0 .. j0+C-1 of the
 // transform starting at element tbase.  Shared by the pass kernel and the
-// ragged persistent kernel.  `lds` holds PassShape::LDS float2; TW supplies the
-// sub-FFT's stage twiddles.  NT selects streaming (nontemporal) data access.
+// ragged persistent kernel.  `lds` holds PassShape::LDS complex elements; TW
+// supplies the sub-FFT's stage twiddles.  NT selects streaming (nontemporal)
+// data access.  R (float or double) is deduced from `ia`.
 //
 // The pass twiddle of input r of column j (k = j mod Ns) is w_M^(r k), M = Ns L.
 // A thread holds r = tp + T m (m < E), so w_M^(r k) = w_M^(tp k) (w_M^(T k))^m:
 // two table lookups per thread and an FP64 running product, rounded once per
-// element (the FP64 recurrence error over E <= 16 steps stays near 1e-15,
-// far below the single rounding to FP32).
+// element to the working precision (the FP64 recurrence error over E <= 16
+// steps stays near 1e-15: far below the rounding to FP32, and within a few
+// units of FP64 rounding for the FP64 instances).
+template <class T> struct nodeduce { using type = T; };
+
 template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN, bool SWAP_OUT,
-          bool NT = false, class TW = TwMem<Sched<LOG2L, LOG2E, false>>>
-__device__ __forceinline__ void pass_tile(const float* ia, const float* ib, float* oa, float* ob, const TW& tw,
-                                          const double2* __restrict__ ta, const double2* __restrict__ tb, int log2N,
-                                          int log2Ns, int hbits, int64_t tbase, int64_t j0, float2* lds, int tid) {
+          bool NT, class TW, class R>
+__device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R>::type* ib,
+                                          typename nodeduce<R>::type* oa, typename nodeduce<R>::type* ob,
+                                          const TW& tw, const double2* __restrict__ ta,
+                                          const double2* __restrict__ tb, int log2N, int log2Ns, int hbits,
+                                          int64_t tbase, int64_t j0, cplx_t<R>* lds, int tid) {
+    using V = cplx_t<R>;
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     using SC = typename SH::SC;
     constexpr int E = SC::E, T = SC::T, C = SH::C;
@@ -182,7 +195,7 @@ __device__ __forceinline__ void pass_tile(const float* ia, const float* ib, floa
     const int64_t NsMask = (int64_t(1) << log2Ns) - 1;
 
     // load: column-fast mapping, C consecutive columns form one contiguous run
-    float2 v[E];
+    V v[E];
     {
         const int c = tid & (C - 1), tp = tid >> LOG2C;
         const int64_t j = j0 + c;
@@ -198,7 +211,7 @@ __device__ __forceinline__ void pass_tile(const float* ia, const float* ib, floa
 #pragma unroll
             for (int m = 0; m < E; ++m) {
                 if (m > 0) w = z_mul(w, step);
-                v[m] = c_mul(v[m], make_float2(static_cast<float>(w.x), static_cast<float>(w.y)));
+                v[m] = c_mul(v[m], cvt_tw<V>(w));
             }
         }
     }
@@ -213,7 +226,7 @@ __device__ __forceinline__ void pass_tile(const float* ia, const float* ib, floa
         const int64_t obase = tbase + (j << LOG2L) + t;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
-            const float2 o = swap_if<SWAP_OUT>(v[m]);
+            const V o = swap_if<SWAP_OUT>(v[m]);
             if constexpr (NT) gstore_nt<SPLIT_OUT>(oa, ob, obase + T * m, o);
             else gstore<SPLIT_OUT>(oa, ob, obase + T * m, o);
         }
@@ -225,7 +238,7 @@ __device__ __forceinline__ void pass_tile(const float* ia, const float* ib, floa
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int64_t q = tp + T * m;
-            const float2 o = swap_if<SWAP_OUT>(v[m]);
+            const V o = swap_if<SWAP_OUT>(v[m]);
             if constexpr (NT) gstore_nt<SPLIT_OUT>(oa, ob, obase + (q << log2Ns), o);
             else gstore<SPLIT_OUT>(oa, ob, obase + (q << log2Ns), o);
         }
@@ -235,20 +248,22 @@ __device__ __forceinline__ void pass_tile(const float* ia, const float* ib, floa
 // Persistent pass kernel: workgroup w takes tiles w, w + grid, ... (mapped
 // so that the tiles one XCD works on are consecutive), with the sub-FFT's stage
 // twiddles held in registers across tiles and streaming data access.
-template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN, bool SWAP_OUT>
+template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN,
+          bool SWAP_OUT>
 __global__ void __launch_bounds__((PassShape<LOG2L, LOG2E, LOG2C>::THREADS))
-k_pass(const float* ia, const float* ib, float* oa, float* ob, const float2* __restrict__ tw,
-       const double2* __restrict__ ta, const double2* __restrict__ tb, int log2N, int log2Ns, int hbits,
-       int64_t tiles) {
+k_pass(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw, const double2* __restrict__ ta,
+       const double2* __restrict__ tb, int log2N, int log2Ns, int hbits, int64_t tiles) {
+    using V = cplx_t<R>;
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     using SC = typename SH::SC;
     using ENG = Engine<SC, SH::C, SH::GS, true, !FIRST, false>;
     // stage twiddles in registers unless the workgroup is so large (1024
-    // threads: at most 128 registers per lane) that they would spill
-    constexpr bool REGTW = SH::THREADS <= 512;
-    __shared__ float2 lds[SH::LDS];
+    // threads: at most 128 registers per lane) that they would spill, or the
+    // elements are FP64 (twice the registers per entry)
+    constexpr bool REGTW = SH::THREADS <= 512 && sizeof(R) == 4;
+    __shared__ V lds[SH::LDS];
     const int tid = threadIdx.x;
-    TwReg<SC> twr(tw);
+    TwReg<SC, V> twr(tw);
     if constexpr (REGTW) twr.template init_engine<ENG>(tid);
     const int log2TilesPerT = log2N - LOG2L - LOG2C;  // tiles per transform (power of two)
     const int64_t slots = static_cast<int64_t>(gridDim.x);
@@ -264,30 +279,32 @@ k_pass(const float* ia, const float* ib, float* oa, float* ob, const float2* __r
                 ia, ib, oa, ob, twr, ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl);
         else
             pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT, true>(
-                ia, ib, oa, ob, TwMem<SC>(tw), ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl);
+                ia, ib, oa, ob, TwMem<SC, V>(tw), ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl);
     }
 }
 
-template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN, bool SWAP_OUT>
-hipError_t launch_pass(const float* ia, const float* ib, float* oa, float* ob, const float2* tw,
-                       const double2* ta, const double2* tb, int log2N, int log2Ns, int hbits,
-                       int64_t batch, int grid, hipStream_t s) {
+template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN,
+          bool SWAP_OUT>
+hipError_t launch_pass(const void* ia, const void* ib, void* oa, void* ob, const void* tw, const double2* ta,
+                       const double2* tb, int log2N, int log2Ns, int hbits, int64_t batch, int grid, hipStream_t s) {
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     if (log2N < LOG2L + LOG2C) return hipErrorInvalidConfiguration;
     const int64_t tiles = (int64_t(1) << (log2N - LOG2L - LOG2C)) * batch;
     const int64_t blocks = tiles < grid ? tiles : grid;
     if (blocks < 1) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_pass<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>),
-                       dim3(static_cast<unsigned>(blocks)), dim3(SH::THREADS), 0, s, ia, ib, oa, ob, tw, ta, tb,
-                       log2N, log2Ns, hbits, tiles);
+    hipLaunchKernelGGL((k_pass<R, LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>),
+                       dim3(static_cast<unsigned>(blocks)), dim3(SH::THREADS), 0, s, static_cast<const R*>(ia),
+                       static_cast<const R*>(ib), static_cast<R*>(oa), static_cast<R*>(ob),
+                       static_cast<const cplx_t<R>*>(tw), ta, tb, log2N, log2Ns, hbits, tiles);
     return hipGetLastError();
 }
 
-template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN = false,
+template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN = false,
           bool SWAP_OUT = false>
 PassKernel pass_entry() {
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     PassKernel k{};
+    k.real_bytes = sizeof(R);
     k.log2l = LOG2L;
     k.log2e = SH::SC::LE;
     k.log2c = LOG2C;
@@ -296,11 +313,12 @@ PassKernel pass_entry() {
     k.split_out = SPLIT_OUT;
     k.swap_in = SWAP_IN;
     k.swap_out = SWAP_OUT;
-    k.fn = &launch_pass<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>;
-    k.kernel = reinterpret_cast<const void*>(&k_pass<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>);
+    k.fn = &launch_pass<R, LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>;
+    k.kernel =
+        reinterpret_cast<const void*>(&k_pass<R, LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>);
     k.eng = engine_info<typename SH::SC>();
     k.threads = SH::THREADS;
-    k.lds_bytes = SH::LDS * sizeof(float2);
+    k.lds_bytes = SH::LDS * sizeof(cplx_t<R>);
     return k;
 }
 

@@ -78,9 +78,9 @@ bool Decomp::parse(const std::string& s, Decomp* out) {
     return false;
 }
 
-const SingleKernel* find_single(int log2n, int log2e, int wgt, bool split, bool swap, bool twreg) {
+const SingleKernel* find_single(int rb, int log2n, int log2e, int wgt, bool split, bool swap, bool twreg) {
     int cnt = 0;
-    const SingleKernel* t = single_kernels(&cnt);
+    const SingleKernel* t = rb == 8 ? single_kernels64(&cnt) : single_kernels(&cnt);
     const int le = log2e < log2n ? log2e : log2n;
     for (int i = 0; i < cnt; ++i)
         if (t[i].log2n == log2n && t[i].log2e == le && t[i].wgt == wgt && t[i].split == split && t[i].swap == swap &&
@@ -89,10 +89,10 @@ const SingleKernel* find_single(int log2n, int log2e, int wgt, bool split, bool 
     return nullptr;
 }
 
-const PassKernel* find_pass(int log2l, int log2c, bool first, bool split_in, bool split_out, bool swap_in,
+const PassKernel* find_pass(int rb, int log2l, int log2c, bool first, bool split_in, bool split_out, bool swap_in,
                             bool swap_out) {
     int cnt = 0;
-    const PassKernel* t = pass_kernels(&cnt);
+    const PassKernel* t = rb == 8 ? pass_kernels64(&cnt) : pass_kernels(&cnt);
     for (int i = 0; i < cnt; ++i)
         if (t[i].log2l == log2l && t[i].log2c == log2c && t[i].first == first && t[i].split_in == split_in &&
             t[i].split_out == split_out && t[i].swap_in == swap_in && t[i].swap_out == swap_out)
@@ -100,49 +100,52 @@ const PassKernel* find_pass(int log2l, int log2c, bool first, bool split_in, boo
     return nullptr;
 }
 
-const PassKernel* pass_kernel_for(int log2l, int log2c, size_t p, size_t P, bool split, bool inverse) {
+const PassKernel* pass_kernel_for(int rb, int log2l, int log2c, size_t p, size_t P, bool split, bool inverse) {
     const bool first = p == 0, last = p + 1 == P;
-    return find_pass(log2l, log2c, first, first && split, last && split, first && inverse && !split,
+    return find_pass(rb, log2l, log2c, first, first && split, last && split, first && inverse && !split,
                      last && inverse && !split);
 }
 
-const SingleKernel* single_kernel_for(int log2n, const Decomp& d, bool split, bool inverse) {
-    return find_single(log2n, d.log2e, d.wgt, split, inverse && !split, d.twreg);
+const SingleKernel* single_kernel_for(int rb, int log2n, const Decomp& d, bool split, bool inverse) {
+    return find_single(rb, log2n, d.log2e, d.wgt, split, inverse && !split, d.twreg);
 }
 
-// column tile for a sub-FFT length: the widest compiled one up to 16 columns
-// (128-byte runs of interleaved data), else the narrowest compiled one
-static int default_log2c(int log2l) {
-    int best_le4 = -1, min_any = 99;
+// column tile for a sub-FFT length: the widest compiled one up to 128-byte
+// runs of interleaved data (16 FP32 or 8 FP64 columns), else the narrowest
+// compiled one
+static int default_log2c(int rb, int log2l) {
+    const int cap = rb == 8 ? 3 : 4;
+    int best = -1, min_any = 99;
     int cnt = 0;
-    const PassKernel* t = pass_kernels(&cnt);
+    const PassKernel* t = rb == 8 ? pass_kernels64(&cnt) : pass_kernels(&cnt);
     for (int i = 0; i < cnt; ++i) {
         if (t[i].log2l != log2l) continue;
         const int c = t[i].log2c;
-        if (c <= 4 && c > best_le4) best_le4 = c;
+        if (c <= cap && c > best) best = c;
         if (c < min_any) min_any = c;
     }
-    return best_le4 >= 0 ? best_le4 : (min_any == 99 ? -1 : min_any);
+    return best >= 0 ? best : (min_any == 99 ? -1 : min_any);
 }
 
-static bool pass_chain_available(const std::vector<int>& ls, const std::vector<int>& cs, fft_layout layout) {
+static bool pass_chain_available(const std::vector<int>& ls, const std::vector<int>& cs, fft_layout layout, int rb) {
     const bool split = layout == FFT_LAYOUT_SPLIT;
     const size_t P = ls.size();
     if (P < 2) return false;
     for (size_t p = 0; p < P; ++p)
         for (bool inv : {false, true})
-            if (!pass_kernel_for(ls[p], cs[p], p, P, split, inv)) return false;
+            if (!pass_kernel_for(rb, ls[p], cs[p], p, P, split, inv)) return false;
     return true;
 }
 
-bool decomposition_available(const Decomp& d, int log2n, fft_layout layout) {
+bool decomposition_available(const Decomp& d, int log2n, fft_layout layout, int rb) {
+    if (rb != 4 && rb != 8) return false;
     switch (d.kind) {
         case Decomp::COPY:
             return log2n == 0;
         case Decomp::SINGLE: {
             const bool split = layout == FFT_LAYOUT_SPLIT;
-            return log2n >= 1 && single_kernel_for(log2n, d, split, false) != nullptr &&
-                   single_kernel_for(log2n, d, split, true) != nullptr;
+            return log2n >= 1 && single_kernel_for(rb, log2n, d, split, false) != nullptr &&
+                   single_kernel_for(rb, log2n, d, split, true) != nullptr;
         }
         case Decomp::MULTI: {
             int sum = 0;
@@ -151,7 +154,7 @@ bool decomposition_available(const Decomp& d, int log2n, fft_layout layout) {
             // every pass needs at least 2^log2c columns
             for (size_t p = 0; p < d.log2l.size(); ++p)
                 if (log2n - d.log2l[p] < d.log2c[p]) return false;
-            return pass_chain_available(d.log2l, d.log2c, layout);
+            return pass_chain_available(d.log2l, d.log2c, layout, rb);
         }
     }
     return false;
@@ -164,7 +167,45 @@ static std::vector<int> even_split(int log2n, int parts) {
     return v;
 }
 
-Decomp default_decomposition(int log2n) {
+// FP64 defaults: single-pass up to 2^13, then passes with 128-byte runs
+static Decomp default_decomposition64(int log2n) {
+    static const struct { int log2e, gmul, twreg; } single[14] = {
+        {4, 1, 1}, {4, 8, 1}, {4, 8, 1}, {4, 8, 1}, {3, 8, 1},  // 2^0 .. 2^4
+        {3, 4, 1}, {3, 4, 1}, {3, 2, 1}, {3, 2, 1}, {3, 2, 1},  // 2^5 .. 2^9
+        {3, 2, 1}, {3, 2, 1}, {3, 2, 0}, {3, 1, 0},             // 2^10 .. 2^13
+    };
+    static const char* multi[kMaxLog2N + 1] = {
+        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+        nullptr, nullptr, nullptr, nullptr,
+        "multi:7c5,7c5",          // 2^14
+        "multi:8c4,7c5",          // 2^15
+        "multi:8c4,8c4",          // 2^16
+        "multi:9c3,8c4",          // 2^17
+        "multi:9c3,9c3",          // 2^18
+        "multi:10c3,9c3",         // 2^19
+        "multi:10c3,10c3",        // 2^20
+        "multi:7c5,7c5,7c5",      // 2^21
+        "multi:8c4,7c5,7c5",      // 2^22
+        "multi:8c4,8c4,7c5",      // 2^23
+        "multi:8c4,8c4,8c4",      // 2^24
+    };
+    Decomp d;
+    if (log2n <= 0) {
+        d.kind = Decomp::COPY;
+    } else if (log2n <= 13) {
+        d.kind = Decomp::SINGLE;
+        d.log2e = single[log2n].log2e;
+        d.wgt = 256;
+        d.gmul = single[log2n].gmul;
+        d.twreg = single[log2n].twreg == 1;
+    } else {
+        Decomp::parse(multi[log2n], &d);
+    }
+    return d;
+}
+
+Decomp default_decomposition(int log2n, int rb) {
+    if (rb == 8) return default_decomposition64(log2n);
     Decomp d;
     if (log2n <= 0) {
         d.kind = Decomp::COPY;
@@ -207,11 +248,11 @@ Decomp default_decomposition(int log2n) {
     d = Decomp();
     d.kind = Decomp::MULTI;
     d.log2l = even_split(log2n, parts);
-    for (int l : d.log2l) d.log2c.push_back(default_log2c(l));
+    for (int l : d.log2l) d.log2c.push_back(default_log2c(rb, l));
     return d;
 }
 
-std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout) {
+std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int rb) {
     std::vector<Decomp> out;
     if (log2n <= 0) {
         Decomp d;
@@ -224,7 +265,7 @@ std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout) {
     for (int e : {4, 3})
         for (int w : {256, 64})
             for (int r : {1, 0}) {
-                const SingleKernel* k = find_single(log2n, e, w, false, false, r == 1);
+                const SingleKernel* k = find_single(rb, log2n, e, w, false, false, r == 1);
                 if (!k) continue;
                 bool dup = false;
                 for (auto* o : shapes) dup |= (o == k);
@@ -237,12 +278,12 @@ std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout) {
                     d.wgt = w;
                     d.gmul = g;
                     d.twreg = r == 1;
-                    if (decomposition_available(d, log2n, layout)) out.push_back(d);
+                    if (decomposition_available(d, log2n, layout, rb)) out.push_back(d);
                 }
             }
     // multi-pass chains with 2 or 3 passes, every sub-length and tile compiled
     int cnt = 0;
-    const PassKernel* t = pass_kernels(&cnt);
+    const PassKernel* t = rb == 8 ? pass_kernels64(&cnt) : pass_kernels(&cnt);
     std::vector<std::pair<int, int>> lc;  // distinct (log2l, log2c)
     for (int i = 0; i < cnt; ++i) {
         std::pair<int, int> x(t[i].log2l, t[i].log2c);
@@ -266,7 +307,7 @@ std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout) {
                 // keep sub-lengths non-increasing to bound the search
                 bool sorted = true;
                 for (int p = 1; p < parts; ++p) sorted &= d.log2l[p] <= d.log2l[p - 1];
-                if (sorted && decomposition_available(d, log2n, layout)) out.push_back(d);
+                if (sorted && decomposition_available(d, log2n, layout, rb)) out.push_back(d);
             }
             int p = parts - 1;
             while (p >= 0 && ++idx[p] == lc.size()) idx[p--] = 0;

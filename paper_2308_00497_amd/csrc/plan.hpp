@@ -33,25 +33,29 @@ struct Decomp {
     bool operator==(const Decomp& o) const { return str() == o.str(); }
 };
 
-// single-pass limit and the default (untuned) choice
+// Largest size, and the default (untuned) choice.  `rb` is the bytes of one
+// real number: 4 (FP32) or 8 (FP64).
 constexpr int kMaxLog2N = 24;
-Decomp default_decomposition(int log2n);
+Decomp default_decomposition(int log2n, int rb);
 
 // every decomposition the library can run for log2n (autotuner candidates)
-std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout);
+std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int rb);
 
 // kernel lookup; nullptr when no such instance was compiled
-const SingleKernel* find_single(int log2n, int log2e, int wgt, bool split, bool swap, bool twreg);
-const PassKernel* find_pass(int log2l, int log2c, bool first, bool split_in, bool split_out, bool swap_in,
+const SingleKernel* find_single(int rb, int log2n, int log2e, int wgt, bool split, bool swap, bool twreg);
+const PassKernel* find_pass(int rb, int log2l, int log2c, bool first, bool split_in, bool split_out, bool swap_in,
                             bool swap_out);
 
 // kernel of pass p (of P) for a layout and direction: the inverse swaps re/im
 // (interleaved data in the kernel, split data by exchanging the pointers)
-const PassKernel* pass_kernel_for(int log2l, int log2c, size_t p, size_t P, bool split, bool inverse);
-const SingleKernel* single_kernel_for(int log2n, const Decomp& d, bool split, bool inverse);
+const PassKernel* pass_kernel_for(int rb, int log2l, int log2c, size_t p, size_t P, bool split, bool inverse);
+const SingleKernel* single_kernel_for(int rb, int log2n, const Decomp& d, bool split, bool inverse);
 
 // true when every kernel the decomposition needs exists for this layout
-bool decomposition_available(const Decomp& d, int log2n, fft_layout layout);
+bool decomposition_available(const Decomp& d, int log2n, fft_layout layout, int rb);
+
+// bytes of one real number for a precision (0 if invalid)
+inline int real_bytes_of(fft_precision p) { return p == FFT_PRECISION_FP32 ? 4 : (p == FFT_PRECISION_FP64 ? 8 : 0); }
 
 int ilog2_exact(int64_t v);  // log2 of a power of two, -1 otherwise
 

@@ -1,28 +1,32 @@
 // Ragged batches: transforms of different power-of-two sizes packed back to
-// back, computed by persistent work-queue kernels captured in ONE HIP graph
-// (one host launch for the whole batch).
+// back, computed by persistent kernels captured in ONE HIP graph (one host
+// launch for the whole batch).
 //
-// The work is cut into tiles of (at most) 4096 complex elements, one tile per
-// workgroup visit:
-//   copy tile     up to 256 transforms of size 1
-//   single tile   G = 256/T whole transforms of size N <= 4096 (T = N/16
-//                 threads each), the single-pass Stockham engine
-//   pass tile     C = 4096/L columns of one pass of a transform with N > 4096,
+// The work is cut into tiles of (at most) 8192 complex elements, one tile per
+// visit of a 512-thread workgroup:
+//   copy tile     up to 512 transforms of size 1
+//   single tile   G = 512/T whole transforms of size N <= 8192 (T = N/E
+//                 threads each, E = 8 points per thread up to 2^12, 16 above),
+//                 the single-pass Stockham engine
+//   pass tile     C = 8192/L columns of one pass of a transform with N > 8192,
 //                 split into P = ceil(log2 N / 8) passes of L <= 256 points
 //                 (the multi-pass scheme of Eq. 1 with M, K the pass lengths)
 // Tiles are grouped in levels: level 0 holds every first-pass tile and then
-// every single/copy tile (the small tiles even out the end of the level),
-// level p > 0 the p-th pass tiles.  Each level is one launch of the persistent
-// kernel, whose workgroups take tiles from that level's queue with an atomic
-// counter; the kernel boundary between levels orders pass p - 1 before pass p,
-// so no workgroup ever waits for another.  A small kernel at the head of the
-// graph clears the queue counters.
+// every single/copy tile, level p > 0 the p-th pass tiles.  Each level is one
+// launch of the persistent kernel; the kernel boundary orders pass p - 1
+// before pass p, so no workgroup ever waits for another.  Within a level the
+// tiles are sorted by class and dealt round-robin to the resident workgroups
+// (tile w, w + grid, ...), and a workgroup keeps running one class's code, with
+// that class's stage twiddles in registers, while its next tile is of the same
+// class.  Descriptors carry every offset a tile needs, so a tile's data loads
+// depend on one descriptor read at most.
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.hpp"
@@ -33,23 +37,25 @@ namespace fftk {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kTileLog2 = 12;  // 4096 elements per tile
+constexpr int kThreads = 512;
+constexpr int kTileLog2 = 13;  // 8192 elements per tile
 constexpr int kMinPassLog2 = 5, kMaxPassLog2 = 8;
 
 enum : uint32_t { CODE_COPY = 0, CODE_PASS_FIRST = 16, CODE_PASS_MID = 20, CODE_PASS_LAST = 24 };
 
 struct RaggedTile {
-    uint32_t code;    // CODE_COPY, log2 N (single, 1..12) or CODE_PASS_* + (log2 L - 5)
-    uint32_t first;   // copy/single: index into the item-id list; pass: item index
+    uint32_t code;    // CODE_COPY, log2 N (single, 1..13) or CODE_PASS_* + (log2 L - 5)
+    uint32_t first;   // copy/single: index into the tile-slot offset list
     uint32_t count;   // copy/single: transforms in the tile
     uint32_t col;     // pass: first butterfly column j0
     int32_t log2n, log2ns, hbits;
     uint32_t tw_eng;  // float2 offset of the engine stage table
     uint32_t ta, tb;  // double2 offsets of the pass twiddle tables
     uint32_t src, dst;  // 0 input, 1 workspace A, 2 workspace B, 3 output
-    uint32_t pad[4];
+    int64_t uoff;     // pass: element offset of the transform in the caller's buffers
+    int64_t woff;     // pass: element offset of the transform in the workspaces
 };
+static_assert(sizeof(RaggedTile) == 64, "one cache line per descriptor");
 
 struct RaggedArgs {
     const float* ia;
@@ -60,22 +66,24 @@ struct RaggedArgs {
     float* wsb;
     const RaggedTile* tiles;  // this level's tiles
     uint32_t ntiles;
-    const uint32_t* ids;
-    const int64_t* offs;
-    const int64_t* wsoff;
+    const int64_t* toffs;     // element offsets of the transforms of copy/single tiles
     const float2* tw32;
     const double2* tw64;
-    uint32_t* head;  // this level's queue counter
 };
 
+// points per thread of the single-pass classes: 8 up to 2^12, 16 for 2^13
+// (the shapes measured fastest for the plain kernels)
+constexpr int single_log2e(int log2n) { return log2n <= 12 ? 3 : 4; }
+
 template <int LOG2N>
-using RSingle = SingleShape<LOG2N, 4, kThreads>;
+using RSingle = SingleShape<LOG2N, single_log2e(LOG2N), kThreads>;
 
 template <int LOG2L>
 using RPass = PassShape<LOG2L, 4, kTileLog2 - LOG2L>;
 
 constexpr int lds_max() {
     int m = 1;
+    m = std::max(m, RSingle<13>::LDS);
     m = std::max(m, RSingle<12>::LDS);
     m = std::max(m, RSingle<11>::LDS);
     m = std::max(m, RSingle<5>::LDS);
@@ -87,123 +95,147 @@ constexpr int lds_max() {
 }
 constexpr int kLds = lds_max();
 
+// Tiles are dealt to the persistent workgroups round-robin (tile w, w + grid,
+// ...); the tiles of a level all carry about the same number of elements.
+__device__ __forceinline__ bool same_class(const RaggedArgs& a, uint32_t ti, uint32_t code) {
+    return ti < a.ntiles && a.tiles[ti].code == code;
+}
+
+// Whole transforms of one size class, tile after tile while this workgroup's
+// next tile is of the same class; the stage twiddles (same table for every
+// tile of the class) stay in registers.  Returns the workgroup's first tile of
+// another class (or past the end).
 template <int LOG2N, bool SPLIT, bool SWAP>
-__device__ __forceinline__ void ragged_single(const RaggedArgs& a, const RaggedTile& d, float2* lds, int tid) {
+__device__ __forceinline__ uint32_t run_single(const RaggedArgs& a, uint32_t ti, float2* lds, int tid) {
     using SH = RSingle<LOG2N>;
     using SC = typename SH::SC;
     static_assert(SH::THREADS == kThreads, "single tiles use the whole workgroup");
     constexpr int E = SC::E, T = SC::T;
-    const int t = tid % T, g = tid / T;
-    const bool active = static_cast<uint32_t>(g) < d.count;
-    const int64_t base = (active ? a.offs[a.ids[d.first + g]] : 0) + t;
-    float2 v[E];
+    // all stage twiddles in registers when they are few, else only the last
+    // stage's (the 128-register budget of two 512-thread workgroups per CU)
+    constexpr bool ALLREG = (SC::NST - 1) * E <= 16;
+    using ENG = Engine<SC, SH::G, SH::GS, false, false, SH::WAVE>;
+    const uint32_t code = static_cast<uint32_t>(LOG2N);
+    const float2* tw = a.tw32 + a.tiles[ti].tw_eng;
+    using TWT = typename std::conditional<ALLREG, TwReg<SC>, TwLast<SC>>::type;
+    TWT twr(tw);
+    twr.init(tid % T);
+    do {
+        const RaggedTile d = a.tiles[ti];
+        int tidl = tid;
+        asm volatile("" : "+v"(tidl));
+        const int t = tidl % T, g = tidl / T;
+        const bool active = static_cast<uint32_t>(g) < d.count;
+        const int64_t base = (active ? a.toffs[d.first + g] : 0) + t;
+        float2 v[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m)
-        v[m] = active ? swap_if<SWAP>(gload_nt<SPLIT>(a.ia, a.ib, base + T * m)) : make_float2(0.f, 0.f);
-    if constexpr (SC::NST >= 1) Engine<SC, SH::G, SH::GS, false, false, SH::WAVE>::run(v, lds, a.tw32 + d.tw_eng, tid);
-    if (active) {
+        for (int m = 0; m < E; ++m)
+            v[m] = active ? swap_if<SWAP>(gload_nt<SPLIT>(a.ia, a.ib, base + T * m)) : make_float2(0.f, 0.f);
+        ENG::run(v, lds, twr, tidl);
+        if (active) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) gstore_nt<SPLIT>(a.oa, a.ob, base + T * m, swap_if<SWAP>(v[m]));
-    }
+            for (int m = 0; m < E; ++m) gstore_nt<SPLIT>(a.oa, a.ob, base + T * m, swap_if<SWAP>(v[m]));
+        }
+        ti += gridDim.x;
+    } while (same_class(a, ti, code));
+    return ti;
 }
 
-__device__ __forceinline__ void ragged_copy(const RaggedArgs& a, const RaggedTile& d, bool split, int tid) {
-    // size-1 transforms are the identity in both directions
-    if (static_cast<uint32_t>(tid) >= d.count) return;
-    const int64_t i = a.offs[a.ids[d.first + tid]];
-    if (split) {
-        a.oa[i] = a.ia[i];
-        a.ob[i] = a.ib[i];
-    } else {
-        reinterpret_cast<float2*>(a.oa)[i] = reinterpret_cast<const float2*>(a.ia)[i];
-    }
+// size-1 transforms are the identity in both directions
+template <bool SPLIT>
+__device__ __forceinline__ uint32_t run_copy(const RaggedArgs& a, uint32_t ti, int tid) {
+    do {
+        const RaggedTile d = a.tiles[ti];
+        if (static_cast<uint32_t>(tid) < d.count) {
+            const int64_t i = a.toffs[d.first + tid];
+            if (SPLIT) {
+                a.oa[i] = a.ia[i];
+                a.ob[i] = a.ib[i];
+            } else {
+                reinterpret_cast<float2*>(a.oa)[i] = reinterpret_cast<const float2*>(a.ia)[i];
+            }
+        }
+        ti += gridDim.x;
+    } while (same_class(a, ti, CODE_COPY));
+    return ti;
 }
 
-// pass tile: interleaved workspace between passes, caller layout at the ends
+// Pass tiles of one (pass kind, sub-length) class; the sub-FFT's stage
+// twiddles stay in registers across tiles.  Interleaved workspace between
+// passes, the caller's layout at the ends.
 template <int LOG2L, uint32_t KIND, bool SPLIT, bool SWAP>
-__device__ __forceinline__ void ragged_pass(const RaggedArgs& a, const RaggedTile& d, float2* lds, int tid) {
+__device__ __forceinline__ uint32_t run_pass(const RaggedArgs& a, uint32_t ti, float2* lds, int tid) {
     constexpr int LOG2C = kTileLog2 - LOG2L;
     constexpr bool FIRST = KIND == CODE_PASS_FIRST, LAST = KIND == CODE_PASS_LAST;
-    const int64_t uoff = a.offs[d.first];
-    const int64_t woff = a.wsoff[d.first];
-    // element offsets folded into the base pointers (interleaved: 2 floats each)
-    const int64_t u = SPLIT ? uoff : 2 * uoff;
-    const float* ia = a.ia + u;
-    const float* ib = SPLIT ? a.ib + uoff : nullptr;
-    float* oa = a.oa + u;
-    float* ob = SPLIT ? a.ob + uoff : nullptr;
-    float* wsrc = (d.src == 2 ? a.wsb : a.wsa) + 2 * woff;
-    float* wdst = (d.dst == 2 ? a.wsb : a.wsa) + 2 * woff;
-    const double2* ta = a.tw64 + d.ta;
-    const double2* tb = a.tw64 + d.tb;
-    const TwMem<typename RPass<LOG2L>::SC> tw(a.tw32 + d.tw_eng);
-    if constexpr (FIRST) {
-        pass_tile<LOG2L, 4, LOG2C, true, SPLIT, false, SWAP, false, true>(ia, ib, wdst, nullptr, tw, ta, tb, d.log2n,
-                                                                           d.log2ns, d.hbits, 0, d.col, lds, tid);
-    } else if constexpr (LAST) {
-        pass_tile<LOG2L, 4, LOG2C, false, false, SPLIT, false, SWAP, true>(wsrc, nullptr, oa, ob, tw, ta, tb,
-                                                                            d.log2n, d.log2ns, d.hbits, 0, d.col,
-                                                                            lds, tid);
-    } else {
-        pass_tile<LOG2L, 4, LOG2C, false, false, false, false, false, true>(wsrc, nullptr, wdst, nullptr, tw, ta,
-                                                                             tb, d.log2n, d.log2ns, d.hbits, 0, d.col,
-                                                                             lds, tid);
-    }
-}
-
-template <bool SPLIT, bool SWAP>
-__device__ __forceinline__ void dispatch(const RaggedArgs& a, const RaggedTile& d, float2* lds, int tid) {
-    switch (d.code) {
-        case CODE_COPY: ragged_copy(a, d, SPLIT, tid); break;
-        case 1: ragged_single<1, SPLIT, SWAP>(a, d, lds, tid); break;
-        case 2: ragged_single<2, SPLIT, SWAP>(a, d, lds, tid); break;
-        case 3: ragged_single<3, SPLIT, SWAP>(a, d, lds, tid); break;
-        case 4: ragged_single<4, SPLIT, SWAP>(a, d, lds, tid); break;
-        case 5: ragged_single<5, SPLIT, SWAP>(a, d, lds, tid); break;
-        case 6: ragged_single<6, SPLIT, SWAP>(a, d, lds, tid); break;
-        case 7: ragged_single<7, SPLIT, SWAP>(a, d, lds, tid); break;
-        case 8: ragged_single<8, SPLIT, SWAP>(a, d, lds, tid); break;
-        case 9: ragged_single<9, SPLIT, SWAP>(a, d, lds, tid); break;
-        case 10: ragged_single<10, SPLIT, SWAP>(a, d, lds, tid); break;
-        case 11: ragged_single<11, SPLIT, SWAP>(a, d, lds, tid); break;
-        case 12: ragged_single<12, SPLIT, SWAP>(a, d, lds, tid); break;
-#define FFT_RP(kind)                                                              \
-    case kind + 0: ragged_pass<5, kind, SPLIT, SWAP>(a, d, lds, tid); break;      \
-    case kind + 1: ragged_pass<6, kind, SPLIT, SWAP>(a, d, lds, tid); break;      \
-    case kind + 2: ragged_pass<7, kind, SPLIT, SWAP>(a, d, lds, tid); break;      \
-    case kind + 3: ragged_pass<8, kind, SPLIT, SWAP>(a, d, lds, tid); break;
-        FFT_RP(CODE_PASS_FIRST)
-        FFT_RP(CODE_PASS_MID)
-        FFT_RP(CODE_PASS_LAST)
-#undef FFT_RP
-        default: break;
-    }
+    using SH = RPass<LOG2L>;
+    using SC = typename SH::SC;
+    static_assert(SH::THREADS == kThreads, "pass tiles use the whole workgroup");
+    using ENG = Engine<SC, SH::C, SH::GS, true, !FIRST, false>;
+    const uint32_t code = KIND + static_cast<uint32_t>(LOG2L - kMinPassLog2);
+    // later passes also form FP64 pass twiddles; their stage twiddles come
+    // from the (L1-resident) table to stay inside the register budget
+    using TWT = typename std::conditional<FIRST, TwReg<SC>, TwMem<SC>>::type;
+    TWT twr(a.tw32 + a.tiles[ti].tw_eng);
+    if constexpr (FIRST) twr.template init_engine<ENG>(tid);
+    do {
+        const RaggedTile d = a.tiles[ti];
+        int tidl = tid;
+        asm volatile("" : "+v"(tidl));
+        const int64_t uoff = d.uoff;
+        const int64_t woff = d.woff;
+        // element offsets folded into the base pointers (interleaved: 2 floats each)
+        const int64_t u = SPLIT ? uoff : 2 * uoff;
+        const float* ia = a.ia + u;
+        const float* ib = SPLIT ? a.ib + uoff : nullptr;
+        float* oa = a.oa + u;
+        float* ob = SPLIT ? a.ob + uoff : nullptr;
+        float* wsrc = (d.src == 2 ? a.wsb : a.wsa) + 2 * woff;
+        float* wdst = (d.dst == 2 ? a.wsb : a.wsa) + 2 * woff;
+        const double2* ta = a.tw64 + d.ta;
+        const double2* tb = a.tw64 + d.tb;
+        if constexpr (FIRST) {
+            pass_tile<LOG2L, 4, LOG2C, true, SPLIT, false, SWAP, false, true>(ia, ib, wdst, nullptr, twr, ta, tb,
+                                                                               d.log2n, d.log2ns, d.hbits, 0, d.col,
+                                                                               lds, tidl);
+        } else if constexpr (LAST) {
+            pass_tile<LOG2L, 4, LOG2C, false, false, SPLIT, false, SWAP, true>(wsrc, nullptr, oa, ob, twr, ta, tb,
+                                                                                d.log2n, d.log2ns, d.hbits, 0, d.col,
+                                                                                lds, tidl);
+        } else {
+            pass_tile<LOG2L, 4, LOG2C, false, false, false, false, false, true>(wsrc, nullptr, wdst, nullptr, twr, ta,
+                                                                                 tb, d.log2n, d.log2ns, d.hbits, 0,
+                                                                                 d.col, lds, tidl);
+        }
+        ti += gridDim.x;
+    } while (same_class(a, ti, code));
+    return ti;
 }
 
 template <bool SPLIT, bool SWAP>
 __global__ void __launch_bounds__(kThreads, 4) k_ragged(RaggedArgs a) {
     __shared__ float2 lds[kLds];
-    __shared__ uint32_t s_tile;
     const int tid = threadIdx.x;
-    for (;;) {
-        if (tid == 0) s_tile = __hip_atomic_fetch_add(a.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        const uint32_t ti = s_tile;
-        __syncthreads();  // s_tile is rewritten only after everyone has read it
-        if (ti >= a.ntiles) break;
-        const RaggedTile d = a.tiles[ti];
-        // thread-derived addresses of every code path are recomputed per tile
-        // rather than hoisted out of the loop (they would all stay live)
-        int tidl = tid;
-        asm volatile("" : "+v"(tidl));
-        dispatch<SPLIT, SWAP>(a, d, lds, tidl);
+    uint32_t ti = blockIdx.x;
+    while (ti < a.ntiles) {
+        switch (a.tiles[ti].code) {
+            case CODE_COPY: ti = run_copy<SPLIT>(a, ti, tid); break;
+#define FFT_RS(n) \
+    case n: ti = run_single<n, SPLIT, SWAP>(a, ti, lds, tid); break;
+            FFT_RS(1) FFT_RS(2) FFT_RS(3) FFT_RS(4) FFT_RS(5) FFT_RS(6) FFT_RS(7)
+            FFT_RS(8) FFT_RS(9) FFT_RS(10) FFT_RS(11) FFT_RS(12) FFT_RS(13)
+#undef FFT_RS
+#define FFT_RP(kind)                                                          \
+    case kind + 0: ti = run_pass<5, kind, SPLIT, SWAP>(a, ti, lds, tid); break; \
+    case kind + 1: ti = run_pass<6, kind, SPLIT, SWAP>(a, ti, lds, tid); break; \
+    case kind + 2: ti = run_pass<7, kind, SPLIT, SWAP>(a, ti, lds, tid); break; \
+    case kind + 3: ti = run_pass<8, kind, SPLIT, SWAP>(a, ti, lds, tid); break;
+            FFT_RP(CODE_PASS_FIRST)
+            FFT_RP(CODE_PASS_MID)
+            FFT_RP(CODE_PASS_LAST)
+#undef FFT_RP
+            default: ti += gridDim.x; break;
+        }
     }
-}
-
-// queue counters to zero (a graph node, no memset)
-__global__ void k_ragged_reset(uint32_t* heads, uint32_t n) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) heads[i] = 0;
 }
 
 template <class SC>
@@ -220,12 +252,9 @@ struct RaggedPlan {
     int grid = 0;
     std::vector<RaggedTile> htiles;
     RaggedTile* tiles = nullptr;
-    uint32_t* ids = nullptr;
-    int64_t* offs = nullptr;
-    int64_t* wsoff = nullptr;
+    int64_t* toffs = nullptr;      // offsets of the transforms of copy/single tiles
     float2* tw32 = nullptr;
     double2* tw64 = nullptr;
-    uint32_t* heads = nullptr;     // one queue counter per level
     void* ws_own = nullptr;
     void* ws_user = nullptr;
     size_t ws_half = 0;            // bytes of one workspace region
@@ -259,7 +288,7 @@ void free_all(RaggedPlan* r) {
         if (r->graph[i]) (void)hipGraphDestroy(r->graph[i]);
     }
     if (r->cap) (void)hipStreamDestroy(r->cap);
-    void* bufs[] = {r->tiles, r->ids, r->offs, r->wsoff, r->tw32, r->tw64, r->heads, r->ws_own};
+    void* bufs[] = {r->tiles, r->toffs, r->tw32, r->tw64, r->ws_own};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -284,14 +313,13 @@ void* kernel_for(bool split, bool swap) {
     return swap ? reinterpret_cast<void*>(&k_ragged<false, true>) : reinterpret_cast<void*>(&k_ragged<false, false>);
 }
 
-// Capture the counter reset and one persistent launch per level into a graph.
+// Capture one persistent launch per level into a graph.
 fft_status build_graph(RaggedPlan* r, int variant, std::string* detail) {
     const bool split = r->layout == FFT_LAYOUT_SPLIT;
     const bool swap = variant == 1;
     void* fn = kernel_for(split, swap);
     hipError_t e = hipStreamBeginCapture(r->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_err(e, "graph capture begin", detail);
-    hipLaunchKernelGGL(k_ragged_reset, dim3(1), dim3(64), 0, r->cap, r->heads, static_cast<uint32_t>(r->nlevels));
     for (int l = 0; l < r->nlevels && e == hipSuccess; ++l) {
         RaggedArgs& a = r->args[variant][l];
         void* kparams[] = {&a};
@@ -318,7 +346,7 @@ fft_status build_graph(RaggedPlan* r, int variant, std::string* detail) {
         if (hipGraphKernelNodeGetParams(nd, &kp) != hipSuccess || kp.func != fn || !kp.kernelParams) continue;
         const RaggedArgs* ka = static_cast<const RaggedArgs*>(kp.kernelParams[0]);
         for (int l = 0; l < r->nlevels; ++l)
-            if (ka->tiles == r->args[variant][l].tiles && ka->head == r->args[variant][l].head) r->node[variant][l] = nd;
+            if (ka->tiles == r->args[variant][l].tiles) r->node[variant][l] = nd;
     }
     for (int l = 0; l < r->nlevels; ++l)
         if (!r->node[variant][l]) {
@@ -372,6 +400,7 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
     eng_single[10] = engine_info<RSingle<10>::SC>();
     eng_single[11] = engine_info<RSingle<11>::SC>();
     eng_single[12] = engine_info<RSingle<12>::SC>();
+    eng_single[13] = engine_info<RSingle<13>::SC>();
     EngineInfo eng_pass[kMaxPassLog2 + 1] = {};
     eng_pass[5] = engine_info<RPass<5>::SC>();
     eng_pass[6] = engine_info<RPass<6>::SC>();
@@ -429,7 +458,7 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
 
     // ---- tiles in queue order ------------------------------------------------
     std::vector<RaggedTile>& tiles = r->htiles;
-    std::vector<uint32_t> ids;
+    std::vector<int64_t> toffs;
     // largest transforms first within each phase
     std::stable_sort(multi.begin(), multi.end(), [&](int64_t a, int64_t b) { return lg[a] > lg[b]; });
     auto pass_tiles = [&](size_t p) {
@@ -441,7 +470,7 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
             int log2ns = 0;
             for (size_t q = 0; q < p; ++q) log2ns += parts[n][q];
             const uint32_t kind = p == 0 ? CODE_PASS_FIRST : (p + 1 == P ? CODE_PASS_LAST : CODE_PASS_MID);
-            const int64_t ntile = int64_t(1) << (n - kTileLog2);  // columns / C = N / 4096
+            const int64_t ntile = int64_t(1) << (n - kTileLog2);  // columns / C = N / 8192
             const int log2c = kTileLog2 - l;
             for (int64_t c = 0; c < ntile; ++c) {
                 RaggedTile t{};
@@ -454,6 +483,8 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
                 t.tw_eng = off_pass[l];
                 t.ta = ptab[n][p].ta;
                 t.tb = ptab[n][p].tb;
+                t.uoff = offs[i];
+                t.woff = wsoff[i];
                 t.src = p == 0 ? 0u : ((p - 1) % 2 == 0 ? 1u : 2u);
                 t.dst = p + 1 == P ? 3u : (p % 2 == 0 ? 1u : 2u);
                 tiles.push_back(t);
@@ -469,12 +500,13 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
         for (int64_t i = 0; i < count; ++i)
             if (lg[i] == n) cls.push_back(static_cast<uint32_t>(i));
         if (cls.empty()) continue;
-        const int T = n <= 4 ? 1 : (1 << (n - 4));
-        const int G = kThreads / T;
+        const int le = std::min(single_log2e(n), n);
+        const int T = 1 << (n - le);  // threads per transform
+        const int G = kThreads / T;   // transforms per tile
         for (size_t s = 0; s < cls.size(); s += G) {
             RaggedTile t{};
             t.code = n == 0 ? CODE_COPY : static_cast<uint32_t>(n);
-            t.first = static_cast<uint32_t>(ids.size() + s);
+            t.first = static_cast<uint32_t>(toffs.size() + s);
             t.count = static_cast<uint32_t>(std::min<size_t>(G, cls.size() - s));
             t.log2n = n;
             t.tw_eng = n >= 1 ? off_single[n] : 0;
@@ -482,7 +514,7 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
             if (n == 0) ++r->ncopy_tiles;
             else ++r->nsingle_tiles;
         }
-        ids.insert(ids.end(), cls.begin(), cls.end());
+        for (uint32_t i : cls) toffs.push_back(offs[i]);
         char buf[48];
         snprintf(buf, sizeof buf, "%s\"2^%d\": %zu", r->classes.empty() ? "" : ", ", n, cls.size());
         r->classes += buf;
@@ -506,12 +538,9 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
     // ---- device state ---------------------------------------------------------
     fft_status st = FFT_OK;
     e = upload(&r->tiles, tiles);
-    if (e == hipSuccess) e = upload(&r->ids, ids);
-    if (e == hipSuccess) e = upload(&r->offs, offs);
-    if (e == hipSuccess) e = upload(&r->wsoff, wsoff);
+    if (e == hipSuccess) e = upload(&r->toffs, toffs);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&r->tw32), std::max<size_t>(2, tw32_n) * sizeof(float2));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&r->tw64), std::max<size_t>(2, tw64_n) * sizeof(double2));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&r->heads), RaggedPlan::kMaxLevels * sizeof(uint32_t));
     r->ws_half = size_t(ws_elems) * sizeof(float2);
     r->ws_regions = max_passes >= 3 ? 2 : (max_passes == 2 ? 1 : 0);
     if (e == hipSuccess && r->ws_half) e = hipMalloc(&r->ws_own, r->ws_half * r->ws_regions);
@@ -522,9 +551,9 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
         delete r;
         return FFT_ERR_ALLOC;
     }
-    for (int n = 1; n <= kTileLog2 && e == hipSuccess; ++n) e = launch_gen_engine_tw(eng_single[n], r->tw32 + off_single[n], nullptr);
+    for (int n = 1; n <= kTileLog2 && e == hipSuccess; ++n) e = launch_gen_engine_tw(eng_single[n], r->tw32 + off_single[n], 4, nullptr);
     for (int l = kMinPassLog2; l <= kMaxPassLog2 && e == hipSuccess; ++l)
-        e = launch_gen_engine_tw(eng_pass[l], r->tw32 + off_pass[l], nullptr);
+        e = launch_gen_engine_tw(eng_pass[l], r->tw32 + off_pass[l], 4, nullptr);
     for (int n = kTileLog2 + 1; n <= kMaxLog2N && e == hipSuccess; ++n)
         for (size_t p = 1; p < ptab[n].size() && e == hipSuccess; ++p) {
             const PassTab& t = ptab[n][p];
@@ -564,12 +593,9 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
             a = RaggedArgs{};
             a.tiles = r->tiles + r->level_begin[l];
             a.ntiles = r->level_begin[l + 1] - r->level_begin[l];
-            a.ids = r->ids;
-            a.offs = r->offs;
-            a.wsoff = r->wsoff;
+            a.toffs = r->toffs;
             a.tw32 = r->tw32;
             a.tw64 = r->tw64;
-            a.head = r->heads + l;
         }
     *out = r;
     return FFT_OK;

@@ -17,17 +17,20 @@ struct EngineInfo {
     int log2e;              // elements per thread
     bool remfirst;          // smaller radix first
     int nst;                // number of stages
-    int tw_size;            // float2 entries of the stage twiddle table
+    int tw_size;            // complex entries of the stage twiddle table
     int log2ns[kMaxStages];
     int log2r[kMaxStages];
     int tw_off[kMaxStages];
 };
 
-// grid = number of persistent workgroups (clamped to the number of groups)
-using single_fn = hipError_t (*)(const float* ia, const float* ib, float* oa, float* ob, const float2* tw,
-                                 int64_t batch, int grid, hipStream_t s);
+// Data pointers are float* / double* and the table float2* / double2* as
+// `real_bytes` says; grid = number of persistent workgroups (clamped to the
+// number of groups).
+using single_fn = hipError_t (*)(const void* ia, const void* ib, void* oa, void* ob, const void* tw, int64_t batch,
+                                 int grid, hipStream_t s);
 
 struct SingleKernel {
+    int real_bytes; // 4 (FP32) or 8 (FP64)
     int log2n;
     int log2e;
     int wgt;        // target threads per workgroup
@@ -43,11 +46,12 @@ struct SingleKernel {
 };
 
 // grid = number of persistent workgroups (clamped to the number of tiles)
-using pass_fn = hipError_t (*)(const float* ia, const float* ib, float* oa, float* ob, const float2* tw,
-                               const double2* ta, const double2* tb, int log2N, int log2Ns, int hbits,
-                               int64_t batch, int grid, hipStream_t s);
+using pass_fn = hipError_t (*)(const void* ia, const void* ib, void* oa, void* ob, const void* tw, const double2* ta,
+                               const double2* tb, int log2N, int log2Ns, int hbits, int64_t batch, int grid,
+                               hipStream_t s);
 
 struct PassKernel {
+    int real_bytes; // 4 (FP32) or 8 (FP64)
     int log2l;
     int log2e;
     int log2c;      // columns per workgroup
@@ -63,15 +67,18 @@ struct PassKernel {
     size_t lds_bytes;
 };
 
-// tables defined in the kernel translation units
+// tables defined in the kernel translation units (FP32 and FP64 instances)
 const SingleKernel* single_kernels(int* count);
 const PassKernel* pass_kernels(int* count);
+const SingleKernel* single_kernels64(int* count);
+const PassKernel* pass_kernels64(int* count);
 
 // plain streaming copy (16-byte accesses), bytes % 16 == 0
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 
-// twiddle generation launches
-hipError_t launch_gen_engine_tw(const EngineInfo& e, float2* dst, hipStream_t s);
+// twiddle generation launches; the stage table holds float2 (real_bytes 4) or
+// double2 (real_bytes 8) entries
+hipError_t launch_gen_engine_tw(const EngineInfo& e, void* dst, int real_bytes, hipStream_t s);
 hipError_t launch_gen_pow64(double2* dst, int log2M, int64_t step, int64_t count, hipStream_t s);
 
 }  // namespace fftk

@@ -6,8 +6,13 @@ import numpy as np
 import oracle
 import workloads
 
-# per-transform relative L2 bound against the FP64 oracle
+# per-transform relative L2 bound against the FP64 oracle: FP32 path
 TOL = 1e-5
+# FP64 path: the rounding error of a radix-2^k FFT grows like eps * log2 N
+# (eps = 2^-53); at N = 2^24 with a few units of twiddle error that is
+# ~1e-14, so 1e-13 leaves headroom while an FP32-rounded twiddle or value
+# anywhere (~1e-7) fails it by six orders of magnitude
+TOL64 = 1e-13
 SIGN = {"forward": -1, "inverse": +1}
 
 
@@ -28,7 +33,7 @@ def from_device(y, layout: str) -> np.ndarray:
 
 
 def widen(re: np.ndarray, im: np.ndarray) -> np.ndarray:
-    """The float32 input, widened exactly to complex128."""
+    """The float32 (or float64) input, widened exactly to complex128."""
     return re.astype(np.float64) + 1j * im.astype(np.float64)
 
 

@@ -82,6 +82,21 @@ def test_explicit_decomposition_validation(lib):
     assert lib.fft_plan_create_explicit(ctypes.byref(h), 4096, 1, 0, -1, None) == 3
 
 
+def test_create_ex_validation(lib):
+    """Precision argument: unknown values are rejected; FP64 has its own kernel
+    set (single-pass up to 2^13, 8-column pass tiles), checked before any HIP call."""
+    h = ctypes.c_void_p()
+    ex = lib.fft_plan_create_ex
+    assert ex(ctypes.byref(h), 4096, 1, 0, -1, 2, None) == 2
+    assert ex(ctypes.byref(h), 4096, 1, 0, -1, -1, b"single:e4:w256:g2:r1") == 2
+    assert ex(ctypes.byref(h), 100, 1, 0, -1, 1, None) == 1
+    assert ex(ctypes.byref(h), 1 << 14, 1, 0, -1, 1, b"single:e4:w256:g8:r0") == 7   # FP64 LDS limit
+    assert ex(ctypes.byref(h), 1 << 13, 1, 0, -1, 1, b"single:e3:w256:g1:r1") == 7   # spills: not compiled
+    assert ex(ctypes.byref(h), 1 << 24, 1, 0, -1, 1, b"multi:12c2,12c2") == 7        # FP64 tile too wide
+    assert ex(ctypes.byref(h), 1 << 24, 1, 0, -1, 0, b"multi:12c2,12c2x") == 2
+    assert ex(None, 64, 1, 0, -1, 1, None) == 3
+
+
 def test_ragged_validation(lib):
     h = ctypes.c_void_p()
     arr = (ctypes.c_int64 * 3)(64, 100, 256)
@@ -108,28 +123,31 @@ def test_copy_validation(lib):
     assert lib.fft_copy_device(16, 32, 64, None) == 2   # overlap
 
 
+@pytest.mark.parametrize("precision,single_max", [("fp32", 14), ("fp64", 13)])
 @pytest.mark.parametrize("log2n", range(0, 25))
-def test_default_decomposition_covers_every_size(fftlib, log2n):
+def test_default_decomposition_covers_every_size(fftlib, log2n, precision, single_max):
     for layout in ("interleaved", "split"):
-        q = fftlib.query_decomposition(1 << log2n, layout)
+        q = fftlib.query_decomposition(1 << log2n, layout, precision)
         assert q["available"], q
+        assert q["precision"] == precision
         assert q["default"] in q["candidates"]
         if log2n == 0:
             assert q["default"] == "copy"
-        elif log2n <= 14:
+        elif log2n <= single_max:
             assert q["default"].startswith("single:")
         else:
             parts = q["default"].split(":")[1].split(",")
             assert sum(int(p.split("c")[0]) for p in parts) == log2n
 
 
-def test_query_rejects_bad_size(lib):
+def test_query_rejects_bad_args(lib):
     buf = ctypes.create_string_buffer(256)
-    assert lib.fft_query_decomposition(12, 0, buf, 256) == 1
-    assert lib.fft_query_decomposition(16, 9, buf, 256) == 2
+    assert lib.fft_query_decomposition(12, 0, 0, buf, 256) == 1
+    assert lib.fft_query_decomposition(16, 9, 0, buf, 256) == 2
+    assert lib.fft_query_decomposition(16, 0, 7, buf, 256) == 2
 
 
 def test_query_truncates(lib):
     buf = ctypes.create_string_buffer(8)
-    assert lib.fft_query_decomposition(1 << 24, 0, buf, 8) == 0
+    assert lib.fft_query_decomposition(1 << 24, 0, 0, buf, 8) == 0
     assert len(buf.value) == 7

@@ -266,3 +266,14 @@ def test_alloc_failure_is_reported():
     lines = r.stdout.split("\n")
     assert lines[0] == "5 None", r.stdout + r.stderr
     assert lines[1] == "0 True", r.stdout + r.stderr
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096, 4096 * 3 + 48, 1 << 24])
+def test_copy_device(fftlib, nbytes):
+    """The streaming copy entry point (the benchmark's HBM ceiling) copies exactly."""
+    src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros(nbytes + 16, dtype=torch.uint8, device="cuda")
+    fftlib.copy_device(src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:nbytes], src)
+    assert int(dst[nbytes:].sum()) == 0

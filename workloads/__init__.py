@@ -3,7 +3,8 @@
 This module holds random-number draws and array shaping only: no transform
 arithmetic.  Every generator uses numpy's PCG64 (``default_rng(seed)``), draws
 in float64 and rounds once to float32, which is what the GPU consumes; the
-oracle later widens those float32 values back to float64 exactly.
+oracle later widens those float32 values back to float64 exactly.  The FP64
+path takes the float64 draws as they are (``dtype=np.float64``).
 
 The five workloads (sizes, distributions and seeds):
   c1  N=1024, batch 16, split, re/im ~ U[-1, 1), seed 1
@@ -21,19 +22,19 @@ import numpy as np
 SEEDS = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c5": 5}
 
 
-def uniform_complex(shape, seed: int) -> tuple[np.ndarray, np.ndarray]:
-    """(re, im) float32 arrays with entries i.i.d. U[-1, 1)."""
+def uniform_complex(shape, seed: int, dtype=np.float32) -> tuple[np.ndarray, np.ndarray]:
+    """(re, im) arrays (float32 unless dtype says otherwise) with entries i.i.d. U[-1, 1)."""
     rng = np.random.default_rng(seed)
-    re = rng.uniform(-1.0, 1.0, size=shape).astype(np.float32)
-    im = rng.uniform(-1.0, 1.0, size=shape).astype(np.float32)
+    re = rng.uniform(-1.0, 1.0, size=shape).astype(dtype)
+    im = rng.uniform(-1.0, 1.0, size=shape).astype(dtype)
     return re, im
 
 
-def normal_complex(shape, seed: int) -> tuple[np.ndarray, np.ndarray]:
-    """(re, im) float32 arrays with entries i.i.d. N(0, 1)."""
+def normal_complex(shape, seed: int, dtype=np.float32) -> tuple[np.ndarray, np.ndarray]:
+    """(re, im) arrays (float32 unless dtype says otherwise) with entries i.i.d. N(0, 1)."""
     rng = np.random.default_rng(seed)
-    re = rng.standard_normal(size=shape).astype(np.float32)
-    im = rng.standard_normal(size=shape).astype(np.float32)
+    re = rng.standard_normal(size=shape).astype(dtype)
+    im = rng.standard_normal(size=shape).astype(dtype)
     return re, im
 
 
@@ -103,8 +104,8 @@ def c5(seed: int = SEEDS["c5"], batch: int = 1024, n: int = 4096):
 
 
 def interleave(re: np.ndarray, im: np.ndarray) -> np.ndarray:
-    """complex64 array from float32 parts (layout change only)."""
-    out = np.empty(re.shape, dtype=np.complex64)
+    """complex64 (complex128) array from float32 (float64) parts (layout change only)."""
+    out = np.empty(re.shape, dtype=np.complex128 if re.dtype == np.float64 else np.complex64)
     out.real = re
     out.imag = im
     return out
