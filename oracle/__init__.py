@@ -12,7 +12,7 @@ exp(+2 pi i k n / N), neither is scaled.
 
 Parity status: every routine here is pinned by ``tests/test_oracle.py``
 (closed forms, Eq. 1 built from Kronecker products, numpy's pocketfft,
-invariants and finite differences).
+invariants, brute-force sums and finite differences).
 """
 from __future__ import annotations
 
@@ -53,8 +53,11 @@ def load_library(path: str):
     lib.oracle_fft_r2_batch.argtypes = [i64, i64, ctypes.c_int, dp, dp, dp, dp, ctypes.c_int]
     lib.oracle_wpower_loss.argtypes = [i64, dp, dp, dp, dp]
     lib.oracle_wpower_grad.argtypes = [i64, dp, dp, dp, dp, dp]
+    lib.oracle_rfft_batch.argtypes = [i64, i64, dp, dp, dp, ctypes.c_int]
+    lib.oracle_irfft_batch.argtypes = [i64, i64, dp, dp, dp, ctypes.c_int]
     for f in (lib.oracle_dft, lib.oracle_fft_r2, lib.oracle_fft_r2_batch,
-              lib.oracle_wpower_loss, lib.oracle_wpower_grad):
+              lib.oracle_wpower_loss, lib.oracle_wpower_grad, lib.oracle_rfft_batch,
+              lib.oracle_irfft_batch):
         f.restype = ctypes.c_int
     return lib
 
@@ -165,6 +168,33 @@ def wpower_grad(x, w) -> np.ndarray:
     gr, gi = np.empty(n), np.empty(n)
     _check(_load().oracle_wpower_grad(n, _ptr(xr), _ptr(xi), _ptr(w), _ptr(gr), _ptr(gi)), "grad")
     return gr + 1j * gi
+
+
+def rfft(x, threads: int = 1) -> np.ndarray:
+    """Real-to-complex: the forward DFT of each real row of length N (last
+    axis), its non-redundant half k = 0 .. N/2 (N/2 + 1 values per row)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n = x.shape[-1]
+    batch = x.size // n if n else 0
+    h = n // 2 + 1
+    yr = np.empty(x.shape[:-1] + (h,))
+    yi = np.empty_like(yr)
+    _check(_load().oracle_rfft_batch(n, batch, _ptr(x), _ptr(yr), _ptr(yi), threads), "rfft")
+    return yr + 1j * yi
+
+
+def irfft(x, n: int, threads: int = 1) -> np.ndarray:
+    """Complex-to-real: rows of N/2 + 1 values (last axis) -> the real part of
+    the unnormalised inverse DFT of their Hermitian extension, N reals per row
+    (irfft(rfft(x), N) = N x)."""
+    xr, xi = _split(x)
+    h = n // 2 + 1
+    if xr.shape[-1] != h:
+        raise ValueError(f"expected rows of {h} values for n = {n}")
+    batch = xr.size // h
+    y = np.empty(xr.shape[:-1] + (n,))
+    _check(_load().oracle_irfft_batch(n, batch, _ptr(xr), _ptr(xi), _ptr(y), threads), "irfft")
+    return y
 
 
 def rel_l2(y, ref) -> float:

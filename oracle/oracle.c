@@ -24,6 +24,11 @@
  *   oracle_fft_r2_batch the same over a batch, optionally on several threads.
  *   oracle_wpower_loss  L = sum_k w_k |(F x)_k|^2 (the differentiable workload).
  *   oracle_wpower_grad  dL/dRe(x) + i dL/dIm(x) = 2 F^H (w .* F x).
+ *   oracle_rfft_batch   the DFT of real sequences, its non-redundant half
+ *                       k = 0 .. N/2 (real-to-complex).
+ *   oracle_irfft_batch  the unnormalised inverse DFT of the Hermitian
+ *                       extension of such a half, real part
+ *                       (complex-to-real).
  *
  * Error behaviour: every routine returns 0 on success, -1 on a bad argument
  * (N not positive, N not a power of two where one is required, sign not +-1)
@@ -271,5 +276,84 @@ int oracle_wpower_grad(int64_t n, const double *xr, const double *xi,
     }
     free(yr);
     free(yi);
+    return rc;
+}
+
+/* ---- real sequences: the non-redundant half ---------------------------- */
+
+/* Real-to-complex.  For real x of length n the DFT satisfies
+ * X[n - k] = conj(X[k]), so X[0 .. n/2] carries all of it.  This computes
+ * exactly those n/2 + 1 values of the forward DFT of (x, 0): the complex
+ * transform of the real row with a zero imaginary part, truncated.  Output
+ * row b starts at b * (n/2 + 1). */
+int oracle_rfft_batch(int64_t n, int64_t batch, const double *x, double *yr,
+                      double *yi, int nthreads)
+{
+    if (!is_pow2(n) || batch < 0)
+        return -1;
+    if (batch == 0)
+        return 0;
+    const int64_t h = n / 2 + 1;
+    const size_t total = (size_t)n * (size_t)batch;
+    double *zi = (double *)calloc(total, sizeof(double));
+    double *fr = (double *)malloc(total * sizeof(double));
+    double *fi = (double *)malloc(total * sizeof(double));
+    int rc = -2;
+    if (zi && fr && fi)
+        rc = oracle_fft_r2_batch(n, batch, -1, x, zi, fr, fi, nthreads);
+    if (rc == 0) {
+        for (int64_t b = 0; b < batch; ++b) {
+            for (int64_t k = 0; k < h; ++k) {
+                yr[b * h + k] = fr[b * n + k];
+                yi[b * h + k] = fi[b * n + k];
+            }
+        }
+    }
+    free(zi);
+    free(fr);
+    free(fi);
+    return rc;
+}
+
+/* Complex-to-real.  Input rows X[0 .. n/2] (n/2 + 1 values each).  The
+ * Hermitian extension is Xe[k] = X[k] for k <= n/2 and conj(X[n - k]) for
+ * k > n/2; the output is the real part of its unnormalised inverse DFT,
+ *     y[m] = Re sum_{k<n} Xe[k] exp(+2 pi i k m / n),
+ * so that C2R(R2C(x)) = n x.  Imaginary parts of X[0] and X[n/2] drop out
+ * of the real part. */
+int oracle_irfft_batch(int64_t n, int64_t batch, const double *xr,
+                       const double *xi, double *y, int nthreads)
+{
+    if (!is_pow2(n) || batch < 0)
+        return -1;
+    if (batch == 0)
+        return 0;
+    const int64_t h = n / 2 + 1;
+    const size_t total = (size_t)n * (size_t)batch;
+    double *er = (double *)malloc(total * sizeof(double));
+    double *ei = (double *)malloc(total * sizeof(double));
+    double *fr = (double *)malloc(total * sizeof(double));
+    double *fi = (double *)malloc(total * sizeof(double));
+    int rc = -2;
+    if (er && ei && fr && fi) {
+        for (int64_t b = 0; b < batch; ++b) {
+            for (int64_t k = 0; k < n; ++k) {
+                if (k <= n / 2) {
+                    er[b * n + k] = xr[b * h + k];
+                    ei[b * n + k] = xi[b * h + k];
+                } else {
+                    er[b * n + k] = xr[b * h + (n - k)];
+                    ei[b * n + k] = -xi[b * h + (n - k)];
+                }
+            }
+        }
+        rc = oracle_fft_r2_batch(n, batch, 1, er, ei, fr, fi, nthreads);
+        if (rc == 0)
+            memcpy(y, fr, total * sizeof(double));
+    }
+    free(er);
+    free(ei);
+    free(fr);
+    free(fi);
     return rc;
 }

@@ -6,6 +6,8 @@ flipped sign, a dropped term, a wrong or transposed index, a missing twiddle)
 fails at least one of them; ``test_mutants_are_caught`` plants such slips in a
 copy of ``oracle.c`` and checks exactly that.
 """
+import cmath
+import math
 import os
 import shutil
 import tempfile
@@ -384,6 +386,100 @@ def test_rejects_bad_sign():
 
 
 # ---------------------------------------------------------------------------
+# Real sequences: R2C (the half k = 0 .. N/2 of the DFT of a real row) and
+# C2R (real part of the unnormalised inverse DFT of the Hermitian extension)
+# ---------------------------------------------------------------------------
+
+def brute_rfft(x):
+    """Direct sum over n, pure Python loops (tiny sizes only)."""
+    n = len(x)
+    out = []
+    for k in range(n // 2 + 1):
+        acc = 0j
+        for m in range(n):
+            acc += x[m] * cmath.exp(-2j * math.pi * ((k * m) % n) / n)
+        out.append(acc)
+    return np.array(out)
+
+
+def brute_irfft(xh, n):
+    """Direct sum over the Hermitian extension, real part (tiny sizes only)."""
+    ext = [xh[k] if k <= n // 2 else xh[n - k].conjugate() for k in range(n)]
+    out = []
+    for m in range(n):
+        acc = 0j
+        for k in range(n):
+            acc += ext[k] * cmath.exp(2j * math.pi * ((k * m) % n) / n)
+        out.append(acc.real)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 16, 32])
+def test_rfft_brute_force(n):
+    x = np.random.default_rng(900 + n).standard_normal((3, n))
+    got = oracle.rfft(x)
+    assert got.shape == (3, n // 2 + 1)
+    for r in range(3):
+        assert np.abs(got[r] - brute_rfft(list(x[r]))).max() <= 1e-12 * max(n, 1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 16, 32])
+def test_irfft_brute_force(n):
+    """Random half-spectra, with non-zero imaginary parts at DC and Nyquist
+    (they drop out of the real part)."""
+    rng = np.random.default_rng(950 + n)
+    h = n // 2 + 1
+    xh = rng.standard_normal((3, h)) + 1j * rng.standard_normal((3, h))
+    got = oracle.irfft(xh, n)
+    for r in range(3):
+        assert np.abs(got[r] - brute_irfft(list(xh[r]), n)).max() <= 1e-12 * max(n, 1)
+
+
+@pytest.mark.parametrize("log2n", range(0, 13))
+def test_rfft_against_numpy(log2n):
+    n = 1 << log2n
+    x = np.random.default_rng(1000 + log2n).standard_normal((4, n))
+    ref = np.fft.rfft(x)
+    assert oracle.rel_l2(oracle.rfft(x), ref) <= 1e-14 * max(log2n, 1)
+
+
+@pytest.mark.parametrize("log2n", range(0, 13))
+def test_irfft_against_numpy(log2n):
+    n = 1 << log2n
+    rng = np.random.default_rng(1100 + log2n)
+    xh = rng.standard_normal((4, n // 2 + 1)) + 1j * rng.standard_normal((4, n // 2 + 1))
+    ref = n * np.fft.irfft(xh, n)
+    assert oracle.rel_l2(oracle.irfft(xh, n), ref) <= 1e-14 * max(log2n, 1)
+
+
+@pytest.mark.parametrize("n,f", [(64, 5), (256, 100), (1024, 1), (16, 7)])
+def test_rfft_cosine_and_sine_closed_form(n, f):
+    """cos(2 pi f m / n) -> n/2 at k = f; sin -> -i n/2 at k = f; zero elsewhere."""
+    m = np.arange(n)
+    ph = 2 * np.pi * ((f * m) % n) / n
+    for sig, val in ((np.cos(ph), n / 2), (np.sin(ph), -1j * n / 2)):
+        want = np.zeros(n // 2 + 1, dtype=complex)
+        want[f] = val
+        assert np.abs(oracle.rfft(sig[None])[0] - want).max() <= 1e-12 * n
+
+
+@pytest.mark.parametrize("n", [2, 8, 512])
+def test_rfft_dc_and_nyquist(n):
+    got = oracle.rfft(np.stack([np.ones(n), (-1.0) ** np.arange(n)]))
+    want = np.zeros((2, n // 2 + 1), dtype=complex)
+    want[0, 0] = n
+    want[1, n // 2] += n
+    assert np.abs(got - want).max() <= 1e-12 * n
+    assert np.all(got[:, 0].imag == 0) and np.all(got[:, -1].imag == 0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 64, 4096])
+def test_real_round_trip(n):
+    x = np.random.default_rng(1200 + n).standard_normal((3, n))
+    assert np.abs(oracle.irfft(oracle.rfft(x), n) - n * x).max() <= 1e-12 * n
+
+
+# ---------------------------------------------------------------------------
 # Planted mistakes: every one must be caught by some pin above
 # ---------------------------------------------------------------------------
 
@@ -401,6 +497,15 @@ MUTANTS = {
     "dft_exponent": ("(unsigned __int128)k * (unsigned __int128)j", "(unsigned __int128)(k + j)"),
     # butterfly outputs swapped (transposed halves)
     "r2_halves_swapped": ("yr[k] = er + orr;", "yr[k] = er - orr;"),
+    # C2R: Hermitian extension without the conjugate
+    "irfft_conj_dropped": ("ei[b * n + k] = -xi[b * h + (n - k)];", "ei[b * n + k] = xi[b * h + (n - k)];"),
+    # C2R: mirrored index off by one
+    "irfft_mirror_index": ("er[b * n + k] = xr[b * h + (n - k)];", "er[b * n + k] = xr[b * h + (n - k - 1)];"),
+    # R2C: conjugated output (sign slip on the imaginary part)
+    "rfft_imag_sign": ("yi[b * h + k] = fi[b * n + k];", "yi[b * h + k] = -fi[b * n + k];"),
+    # R2C: inverse exponent
+    "rfft_exponent_sign": ("rc = oracle_fft_r2_batch(n, batch, -1, x, zi, fr, fi, nthreads);",
+                           "rc = oracle_fft_r2_batch(n, batch, 1, x, zi, fr, fi, nthreads);"),
 }
 
 
@@ -415,6 +520,9 @@ def _pins_pass(lib_path) -> bool:
             lambda: test_against_numpy_pocketfft(6),
             lambda: test_cosine_gives_two_spikes(64, 5),
             lambda: test_round_trip_is_n_times_identity(64),
+            lambda: test_rfft_brute_force(16),
+            lambda: test_irfft_brute_force(16),
+            lambda: test_rfft_cosine_and_sine_closed_form(64, 5),
         ]
         for c in checks:
             try:
