@@ -197,6 +197,18 @@ def irfft(x, n: int, threads: int = 1) -> np.ndarray:
     return y
 
 
+def fftn(x, ndim: int, sign: int = FORWARD, threads: int = 1) -> np.ndarray:
+    """Multi-dimensional DFT over the last `ndim` axes,
+        X[k_1..k_d] = sum_{n_1..n_d} x[n_1..n_d] exp(sign 2 pi i sum_j k_j n_j / N_j),
+    evaluated one axis at a time with the 1D transform above (the exponential
+    factorises over the axes, so the d-fold sum is d nested 1D sums)."""
+    y = np.asarray(x, dtype=np.complex128)
+    for ax in range(y.ndim - ndim, y.ndim):
+        moved = np.moveaxis(y, ax, -1)
+        y = np.moveaxis(fft(np.ascontiguousarray(moved), sign, threads), -1, ax)
+    return y
+
+
 def rel_l2(y, ref) -> float:
     """||y - ref||_2 / ||ref||_2 in float64 (0/0 is 0)."""
     y = np.asarray(y, dtype=np.complex128)
