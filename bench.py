@@ -218,8 +218,10 @@ def _time(torch, fn, reps):
 def extras(fftlib, torch, workloads, dev):
     """Supplementary timings on the other workloads (not the headline value):
     the single 2^24 transform, the ragged batch against per-size launches, the
-    autograd forward+backward against the same two kernels called directly, and
-    the FP64 path on the batched shape and on 2^24."""
+    autograd forward+backward against the same two kernels called directly, the
+    FP64 path on the batched shape and on 2^24, the real-input transforms, and
+    the per-operator baseline (the paper's one-kernel-per-operator mapping)
+    against the fused kernel."""
     out = {}
     # --- single large transform, split, noise + 8 cosines ---------------------
     n = 1 << 24
@@ -305,6 +307,39 @@ def extras(fftlib, torch, workloads, dev):
                     "decomposition": d["decomposition"], "passes": passes,
                     "hbm_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 3)}
             del x, y
+    # --- real input: R2C and C2R on 8192 rows of 4096 reals ------------------
+    n, batch = 4096, 8192
+    xr = torch.from_numpy(np.random.default_rng(workloads.SEEDS["c2"]).standard_normal((batch, n))
+                          .astype(np.float32)).to(dev)
+    with fftlib.RealPlan(n, batch, "interleaved", "forward") as pf, \
+            fftlib.RealPlan(n, batch, "interleaved", "inverse") as pi:
+        zc = pf.execute(xr)
+        xb = torch.empty_like(xr)
+        ms_f = _time(torch, lambda: pf.execute(xr, out=zc), 50)
+        ms_i = _time(torch, lambda: pi.execute(zc, out=xb), 50)
+        nbytes = batch * (n * 4 + (n // 2 + 1) * 8)  # real array once, half spectrum once
+        for key, ms, plan in (("r2c", ms_f, pf), ("c2r", ms_i, pi)):
+            gbs = nbytes / (ms * 1e-3) / 1e9
+            out[f"{key}_n4096_b8192_fp32"] = {
+                "ms": round(ms, 4), "gflops": round(plan.nominal_flops / (ms * 1e-3) / 1e9, 1),
+                "decomposition": plan.describe()["decomposition"], "hbm_gbs_algorithmic": round(gbs, 1),
+                "hbm_frac": round(gbs / PEAK_HBM_GBS, 3)}
+    del xr, zc, xb
+    # --- per-operator baseline (Table 1 operators one kernel each) vs fused ---
+    n, batch = 4096, 8192
+    re, im = workloads.c2()
+    z = torch.from_numpy(workloads.interleave(re, im)).to(dev)
+    zo = torch.empty_like(z)
+    base = {}
+    for dec in (None, "ops:r4", "ops:r3", "ops:r2", "ops:r1"):
+        with fftlib.Plan(n, batch, "interleaved", "forward", decomposition=dec) as p:
+            ms = _time(torch, lambda: p.execute(z, out=zo), 10)
+            base[p.describe()["decomposition"] if dec is None else dec] = round(ms, 4)
+    fused = min(v for k, v in base.items() if not k.startswith("ops"))
+    out["per_operator_baseline_4096x8192"] = {
+        "ms": base, "kernels": {f"ops:r{r}": 3 * ((12 + r - 1) // r) - 2 for r in (1, 2, 3, 4)},
+        "fusion_speedup_vs_best_ops": round(min(v for k, v in base.items() if k.startswith("ops")) / fused, 2)}
+    del z, zo
     return out
 
 

@@ -116,6 +116,49 @@ fft_status fft_plan_create_ex(fft_plan *out, int64_t n, int64_t batch,
                               fft_precision precision,
                               const char *decomposition);
 
+/* Real-input plan: `batch` rows of n real values (n a power of two in
+ * [1, 2^24]).  dir FFT_FORWARD is real-to-complex (R2C): row b of the real
+ * input maps to the n/2 + 1 values X[k] = sum_m x[m] exp(-2 pi i k m / n),
+ * k = 0 .. n/2, the half of the DFT of a real sequence that determines the
+ * rest (X[n-k] = conj X[k]).  dir FFT_INVERSE is complex-to-real (C2R): rows
+ * of n/2 + 1 values map to y[m] = Re sum_{k<n} Xe[k] exp(+2 pi i k m / n),
+ * Xe the Hermitian extension (Xe[k] = X[k] for k <= n/2, conj X[n-k] above),
+ * unnormalised, so C2R(R2C(x)) = n x; the imaginary parts of X[0] and X[n/2]
+ * do not contribute.  Computed through the complex transform of length n/2
+ * (Eq. 1 with K = 2 splits x into even and odd samples, which form one
+ * complex sequence): single-pass for n/2 up to the complex single-pass limit,
+ * else the half-length multi-pass chain plus one pass that separates (R2C) or
+ * merges (C2R) the two spectra.
+ *   Buffers of fft_execute: R2C in_re_or_z = real array [batch][n], in_im
+ *   ignored; out = complex array(s) [batch][n/2 + 1] in `layout`.  C2R in =
+ *   complex array(s) [batch][n/2 + 1], out_re_or_z = real array [batch][n],
+ *   out_im ignored.  The real and complex buffers may not overlap (no in-place).
+ *   fft_execute_backward returns FFT_ERR_NOT_SUPPORTED.  fft_plan_sizes
+ *   reports n*batch elements and 2.5 n log2 n flops per row.
+ * `decomposition` is NULL (default) or a decomposition string of the half
+ * length ("copy" for n = 2); n = 1 takes none. */
+fft_status fft_plan_create_real(fft_plan *out, int64_t n, int64_t batch,
+                                fft_layout layout, fft_direction dir,
+                                fft_precision precision,
+                                const char *decomposition);
+
+/* Multi-dimensional plan: `batch` arrays of shape dims[0] x ... x
+ * dims[rank-1] (row-major, the last axis contiguous; rank 1, 2 or 3; every
+ * dim a power of two, the last up to 2^24, the others up to 2^12), the DFT
+ * over all `rank` axes:
+ *     X[k] = sum_n x[n] exp(-+ 2 pi i sum_j k_j n_j / dims[j]),
+ * unnormalised, in `layout` and `dir` and `precision`.  The exponential
+ * factorises over the axes, so it runs as the batched 1D transform of the last
+ * axis (a plan as from fft_plan_create_ex, in -> out) followed by one pass per
+ * other axis, in place on the output, each a DFT down the columns of that
+ * axis's stride.  In-place execution, the adjoint (fft_execute_backward) and a
+ * caller workspace (that of the last-axis plan) work as for 1D plans.
+ * fft_plan_sizes counts batch x prod(dims) elements and 5 M log2 M flops per
+ * array, M = prod(dims).  rank 1 returns an ordinary 1D plan. */
+fft_status fft_plan_create_nd(fft_plan *out, int rank, const int64_t *dims,
+                              int64_t batch, fft_layout layout,
+                              fft_direction dir, fft_precision precision);
+
 /* Apply the plan's transform to `batch` transforms: in -> out.
  * in_re_or_z / out_re_or_z: interleaved array, or the real array (split).
  * in_im / out_im: the imaginary arrays (split), ignored (may be NULL) when

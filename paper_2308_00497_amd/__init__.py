@@ -10,7 +10,11 @@ inverse exp(+2 pi i k n / N), neither scaled.
     Plan(n, batch, layout="interleaved" | "split", direction="forward" | "inverse",
          precision="fp32" | "fp64")
     RaggedPlan(sizes, layout, direction)          (FP32)
+    RealPlan(n, batch, layout, direction, precision)  R2C (forward) / C2R (inverse)
+    PlanND(dims, batch, layout, direction, precision) 2D / 3D transforms
+    fftn(x, ndim), ifftn(x, ndim)   over the last ndim (2 or 3) axes
     fft(x), ifft(x)                 complex64/complex128 tensors or (re, im) float32/float64 tuples
+    rfft(x), irfft(X, n)            real tensors [..., n] <-> complex [..., n/2 + 1]
     FFTFunction.apply(re, im)       differentiable split-layout forward FFT
     fft_autograd(z)                 differentiable complex forward FFT
 """
@@ -24,8 +28,8 @@ import torch
 from ._lib import (FFT_FORWARD, FFT_INVERSE, FFT_LAYOUT_INTERLEAVED, FFT_LAYOUT_SPLIT, FFT_PRECISION_FP32,
                    FFT_PRECISION_FP64, FFTError, check, lib)
 
-__all__ = ["Plan", "RaggedPlan", "fft", "ifft", "FFTFunction", "fft_autograd", "copy_device",
-           "query_decomposition", "FFTError"]
+__all__ = ["Plan", "RaggedPlan", "RealPlan", "PlanND", "fft", "ifft", "rfft", "irfft", "fftn", "ifftn",
+           "FFTFunction", "fft_autograd", "copy_device", "query_decomposition", "FFTError"]
 
 _LAYOUTS = {"interleaved": FFT_LAYOUT_INTERLEAVED, "split": FFT_LAYOUT_SPLIT}
 _DIRS = {"forward": FFT_FORWARD, "inverse": FFT_INVERSE}
@@ -174,6 +178,23 @@ class Plan(_PlanBase):
         self.batch = int(batch)
 
 
+class PlanND(_PlanBase):
+    """`batch` arrays of shape `dims` (rank 1..3, row-major, powers of two; the
+    last axis up to 2^24, the others up to 2^12), transformed over all axes."""
+
+    def __init__(self, dims, batch: int = 1, layout: str = "interleaved", direction: str = "forward",
+                 precision: str = "fp32"):
+        super().__init__(layout, direction, precision)
+        dims = [int(d) for d in dims]
+        arr = (ctypes.c_int64 * len(dims))(*dims)
+        h = ctypes.c_void_p()
+        check(lib.fft_plan_create_nd(ctypes.byref(h), len(dims), arr, int(batch), _LAYOUTS[layout],
+                                     _DIRS[direction], _PRECISIONS[precision]), "fft_plan_create_nd")
+        self._handle = h
+        self.dims = dims
+        self.batch = int(batch)
+
+
 class RaggedPlan(_PlanBase):
     """Transforms of the given power-of-two sizes packed back to back, one launch."""
 
@@ -186,6 +207,79 @@ class RaggedPlan(_PlanBase):
               "fft_plan_create_ragged")
         self._handle = h
         self.sizes_list = sizes
+
+
+class RealPlan(_PlanBase):
+    """`batch` rows of n real values (n a power of two up to 2^24).
+
+    direction "forward" is real-to-complex: real [batch][n] -> complex
+    [batch][n/2 + 1] (X[k] for k = 0 .. n/2); "inverse" is complex-to-real,
+    unnormalised (C2R(R2C(x)) = n x).  `layout` is the complex side's
+    (interleaved complex tensor, or a (re, im) pair).  No backward.
+    """
+
+    def __init__(self, n: int, batch: int = 1, layout: str = "interleaved", direction: str = "forward",
+                 precision: str = "fp32", decomposition: str | None = None):
+        super().__init__(layout, direction, precision)
+        h = ctypes.c_void_p()
+        check(lib.fft_plan_create_real(ctypes.byref(h), int(n), int(batch), _LAYOUTS[layout], _DIRS[direction],
+                                       _PRECISIONS[precision],
+                                       None if decomposition is None else decomposition.encode()),
+              "fft_plan_create_real")
+        self._handle = h
+        self.n = int(n)
+        self.batch = int(batch)
+        self.half = self.n // 2 + 1
+
+    def _check_real(self, t, count):
+        rdt, _ = _DTYPES[self.precision]
+        if t.dtype != rdt or not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"real data must be a contiguous {rdt} CUDA tensor")
+        if t.numel() != count:
+            raise ValueError(f"expected {count} real values, got {t.numel()}")
+
+    def _check_complex(self, x, count):
+        rdt, cdt = _DTYPES[self.precision]
+        if self.split:
+            if not (isinstance(x, (tuple, list)) and len(x) == 2):
+                raise TypeError(f"split layout takes (re, im) {rdt} tensors")
+            for t in x:
+                self._check_real(t, count)
+            return _ptr(x[0]), _ptr(x[1])
+        if x.dtype != cdt or not x.is_cuda or not x.is_contiguous():
+            raise TypeError(f"interleaved data must be a contiguous {cdt} CUDA tensor")
+        if x.numel() != count:
+            raise ValueError(f"expected {count} complex values, got {x.numel()}")
+        return _ptr(x), None
+
+    def execute(self, x, out=None, stream=None):
+        rdt, cdt = _DTYPES[self.precision]
+        nc = self.half * self.batch
+        if self.direction == "forward":
+            self._check_real(x, self.n * self.batch)
+            if out is None:
+                shape = tuple(x.shape[:-1]) + (self.half,)
+                if self.split:
+                    out = (torch.empty(shape, dtype=rdt, device=x.device),
+                           torch.empty(shape, dtype=rdt, device=x.device))
+                else:
+                    out = torch.empty(shape, dtype=cdt, device=x.device)
+            oa, ob = self._check_complex(out, nc)
+            ia, ib = _ptr(x), None
+        else:
+            ia, ib = self._check_complex(x, nc)
+            if out is None:
+                ref = x[0] if self.split else x
+                out = torch.empty(tuple(ref.shape[:-1]) + (self.n,), dtype=rdt, device=ref.device)
+            self._check_real(out, self.n * self.batch)
+            oa, ob = _ptr(out), None
+        check(lib.fft_execute(self._handle, ia, ib, oa, ob, _stream_handle(stream)), "fft_execute")
+        return out
+
+    __call__ = execute
+
+    def backward(self, g, out=None, stream=None):
+        raise FFTError(7, "RealPlan.backward", "real-input plans have no backward")
 
 
 _plan_cache: dict = {}
@@ -213,6 +307,59 @@ def _transform(x, direction: str):
 def fft(x):
     """Forward FFT along the last axis (unnormalised)."""
     return _transform(x, "forward")
+
+
+def _cached_real_plan(n: int, batch: int, direction: str, precision: str) -> RealPlan:
+    key = ("real", n, batch, direction, precision, torch.cuda.current_device())
+    p = _plan_cache.get(key)
+    if p is None:
+        p = RealPlan(n, batch, "interleaved", direction, precision)
+        _plan_cache[key] = p
+    return p
+
+
+def _transform_nd(x, ndim: int, direction: str):
+    if ndim < 1 or ndim > 3:
+        raise ValueError("ndim must be 1, 2 or 3")
+    split = isinstance(x, (tuple, list))
+    ref = x[0] if split else x
+    dims = tuple(int(d) for d in ref.shape[-ndim:])
+    count = 1
+    for d in dims:
+        count *= d
+    key = ("nd", dims, ref.numel() // count, "split" if split else "interleaved", direction,
+           _precision_of(ref.dtype), torch.cuda.current_device())
+    p = _plan_cache.get(key)
+    if p is None:
+        p = PlanND(dims, ref.numel() // count, key[3], direction, key[5])
+        _plan_cache[key] = p
+    return p.execute((x[0].contiguous(), x[1].contiguous()) if split else x.contiguous())
+
+
+def fftn(x, ndim: int = 2):
+    """Forward DFT over the last `ndim` axes (unnormalised)."""
+    return _transform_nd(x, ndim, "forward")
+
+
+def ifftn(x, ndim: int = 2):
+    """Inverse DFT over the last `ndim` axes, unnormalised."""
+    return _transform_nd(x, ndim, "inverse")
+
+
+def rfft(x: torch.Tensor) -> torch.Tensor:
+    """Real-to-complex FFT along the last axis: [..., n] real -> [..., n/2 + 1] complex."""
+    n = x.shape[-1]
+    x = x.contiguous()
+    return _cached_real_plan(n, x.numel() // n, "forward", _precision_of(x.dtype)).execute(x)
+
+
+def irfft(x: torch.Tensor, n: int) -> torch.Tensor:
+    """Complex-to-real along the last axis, unnormalised: [..., n/2 + 1] -> [..., n]
+    (irfft(rfft(x), n) = n x)."""
+    if x.shape[-1] != n // 2 + 1:
+        raise ValueError(f"last axis must hold n/2 + 1 = {n // 2 + 1} values")
+    x = x.contiguous()
+    return _cached_real_plan(n, x.numel() // (n // 2 + 1), "inverse", _precision_of(x.dtype)).execute(x)
 
 
 def ifft(x):

@@ -35,6 +35,8 @@ EXPORTS = [
     "fft_plan_create",
     "fft_plan_create_explicit",
     "fft_plan_create_ex",
+    "fft_plan_create_real",
+    "fft_plan_create_nd",
     "fft_execute",
     "fft_execute_backward",
     "fft_plan_destroy",
@@ -67,6 +69,8 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.fft_plan_create.argtypes = [ctypes.POINTER(vp), i64, i64, ci, ci]
     lib.fft_plan_create_explicit.argtypes = [ctypes.POINTER(vp), i64, i64, ci, ci, ctypes.c_char_p]
     lib.fft_plan_create_ex.argtypes = [ctypes.POINTER(vp), i64, i64, ci, ci, ci, ctypes.c_char_p]
+    lib.fft_plan_create_real.argtypes = [ctypes.POINTER(vp), i64, i64, ci, ci, ci, ctypes.c_char_p]
+    lib.fft_plan_create_nd.argtypes = [ctypes.POINTER(vp), ci, ctypes.POINTER(i64), i64, ci, ci, ci]
     lib.fft_execute.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.fft_execute_backward.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.fft_plan_destroy.argtypes = [vp]

@@ -29,6 +29,10 @@ SOURCES = [
     "k_pass.hip",
     "k_single64.hip",
     "k_pass64.hip",
+    "k_real.hip",
+    "k_real64.hip",
+    "k_ops.hip",
+    "k_nd.hip",
     "k_misc.hip",
     "ragged.hip",
     "plan.cpp",

@@ -60,6 +60,17 @@ struct PassStep {
     int grid; // persistent workgroups: resident per CU x CUs
 };
 
+// One strided axis of a multi-dimensional plan: DFT down the columns of
+// stride 2^log2s, in place on the output.
+struct NdStep {
+    const fftk::StridedKernel* k;      // forward
+    const fftk::StridedKernel* k_inv;  // inverse (interleaved re/im swap)
+    int log2s;
+    int64_t blocks;  // column blocks: batch x the axes before this one
+    size_t twe_off;  // engine stage table (complex entries)
+    int grid;
+};
+
 bool valid_layout(int l) { return l == FFT_LAYOUT_INTERLEAVED || l == FFT_LAYOUT_SPLIT; }
 bool valid_dir(int d) { return d == FFT_FORWARD || d == FFT_INVERSE; }
 
@@ -80,6 +91,8 @@ struct fft_plan_s {
     const fftk::SingleKernel* single = nullptr;      // forward kernel
     const fftk::SingleKernel* single_inv = nullptr;  // inverse kernel
     std::vector<PassStep> steps;
+    std::vector<int> ops_r;        // per-operator baseline: radices (log2), outermost first
+    std::vector<size_t> ops_doff;  // offsets (complex entries) of the Mul diagonals in twe
     void* twe = nullptr;   // engine stage tables (float2 or double2)
     size_t twe_n = 0;
     double2* tw64 = nullptr;
@@ -91,6 +104,20 @@ struct fft_plan_s {
     double flops = 0.0;
     fftk::RaggedPlan* ragged = nullptr;
     std::string source;  // "default" | "cache" | "autotune"
+    // real-input plans: R2C (dir FORWARD) or C2R (dir INVERSE) of n real points
+    // through the half length H = n/2 (log2h); `dec` describes the half length
+    bool real = false;
+    int log2h = 0;
+    const fftk::RealKernel* rk = nullptr;  // single-pass kernel
+    void* twn = nullptr;                   // w_n^k, k < H, in the plan's precision
+    size_t rta_off = 0, rtb_off = 0;       // FP64 tables of w_n (pre/post pass)
+    int rhbits = 0;
+    // multi-dimensional plans: the last axis by `inner` (a 1D plan over
+    // batch x the other axes), every other axis by a column pass in place
+    int rank = 1;
+    int64_t dims[3] = {0, 0, 0};
+    fft_plan_s* inner = nullptr;
+    std::vector<NdStep> nd;
 
     void* ws() const { return ws_user ? ws_user : ws_own; }
     size_t cbytes() const { return 2 * size_t(rb); }  // bytes per complex element
@@ -107,6 +134,14 @@ void free_plan_memory(fft_plan p) {
     p->twe = nullptr;
     p->tw64 = nullptr;
     p->ws_own = nullptr;
+    if (p->twn) (void)hipFree(p->twn);
+    p->twn = nullptr;
+    if (p->inner) {
+        free_plan_memory(p->inner);
+        p->inner->magic = kDeadMagic;
+        delete p->inner;
+        p->inner = nullptr;
+    }
     if (p->ragged) fftk::ragged_destroy(p->ragged);
     p->ragged = nullptr;
 }
@@ -121,9 +156,23 @@ fft_status resolve(fft_plan p, const Decomp& dec) {
     p->twe_n = 0;
     p->tw64_n = 0;
     p->ws_bytes = 0;
+    p->ops_r.clear();
+    p->ops_doff.clear();
     switch (dec.kind) {
         case Decomp::COPY:
             break;
+        case Decomp::OPS: {
+            // one Mul diagonal of n_l entries per level l < L - 1
+            p->ops_r = fftk::ops_radices(p->log2n, dec.log2r);
+            int log2nl = p->log2n;
+            for (size_t l = 0; l + 1 < p->ops_r.size(); ++l) {
+                p->ops_doff.push_back(p->twe_n);
+                p->twe_n += size_t(1) << log2nl;
+                log2nl -= p->ops_r[l];
+            }
+            p->ws_bytes = 2 * size_t(p->n) * size_t(p->batch) * p->cbytes();
+            break;
+        }
         case Decomp::SINGLE:
             p->single = fftk::single_kernel_for(p->rb, p->log2n, dec, split, false);
             p->single_inv = fftk::single_kernel_for(p->rb, p->log2n, dec, split, true);
@@ -170,6 +219,78 @@ fft_status resolve(fft_plan p, const Decomp& dec) {
     return FFT_OK;
 }
 
+// Real plans: the half-length chain (interleaved data; R2C forward, C2R
+// inverse), the fused single-pass kernel, or H = 1 (pre/post pass alone).
+fft_status resolve_real(fft_plan p, const Decomp& dec) {
+    const bool split = p->layout == FFT_LAYOUT_SPLIT;
+    const bool c2r = p->dir == FFT_INVERSE;
+    p->dec = dec;
+    p->rk = nullptr;
+    p->steps.clear();
+    p->twe_n = 0;
+    p->tw64_n = 0;
+    p->ws_bytes = 0;
+    if (p->log2n == 0) return FFT_OK;  // N = 1
+    const int log2nn = p->log2n;      // w_N tables, N = 2H
+    auto add_wn_tables = [&]() {
+        p->rhbits = (log2nn + 1) / 2;
+        p->rta_off = p->tw64_n;
+        p->tw64_n += size_t(1) << (log2nn - p->rhbits);
+        p->rtb_off = p->tw64_n;
+        p->tw64_n += size_t(1) << p->rhbits;
+    };
+    switch (dec.kind) {
+        case Decomp::OPS:
+            return FFT_ERR_NOT_SUPPORTED;
+        case Decomp::COPY:
+            add_wn_tables();
+            break;
+        case Decomp::SINGLE:
+            p->rk = fftk::find_real(p->rb, p->log2h, dec.log2e, dec.wgt, c2r, split, dec.twreg);
+            if (!p->rk) return FFT_ERR_NOT_SUPPORTED;
+            p->twe_n = p->rk->eng.tw_size;
+            break;
+        case Decomp::MULTI: {
+            const size_t P = dec.log2l.size();
+            int log2ns = 0;
+            int prev = c2r ? 1 : 0;  // C2R starts from the pre pass's output in workspace A
+            for (size_t i = 0; i < P; ++i) {
+                PassStep st{};
+                const bool first = i == 0, last = i == P - 1;
+                st.k = fftk::pass_kernel_for(p->rb, dec.log2l[i], dec.log2c[i], i, P, false, c2r);
+                st.k_inv = st.k;
+                if (!st.k) return FFT_ERR_NOT_SUPPORTED;
+                int per_cu = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, st.k->kernel, st.k->threads, 0) !=
+                        hipSuccess ||
+                    per_cu < 1)
+                    per_cu = 1;
+                st.grid = per_cu * p->cus;
+                st.log2ns = log2ns;
+                st.twe_off = p->twe_n;
+                p->twe_n += (st.k->eng.tw_size + 1) & ~size_t(1);
+                if (!first) {
+                    const int log2m = log2ns + dec.log2l[i];
+                    st.hbits = (log2m + 1) / 2;
+                    st.ta_off = p->tw64_n;
+                    p->tw64_n += size_t(1) << (log2m - st.hbits);
+                    st.tb_off = p->tw64_n;
+                    p->tw64_n += size_t(1) << st.hbits;
+                }
+                st.src = prev;
+                st.dst = (c2r && last) ? 3 : (prev == 1 ? 2 : 1);
+                prev = st.dst;
+                p->steps.push_back(st);
+                log2ns += dec.log2l[i];
+            }
+            add_wn_tables();
+            p->ws_bytes = 2 * (size_t(1) << p->log2h) * size_t(p->batch) * p->cbytes();
+            break;
+        }
+    }
+    return FFT_OK;
+}
+
 // Allocate and fill the twiddle tables (FP64 on the GPU, rounded once to the
 // plan's precision).
 fft_status build_tables(fft_plan p, hipStream_t s) {
@@ -191,6 +312,36 @@ fft_status build_tables(fft_plan p, hipStream_t s) {
     if (p->single && p->single->eng.tw_size) {
         e = fftk::launch_gen_engine_tw(p->single->eng, p->twe, p->rb, s);
         if (e != hipSuccess) return fail_hip(e, "twiddle generation");
+    }
+    {
+        int log2nl = p->log2n;
+        for (size_t l = 0; l < p->ops_doff.size(); ++l) {
+            e = fftk::launch_gen_diag(p->rb, static_cast<char*>(p->twe) + p->ops_doff[l] * p->cbytes(), log2nl,
+                                      log2nl - p->ops_r[l], s);
+            if (e != hipSuccess) return fail_hip(e, "diagonal generation");
+            log2nl -= p->ops_r[l];
+        }
+    }
+    if (p->rk) {
+        if (p->rk->eng.tw_size) {
+            e = fftk::launch_gen_engine_tw(p->rk->eng, p->twe, p->rb, s);
+            if (e != hipSuccess) return fail_hip(e, "twiddle generation");
+        }
+        const int64_t h = int64_t(1) << p->log2h;
+        e = dev_malloc(&p->twn, size_t(h) * p->cbytes());
+        if (e != hipSuccess) {
+            p->twn = nullptr;
+            g_detail = "twiddle table allocation failed";
+            return FFT_ERR_ALLOC;
+        }
+        e = fftk::launch_gen_pow_round(p->twn, p->rb, p->log2n, h, s);
+        if (e != hipSuccess) return fail_hip(e, "twiddle generation");
+    }
+    if (p->real && p->rhbits > 0) {
+        e = fftk::launch_gen_pow64(p->tw64 + p->rta_off, p->log2n, int64_t(1) << p->rhbits,
+                                   int64_t(1) << (p->log2n - p->rhbits), s);
+        if (e == hipSuccess) e = fftk::launch_gen_pow64(p->tw64 + p->rtb_off, p->log2n, 1, int64_t(1) << p->rhbits, s);
+        if (e != hipSuccess) return fail_hip(e, "FP64 twiddle generation");
     }
     for (const PassStep& st : p->steps) {
         if (st.k->eng.tw_size) {
@@ -234,8 +385,80 @@ struct DeviceGuard {
 };
 
 // Checks shared by execute and execute_backward (before any HIP call).
+// Real plans: the real array and the complex array(s) must not overlap at all.
+fft_status check_real_buffers(fft_plan p, const void* ia, const void* ib, const void* oa, const void* ob) {
+    const bool split = p->layout == FFT_LAYOUT_SPLIT;
+    const bool c2r = p->dir == FFT_INVERSE;
+    const void* ca = c2r ? ia : oa;  // complex side
+    const void* cb = c2r ? ib : ob;
+    const void* ra = c2r ? oa : ia;  // real side
+    if (!ca || !ra || (split && !cb)) return FFT_ERR_NULL_POINTER;
+    auto mis = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) != 0; };
+    if (mis(ca) || mis(ra) || (split && mis(cb))) return FFT_ERR_MISALIGNED;
+    const size_t hc = (p->n / 2 + 1) * size_t(p->batch);  // complex values per array
+    const size_t rbytes = size_t(p->n) * size_t(p->batch) * size_t(p->rb);
+    const size_t cbytes = split ? hc * size_t(p->rb) : hc * p->cbytes();
+    if (overlaps(uintptr_t(ra), rbytes, uintptr_t(ca), cbytes)) return FFT_ERR_INVALID_ARG;
+    if (split && (overlaps(uintptr_t(ra), rbytes, uintptr_t(cb), cbytes) ||
+                  overlaps(uintptr_t(ca), cbytes, uintptr_t(cb), cbytes)))
+        return FFT_ERR_INVALID_ARG;
+    return FFT_OK;
+}
+
+fft_status run_real(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, hipStream_t s) {
+    const bool split = p->layout == FFT_LAYOUT_SPLIT;
+    const bool c2r = p->dir == FFT_INVERSE;
+    hipError_t e = hipSuccess;
+    if (p->log2n == 0) {
+        e = fftk::launch_real1(p->rb, c2r, split, ia, ib, oa, ob, p->batch, s);
+        return e == hipSuccess ? FFT_OK : fail_hip(e, "real N=1 launch");
+    }
+    const double2* ta = p->tw64 ? p->tw64 + p->rta_off : nullptr;
+    const double2* tb = p->tw64 ? p->tw64 + p->rtb_off : nullptr;
+    switch (p->dec.kind) {
+        case Decomp::OPS:
+            return FFT_ERR_NOT_SUPPORTED;
+        case Decomp::COPY:  // H = 1: the pre/post pass is the whole transform
+            e = c2r ? fftk::launch_c2r_pre(p->rb, split, ia, ib, oa, ta, tb, p->rhbits, 0, p->batch, s)
+                    : fftk::launch_r2c_post(p->rb, split, ia, oa, ob, ta, tb, p->rhbits, 0, p->batch, s);
+            return e == hipSuccess ? FFT_OK : fail_hip(e, "real pre/post launch");
+        case Decomp::SINGLE:
+            e = p->rk->fn(ia, ib, oa, ob, p->twe, p->twn, p->batch, p->dec.gmul * p->cus, s);
+            return e == hipSuccess ? FFT_OK : fail_hip(e, "real single-pass launch");
+        case Decomp::MULTI: {
+            if (!p->ws()) {
+                g_detail = "no workspace";
+                return FFT_ERR_INVALID_ARG;
+            }
+            const size_t half = (size_t(1) << p->log2h) * size_t(p->batch) * p->cbytes();
+            void* ws[3] = {nullptr, p->ws(), static_cast<char*>(p->ws()) + half};
+            if (c2r) {
+                e = fftk::launch_c2r_pre(p->rb, split, ia, ib, ws[1], ta, tb, p->rhbits, p->log2h, p->batch, s);
+                if (e != hipSuccess) return fail_hip(e, "C2R pre-pass launch");
+            }
+            int last = 0;
+            for (const PassStep& st : p->steps) {
+                const void* src = st.src == 0 ? ia : ws[st.src];
+                void* dst = st.dst == 3 ? oa : ws[st.dst];
+                e = st.k->fn(src, nullptr, dst, nullptr, static_cast<const char*>(p->twe) + st.twe_off * p->cbytes(),
+                             p->tw64 + st.ta_off, p->tw64 + st.tb_off, p->log2h, st.log2ns, st.hbits, p->batch,
+                             st.grid, s);
+                if (e != hipSuccess) return fail_hip(e, "pass launch");
+                last = st.dst;
+            }
+            if (!c2r) {
+                e = fftk::launch_r2c_post(p->rb, split, ws[last], oa, ob, ta, tb, p->rhbits, p->log2h, p->batch, s);
+                if (e != hipSuccess) return fail_hip(e, "R2C post-pass launch");
+            }
+            return FFT_OK;
+        }
+    }
+    return FFT_ERR_INVALID_ARG;
+}
+
 fft_status check_buffers(fft_plan p, const void* ia, const void* ib, const void* oa, const void* ob) {
     if (!plan_ok(p)) return FFT_ERR_INVALID_ARG;
+    if (p->real) return check_real_buffers(p, ia, ib, oa, ob);
     const bool split = p->layout == FFT_LAYOUT_SPLIT;
     if (!ia || !oa || (split && (!ib || !ob))) return FFT_ERR_NULL_POINTER;
     auto mis = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) != 0; };
@@ -255,11 +478,39 @@ fft_status check_buffers(fft_plan p, const void* ia, const void* ib, const void*
     return FFT_OK;
 }
 
+fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, void* stream, bool adjoint);
+
+// Multi-dimensional: the last axis (inner 1D plan, in -> out), then the
+// column passes in place on the output, last-but-one axis first.
+fft_status run_nd(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, void* stream, bool adjoint) {
+    fft_status st = run(p->inner, ia, ib, oa, ob, stream, adjoint);
+    if (st != FFT_OK) return st;
+    const bool inverse = (p->dir == FFT_INVERSE) != adjoint;
+    const bool split = p->layout == FFT_LAYOUT_SPLIT;
+    void* a = oa;
+    void* b = ob;
+    if (inverse && split) std::swap(a, b);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (const NdStep& stp : p->nd) {
+        const fftk::StridedKernel* k = inverse && !split ? stp.k_inv : stp.k;
+        const hipError_t e = k->fn(a, b, a, b, static_cast<const char*>(p->twe) + stp.twe_off * p->cbytes(), stp.log2s,
+                                   stp.blocks, stp.grid, s);
+        if (e != hipSuccess) return fail_hip(e, "column pass launch");
+    }
+    return FFT_OK;
+}
+
 fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, void* stream, bool adjoint) {
+    if (plan_ok(p) && p->real && adjoint) {
+        g_detail = "real-input plans have no backward";
+        return FFT_ERR_NOT_SUPPORTED;
+    }
     fft_status st = check_buffers(p, ia, ib, oa, ob);
     if (st != FFT_OK) return st;
     DeviceGuard guard(p->device);
+    if (p->rank > 1) return run_nd(p, ia, ib, oa, ob, stream, adjoint);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->real) return run_real(p, ia, ib, oa, ob, s);
     // forward kernels everywhere; the inverse swaps re and im on the way in and
     // out: split arrays by exchanging the pointers, interleaved data in-kernel
     const bool inverse = (p->dir == FFT_INVERSE) != adjoint;
@@ -286,6 +537,49 @@ fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, v
             e = hipMemcpyAsync(oa, ia, bytes, hipMemcpyDeviceToDevice, s);
             if (e == hipSuccess && split) e = hipMemcpyAsync(ob, ib, bytes, hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) return fail_hip(e, "copy");
+            return FFT_OK;
+        }
+        case Decomp::OPS: {
+            // Permute for l = 0 .. L-2, innermost DFT blocks, then Mul and
+            // FusedMKIV for l = L-2 .. 0; ping-pong through the workspace
+            if (!p->ws()) {
+                g_detail = "no workspace";
+                return FFT_ERR_INVALID_ARG;
+            }
+            const size_t full = size_t(p->n) * size_t(p->batch) * p->cbytes();
+            void* buf[2] = {p->ws(), static_cast<char*>(p->ws()) + full};
+            const int L = static_cast<int>(p->ops_r.size());
+            const int nops = 3 * L - 2;
+            int done = 0, cur = -1;  // cur = -1: the caller's input
+            auto src = [&]() -> const void* { return cur < 0 ? ia : buf[cur]; };
+            auto dst = [&]() -> void* { return done + 1 == nops ? oa : buf[cur < 0 ? 0 : 1 - cur]; };
+            auto step = [&]() { cur = cur < 0 ? 0 : 1 - cur; ++done; };
+            int64_t a = p->batch;
+            int log2nl = p->log2n;
+            for (int l = 0; l + 1 < L; ++l) {
+                e = fftk::launch_op_perm(p->rb, src(), dst(), a, log2nl - p->ops_r[l], p->ops_r[l],
+                                         inverse && done == 0, s);
+                if (e != hipSuccess) return fail_hip(e, "Permute launch");
+                step();
+                a <<= p->ops_r[l];
+                log2nl -= p->ops_r[l];
+            }
+            e = fftk::launch_op_kron(p->rb, p->ops_r[L - 1], src(), dst(), a, 1, inverse && done == 0,
+                                     inverse && done + 1 == nops, s);
+            if (e != hipSuccess) return fail_hip(e, "FusedIKMV launch");
+            step();
+            for (int l = L - 2; l >= 0; --l) {
+                a >>= p->ops_r[l];
+                log2nl += p->ops_r[l];
+                e = fftk::launch_op_mul(p->rb, src(), dst(), static_cast<const char*>(p->twe) + p->ops_doff[l] * p->cbytes(),
+                                        a, log2nl, s);
+                if (e != hipSuccess) return fail_hip(e, "Mul launch");
+                step();
+                e = fftk::launch_op_kron(p->rb, p->ops_r[l], src(), dst(), a, int64_t(1) << (log2nl - p->ops_r[l]),
+                                         false, inverse && done + 1 == nops, s);
+                if (e != hipSuccess) return fail_hip(e, "FusedMKIV launch");
+                step();
+            }
             return FFT_OK;
         }
         case Decomp::SINGLE: {
@@ -346,9 +640,36 @@ std::string describe(fft_plan p) {
         s += "}";
         return s;
     }
+    if (p->rank > 1) {
+        std::string d, cols;
+        for (int i = 0; i < p->rank; ++i) d += (i ? ", " : "") + std::to_string(p->dims[i]);
+        for (size_t i = 0; i < p->nd.size(); ++i) {
+            const NdStep& st = p->nd[i];
+            snprintf(buf, sizeof buf, "%s{\"length\": %d, \"stride\": %lld, \"columns_per_wg\": %d}", i ? ", " : "",
+                     1 << st.k->log2l, (long long)(int64_t(1) << st.log2s), 1 << st.k->log2c);
+            cols += buf;
+        }
+        s += "\"rank\": " + std::to_string(p->rank) + ", \"dims\": [" + d + "], \"last_axis\": " + describe(p->inner) +
+             ", \"column_passes\": [" + cols + "], \"workspace_bytes\": " + std::to_string(p->ws_bytes) + "}";
+        return s;
+    }
+    if (p->real) {
+        snprintf(buf, sizeof buf, "\"real\": \"%s\", \"half_length\": %lld, ", p->dir == FFT_INVERSE ? "c2r" : "r2c",
+                 (long long)(p->log2n ? int64_t(1) << p->log2h : 0));
+        s += buf;
+    }
     snprintf(buf, sizeof buf, "\"decomposition\": \"%s\", \"source\": \"%s\", \"workspace_bytes\": %zu",
-             p->dec.str().c_str(), p->source.c_str(), p->ws_bytes);
+             p->log2n == 0 && p->real ? "n1" : p->dec.str().c_str(), p->source.c_str(), p->ws_bytes);
     s += buf;
+    if (p->rk) {
+        std::string radices;
+        for (int i = 0; i < p->rk->eng.nst; ++i) radices += (i ? "," : "") + std::to_string(1 << p->rk->eng.log2r[i]);
+        snprintf(buf, sizeof buf,
+                 ", \"kernel\": \"real-single\", \"radices\": [%s], \"threads\": %d, \"transforms_per_wg\": %d, "
+                 "\"lds_bytes\": %zu",
+                 radices.c_str(), p->rk->threads, p->rk->per_wg, p->rk->lds_bytes);
+        s += buf;
+    }
     if (p->single) {
         std::string radices;
         for (int i = 0; i < p->single->eng.nst; ++i)
@@ -478,6 +799,158 @@ fft_status fft_plan_create_ex(fft_plan* out, int64_t n, int64_t batch, fft_layou
     return create_impl(out, n, batch, layout, dir, precision, decomposition);
 }
 
+fft_status fft_plan_create_nd(fft_plan* out, int rank, const int64_t* dims, int64_t batch, fft_layout layout,
+                              fft_direction dir, fft_precision precision) {
+    if (!out) return FFT_ERR_NULL_POINTER;
+    *out = nullptr;
+    if (!dims) return FFT_ERR_NULL_POINTER;
+    if (rank < 1 || rank > 3) return FFT_ERR_INVALID_ARG;
+    int log2d[3] = {0, 0, 0};
+    int log2total = 0;
+    for (int i = 0; i < rank; ++i) {
+        log2d[i] = fftk::ilog2_exact(dims[i]);
+        if (log2d[i] < 0) return FFT_ERR_INVALID_SIZE;
+        if (i + 1 < rank && log2d[i] > fftk::kMaxStridedLog2) return FFT_ERR_INVALID_SIZE;
+        if (i + 1 == rank && log2d[i] > fftk::kMaxLog2N) return FFT_ERR_INVALID_SIZE;
+        log2total += log2d[i];
+    }
+    const int rb = fftk::real_bytes_of(precision);
+    if (batch < 1 || !valid_layout(layout) || !valid_dir(dir) || rb == 0) return FFT_ERR_INVALID_ARG;
+    if (log2total > 40 || batch > (int64_t(1) << (40 - log2total))) return FFT_ERR_INVALID_ARG;
+    if (rank == 1) return create_impl(out, dims[0], batch, layout, dir, precision, nullptr);
+    const bool split = layout == FFT_LAYOUT_SPLIT;
+    // kernels of the strided axes (checked before any allocation)
+    std::vector<NdStep> steps;
+    for (int k = rank - 2; k >= 0; --k) {
+        if (log2d[k] == 0) continue;
+        int log2s = 0;
+        for (int j = k + 1; j < rank; ++j) log2s += log2d[j];
+        NdStep st{};
+        st.k = fftk::strided_kernel_for(rb, log2d[k], log2s, split, false);
+        st.k_inv = split ? st.k : fftk::strided_kernel_for(rb, log2d[k], log2s, split, true);
+        if (!st.k || !st.k_inv) return FFT_ERR_NOT_SUPPORTED;
+        st.log2s = log2s;
+        st.blocks = batch;
+        for (int j = 0; j < k; ++j) st.blocks *= dims[j];
+        steps.push_back(st);
+    }
+    fft_plan p = new (std::nothrow) fft_plan_s;
+    if (!p) return FFT_ERR_ALLOC;
+    p->rank = rank;
+    for (int i = 0; i < rank; ++i) p->dims[i] = dims[i];
+    p->n = int64_t(1) << log2total;
+    p->log2n = log2total;
+    p->batch = batch;
+    p->layout = layout;
+    p->dir = dir;
+    p->rb = rb;
+    p->elements = p->n * batch;
+    p->flops = nominal_flops(p->n) * double(batch);
+    p->source = "nd";
+    hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return fail_hip(e, "hipGetDevice");
+    }
+    fft_status st = create_impl(&p->inner, dims[rank - 1], p->elements / dims[rank - 1], layout, dir, precision,
+                                nullptr);
+    if (st == FFT_OK) {
+        for (NdStep& stp : steps) {
+            stp.twe_off = p->twe_n;
+            p->twe_n += (stp.k->eng.tw_size + 1) & ~size_t(1);
+            int per_cu = 1;
+            if (stp.k->kernel &&
+                (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stp.k->kernel, stp.k->threads, 0) != hipSuccess ||
+                 per_cu < 1))
+                per_cu = 1;
+            stp.grid = per_cu * p->cus;
+        }
+        p->nd = steps;
+        if (p->twe_n) {
+            e = dev_malloc(&p->twe, p->twe_n * p->cbytes());
+            if (e != hipSuccess) {
+                p->twe = nullptr;
+                g_detail = "twiddle table allocation failed";
+                st = FFT_ERR_ALLOC;
+            }
+        }
+        for (size_t i = 0; st == FFT_OK && i < p->nd.size(); ++i) {
+            if (!p->nd[i].k->eng.tw_size) continue;
+            e = fftk::launch_gen_engine_tw(p->nd[i].k->eng, static_cast<char*>(p->twe) + p->nd[i].twe_off * p->cbytes(),
+                                           rb, nullptr);
+            if (e != hipSuccess) st = fail_hip(e, "twiddle generation");
+        }
+        if (st == FFT_OK) {
+            e = hipStreamSynchronize(nullptr);
+            if (e != hipSuccess) st = fail_hip(e, "twiddle generation sync");
+        }
+        p->ws_bytes = p->inner ? p->inner->ws_bytes : 0;
+    }
+    if (st != FFT_OK) {
+        free_plan_memory(p);
+        p->magic = kDeadMagic;
+        delete p;
+        return st;
+    }
+    *out = p;
+    return FFT_OK;
+}
+
+fft_status fft_plan_create_real(fft_plan* out, int64_t n, int64_t batch, fft_layout layout, fft_direction dir,
+                                fft_precision precision, const char* decomposition) {
+    if (!out) return FFT_ERR_NULL_POINTER;
+    *out = nullptr;
+    const int log2n = fftk::ilog2_exact(n);
+    if (log2n < 0 || log2n > fftk::kMaxLog2N) return FFT_ERR_INVALID_SIZE;
+    const int rb = fftk::real_bytes_of(precision);
+    if (batch < 1 || !valid_layout(layout) || !valid_dir(dir) || rb == 0) return FFT_ERR_INVALID_ARG;
+    if (batch > (int64_t(1) << 40) / n) return FFT_ERR_INVALID_ARG;
+    const bool c2r = dir == FFT_INVERSE;
+    Decomp dec;
+    if (log2n >= 1) {
+        if (decomposition) {
+            if (!Decomp::parse(decomposition, &dec)) return FFT_ERR_INVALID_ARG;
+            if (!fftk::real_decomposition_available(dec, log2n, layout, rb, c2r)) return FFT_ERR_NOT_SUPPORTED;
+        } else {
+            dec = fftk::default_real_decomposition(log2n, rb);
+            if (!fftk::real_decomposition_available(dec, log2n, layout, rb, c2r)) return FFT_ERR_NOT_SUPPORTED;
+        }
+    } else if (decomposition) {
+        return FFT_ERR_NOT_SUPPORTED;  // N = 1 has no decomposition
+    }
+    fft_plan p = new (std::nothrow) fft_plan_s;
+    if (!p) return FFT_ERR_ALLOC;
+    p->n = n;
+    p->batch = batch;
+    p->log2n = log2n;
+    p->log2h = log2n > 0 ? log2n - 1 : 0;
+    p->layout = layout;
+    p->dir = dir;
+    p->rb = rb;
+    p->real = true;
+    p->elements = n * batch;
+    p->flops = 0.5 * nominal_flops(n) * double(batch);
+    p->source = decomposition ? "explicit" : "default";
+    hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return fail_hip(e, "hipGetDevice");
+    }
+    fft_status st = resolve_real(p, dec);
+    if (st == FFT_OK) st = build_tables(p, nullptr);
+    if (st == FFT_OK) st = alloc_workspace(p);
+    if (st != FFT_OK) {
+        free_plan_memory(p);
+        p->magic = kDeadMagic;
+        delete p;
+        return st;
+    }
+    *out = p;
+    return FFT_OK;
+}
+
 fft_status fft_execute(fft_plan p, const void* in_re_or_z, const void* in_im, void* out_re_or_z, void* out_im,
                        void* stream) {
     return run(p, in_re_or_z, in_im, out_re_or_z, out_im, stream, false);
@@ -551,6 +1024,7 @@ fft_status fft_plan_set_workspace(fft_plan p, void* dev_ptr) {
     if (dev_ptr && (reinterpret_cast<uintptr_t>(dev_ptr) & 15u)) return FFT_ERR_MISALIGNED;
     DeviceGuard guard(p->device);
     if (p->ragged) return fftk::ragged_set_workspace(p->ragged, dev_ptr, &g_detail);
+    if (p->inner) return fft_plan_set_workspace(p->inner, dev_ptr);
     if (dev_ptr) {
         if (p->ws_own) {
             (void)hipDeviceSynchronize();

@@ -203,15 +203,21 @@ template <int GS>
 __device__ __forceinline__ int lds_at(int g, int i) { return g * GS + i + (i >> 4); }
 
 // Synchronisation between stages: a workgroup barrier, or (when every
-// sub-FFT lives inside one wavefront) only a wavefront-scope fence.
+// sub-FFT lives inside one wavefront) only a wavefront-scope fence.  The
+// fences order LDS only: stages exchange data through LDS alone (a thread's
+// global stores go to addresses no other thread of the kernel reads), so
+// global loads issued before a barrier - the next transform's data in the
+// prefetching kernels - stay in flight across it.
 template <bool WAVE>
 __device__ __forceinline__ void stage_sync() {
     if constexpr (WAVE) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
         __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
     } else {
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     }
 }
 

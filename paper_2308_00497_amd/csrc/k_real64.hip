@@ -1,0 +1,24 @@
+// FP64 instances of the single-pass R2C/C2R kernel (half lengths up to 2^13).
+#include "real.hpp"
+
+namespace fftk {
+
+#define FFT_RD1(h, e, r)                                                                                       \
+    real_entry<double, h, e, 256, false, false, r>(), real_entry<double, h, e, 256, false, true, r>(),        \
+        real_entry<double, h, e, 256, true, false, r>(), real_entry<double, h, e, 256, true, true, r>()
+#define FFT_RD(h, e) FFT_RD1(h, e, false), FFT_RD1(h, e, true)
+
+static const RealKernel kReal64[] = {
+    FFT_RD(1, 4), FFT_RD(2, 4), FFT_RD(3, 4), FFT_RD(4, 3), FFT_RD(5, 3), FFT_RD(6, 3), FFT_RD(7, 3),
+    FFT_RD(8, 3), FFT_RD(9, 3), FFT_RD(10, 3), FFT_RD(11, 3), FFT_RD1(12, 3, false), FFT_RD1(13, 3, false),
+};
+
+#undef FFT_RD
+#undef FFT_RD1
+
+const RealKernel* real_kernels64(int* count) {
+    *count = static_cast<int>(sizeof(kReal64) / sizeof(kReal64[0]));
+    return kReal64;
+}
+
+}  // namespace fftk

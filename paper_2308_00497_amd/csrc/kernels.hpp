@@ -56,8 +56,11 @@ struct SingleShape {
 // register-resident twiddles is loaded once per workgroup.  Data is read and
 // written with streaming (nontemporal) accesses.  SWAP exchanges the real and
 // imaginary halves of each interleaved element on load and store (the inverse
-// transform; split arrays get the same effect from swapped pointers).
-template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG>
+// transform; split arrays get the same effect from swapped pointers).  With PF
+// the loads of the workgroup's next group are issued before the stages of the
+// current one run, so HBM reads overlap the LDS work (the stage barriers
+// order LDS only and leave them in flight).
+template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false>
 __global__ void __launch_bounds__((SingleShape<LOG2N, LOG2E, WGT>::THREADS))
 k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw, int64_t batch) {
     using V = cplx_t<R>;
@@ -71,6 +74,21 @@ k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ t
     if constexpr (TWREG) twr.init(tid % T);
 
     const int64_t groups = (batch + G - 1) / G;
+    // element index of this thread's first point in group grp (row >= batch: none)
+    auto row_base = [&](int64_t grp, int tidl, bool& active) {
+        const int64_t tr = grp * G + tidl / T;
+        active = tr < batch;
+        return tr * L + tidl % T;
+    };
+    V nxt[PF ? E : 1];
+    if constexpr (PF) {
+        bool act;
+        const int64_t base = row_base(blockIdx.x, tid, act);
+        if (blockIdx.x < groups && act) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) nxt[m] = swap_if<SWAP>(gload_nt<SPLIT>(ia, ib, base + T * m));
+        }
+    }
     for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
         // table reads stay inside the loop unless the registers were asked for:
         // the empty asm hides the pointer's loop invariance from the compiler
@@ -81,12 +99,19 @@ k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ t
         int tidl = tid;
         asm volatile("" : "+v"(tidl));
         if constexpr (!TWREG) asm volatile("" : "+s"(twl));
-        const int tl = tidl % T, gl = tidl / T;
-        const int64_t tr = grp * G + gl;
-        const bool active = tr < batch;
-        const int64_t base = tr * L + tl;
+        bool active;
+        const int64_t base = row_base(grp, tidl, active);
         V v[E];
-        if (active) {
+        if constexpr (PF) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = active ? nxt[m] : c_zero<V>();
+            bool act2;
+            const int64_t base2 = row_base(grp + gridDim.x, tidl, act2);
+            if (grp + gridDim.x < groups && act2) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) nxt[m] = swap_if<SWAP>(gload_nt<SPLIT>(ia, ib, base2 + T * m));
+            }
+        } else if (active) {
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = swap_if<SWAP>(gload_nt<SPLIT>(ia, ib, base + T * m));
         } else {
@@ -102,14 +127,14 @@ k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ t
     }
 }
 
-template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG>
+template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false>
 hipError_t launch_single(const void* ia, const void* ib, void* oa, void* ob, const void* tw, int64_t batch, int grid,
                          hipStream_t s) {
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
     const int64_t groups = (batch + SH::G - 1) / SH::G;
     const int64_t blocks = groups < grid ? groups : grid;
     if (blocks < 1) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG>), dim3(static_cast<unsigned>(blocks)),
+    hipLaunchKernelGGL((k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF>), dim3(static_cast<unsigned>(blocks)),
                        dim3(SH::THREADS), 0, s, static_cast<const R*>(ia), static_cast<const R*>(ib),
                        static_cast<R*>(oa), static_cast<R*>(ob), static_cast<const cplx_t<R>*>(tw), batch);
     return hipGetLastError();
@@ -174,13 +199,15 @@ struct PassShape {
 // The pass twiddle of input r of column j (k = j mod Ns) is w_M^(r k), M = Ns L.
 // A thread holds r = tp + T m (m < E), so w_M^(r k) = w_M^(tp k) (w_M^(T k))^m:
 // two table lookups per thread and an FP64 running product, rounded once per
-// element to the working precision (the FP64 recurrence error over E <= 16
+// element to the working precision (PASSTW = false leaves the factors out: a
+// plain DFT_L down every column, the strided axes of multi-dimensional
+// transforms) (the FP64 recurrence error over E <= 16
 // steps stays near 1e-15: far below the rounding to FP32, and within a few
 // units of FP64 rounding for the FP64 instances).
 template <class T> struct nodeduce { using type = T; };
 
 template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN, bool SWAP_OUT,
-          bool NT, class TW, class R>
+          bool NT, class TW, class R, bool PASSTW = true>
 __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R>::type* ib,
                                           typename nodeduce<R>::type* oa, typename nodeduce<R>::type* ob,
                                           const TW& tw, const double2* __restrict__ ta,
@@ -205,7 +232,7 @@ __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R
             const int64_t i = tbase + j + (tp + T * m) * stride;
             v[m] = swap_if<SWAP_IN>(NT ? gload_nt<SPLIT_IN>(ia, ib, i) : gload<SPLIT_IN>(ia, ib, i));
         }
-        if constexpr (!FIRST) {
+        if constexpr (!FIRST && PASSTW) {
             double2 w = twiddle_2level64(ta, tb, k * tp, hbits);
             const double2 step = twiddle_2level64(ta, tb, k * T, hbits);
 #pragma unroll

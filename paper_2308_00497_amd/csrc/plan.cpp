@@ -29,6 +29,9 @@ std::string Decomp::str() const {
         case SINGLE:
             snprintf(buf, sizeof buf, "single:e%d:w%d:g%d:r%d", log2e, wgt, gmul, twreg ? 1 : 0);
             return buf;
+        case OPS:
+            snprintf(buf, sizeof buf, "ops:r%d", log2r);
+            return buf;
         case MULTI: {
             std::string s = "multi:";
             for (size_t p = 0; p < log2l.size(); ++p) {
@@ -56,6 +59,14 @@ bool Decomp::parse(const std::string& s, Decomp* out) {
         d.wgt = w;
         d.gmul = g;
         d.twreg = r == 1;
+        *out = d;
+        return true;
+    }
+    int rr = 0;
+    if (sscanf(s.c_str(), "ops:r%d%n", &rr, &used) == 1 && used == (int)s.size()) {
+        if (rr < 1 || rr > 4) return false;
+        d.kind = OPS;
+        d.log2r = rr;
         *out = d;
         return true;
     }
@@ -137,9 +148,17 @@ static bool pass_chain_available(const std::vector<int>& ls, const std::vector<i
     return true;
 }
 
+std::vector<int> ops_radices(int log2n, int log2r) {
+    std::vector<int> r(log2n / log2r, log2r);
+    if (log2n % log2r) r.push_back(log2n % log2r);
+    return r;
+}
+
 bool decomposition_available(const Decomp& d, int log2n, fft_layout layout, int rb) {
     if (rb != 4 && rb != 8) return false;
     switch (d.kind) {
+        case Decomp::OPS:
+            return log2n >= 1 && layout == FFT_LAYOUT_INTERLEAVED && d.log2r >= 1 && d.log2r <= 4;
         case Decomp::COPY:
             return log2n == 0;
         case Decomp::SINGLE: {
@@ -167,12 +186,13 @@ static std::vector<int> even_split(int log2n, int parts) {
     return v;
 }
 
-// FP64 defaults: single-pass up to 2^13, then passes with 128-byte runs
+// FP64 defaults, measured on MI355X (batches of 2^24 elements, the faster on
+// average over both layouts): single-pass up to 2^13, then passes
 static Decomp default_decomposition64(int log2n) {
-    static const struct { int log2e, gmul, twreg; } single[14] = {
-        {4, 1, 1}, {4, 8, 1}, {4, 8, 1}, {4, 8, 1}, {3, 8, 1},  // 2^0 .. 2^4
-        {3, 4, 1}, {3, 4, 1}, {3, 2, 1}, {3, 2, 1}, {3, 2, 1},  // 2^5 .. 2^9
-        {3, 2, 1}, {3, 2, 1}, {3, 2, 0}, {3, 1, 0},             // 2^10 .. 2^13
+    static const struct { int log2e, wgt, gmul, twreg; } single[14] = {
+        {4, 256, 1, 1}, {4, 256, 2, 0}, {4, 64, 3, 0}, {4, 64, 1, 0}, {3, 256, 8, 1},  // 2^0 .. 2^4
+        {3, 256, 8, 1}, {3, 256, 1, 1}, {3, 64, 3, 1}, {3, 64, 3, 1}, {3, 64, 4, 1},   // 2^5 .. 2^9
+        {3, 256, 2, 1}, {3, 256, 2, 1}, {3, 256, 1, 1}, {4, 256, 2, 0},                // 2^10 .. 2^13
     };
     static const char* multi[kMaxLog2N + 1] = {
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
@@ -180,14 +200,14 @@ static Decomp default_decomposition64(int log2n) {
         "multi:7c5,7c5",          // 2^14
         "multi:8c4,7c5",          // 2^15
         "multi:8c4,8c4",          // 2^16
-        "multi:9c3,8c4",          // 2^17
-        "multi:9c3,9c3",          // 2^18
-        "multi:10c3,9c3",         // 2^19
+        "multi:9c4,8c5",          // 2^17
+        "multi:10c3,8c5",         // 2^18
+        "multi:10c3,9c4",         // 2^19
         "multi:10c3,10c3",        // 2^20
-        "multi:7c5,7c5,7c5",      // 2^21
-        "multi:8c4,7c5,7c5",      // 2^22
+        "multi:7c5,7c6,7c5",      // 2^21
+        "multi:8c5,8c5,6c7",      // 2^22
         "multi:8c4,8c4,7c5",      // 2^23
-        "multi:8c4,8c4,8c4",      // 2^24
+        "multi:9c4,8c5,7c4",      // 2^24
     };
     Decomp d;
     if (log2n <= 0) {
@@ -195,7 +215,7 @@ static Decomp default_decomposition64(int log2n) {
     } else if (log2n <= 13) {
         d.kind = Decomp::SINGLE;
         d.log2e = single[log2n].log2e;
-        d.wgt = 256;
+        d.wgt = single[log2n].wgt;
         d.gmul = single[log2n].gmul;
         d.twreg = single[log2n].twreg == 1;
     } else {
@@ -217,7 +237,7 @@ Decomp default_decomposition(int log2n, int rb) {
         static const struct { int log2e, gmul, twreg; } table[15] = {
             {4, 1, 1}, {4, 8, 1}, {4, 8, 1}, {4, 8, 1}, {3, 8, 1},  // 2^0 .. 2^4
             {3, 8, 1}, {3, 8, 1}, {3, 2, 1}, {3, 2, 1}, {3, 2, 1},  // 2^5 .. 2^9
-            {3, 2, 1}, {3, 2, 1}, {4, 2, 1}, {3, 1, 1}, {4, 8, 0},  // 2^10 .. 2^14
+            {3, 2, 1}, {3, 2, 1}, {4, 2, 1}, {4, 3, 1}, {4, 8, 0},  // 2^10 .. 2^14
         };
         d.kind = Decomp::SINGLE;
         d.log2e = table[log2n].log2e;
@@ -250,6 +270,74 @@ Decomp default_decomposition(int log2n, int rb) {
     d.log2l = even_split(log2n, parts);
     for (int l : d.log2l) d.log2c.push_back(default_log2c(rb, l));
     return d;
+}
+
+const RealKernel* find_real(int rb, int log2h, int log2e, int wgt, bool c2r, bool split, bool twreg) {
+    int cnt = 0;
+    const RealKernel* t = rb == 8 ? real_kernels64(&cnt) : real_kernels(&cnt);
+    const int le = log2e < log2h ? log2e : log2h;
+    for (int i = 0; i < cnt; ++i)
+        if (t[i].log2h == log2h && t[i].log2e == le && t[i].wgt == wgt && t[i].c2r == c2r && t[i].split == split &&
+            t[i].twreg == twreg)
+            return &t[i];
+    return nullptr;
+}
+
+bool real_decomposition_available(const Decomp& d, int log2n, fft_layout layout, int rb, bool c2r) {
+    if ((rb != 4 && rb != 8) || log2n < 1) return false;
+    const int log2h = log2n - 1;
+    const bool split = layout == FFT_LAYOUT_SPLIT;
+    switch (d.kind) {
+        case Decomp::OPS:
+            return false;
+        case Decomp::COPY:
+            return log2h == 0;
+        case Decomp::SINGLE:
+            return log2h >= 1 && find_real(rb, log2h, d.log2e, d.wgt, c2r, split, d.twreg) != nullptr;
+        case Decomp::MULTI: {
+            // the half-length chain runs on interleaved data in both directions
+            int sum = 0;
+            for (int l : d.log2l) sum += l;
+            if (sum != log2h || d.log2l.size() != d.log2c.size() || d.log2l.size() < 2) return false;
+            const size_t P = d.log2l.size();
+            for (size_t q = 0; q < P; ++q) {
+                if (log2h - d.log2l[q] < d.log2c[q]) return false;
+                if (!pass_kernel_for(rb, d.log2l[q], d.log2c[q], q, P, false, c2r)) return false;
+            }
+            return true;
+        }
+    }
+    return false;
+}
+
+// The half length's complex default, with the single-pass shape moved to a
+// compiled real instance if the complex one has none.
+Decomp default_real_decomposition(int log2n, int rb) {
+    Decomp d = default_decomposition(log2n - 1, rb);
+    if (d.kind != Decomp::SINGLE) return d;
+    const int log2h = log2n - 1;
+    if (find_real(rb, log2h, d.log2e, d.wgt, false, false, d.twreg)) return d;
+    for (int r : {1, 0})
+        for (int e : {4, 3})
+            if (find_real(rb, log2h, e, 256, false, false, r == 1)) {
+                d.log2e = e;
+                d.wgt = 256;
+                d.twreg = r == 1;
+                return d;
+            }
+    return default_decomposition(log2n - 1, rb);
+}
+
+const StridedKernel* strided_kernel_for(int rb, int log2l, int log2s, bool split, bool swap) {
+    int cnt = 0;
+    const StridedKernel* t = strided_kernels(&cnt);
+    const StridedKernel* best = nullptr;
+    for (int i = 0; i < cnt; ++i) {
+        const StridedKernel& k = t[i];
+        if (k.real_bytes != rb || k.log2l != log2l || k.split != split || k.swap != swap || k.log2c > log2s) continue;
+        if (!best || k.log2c > best->log2c) best = &k;
+    }
+    return best;
 }
 
 std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int rb) {

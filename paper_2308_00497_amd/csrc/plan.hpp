@@ -19,8 +19,11 @@ namespace fftk {
 //            compute unit, stage twiddles in registers when twreg)
 //   multi    P passes of sub-FFT lengths 2^log2l[p] with 2^log2c[p] columns per
 //            workgroup, sum of log2l = log2 N (Stockham radix-L passes)
+//   ops      the per-operator baseline: Table 1's operators one kernel each,
+//            radix 2^log2r (interleaved layout only; never chosen by default)
 struct Decomp {
-    enum Kind { COPY = 0, SINGLE = 1, MULTI = 2 } kind = COPY;
+    enum Kind { COPY = 0, SINGLE = 1, MULTI = 2, OPS = 3 } kind = COPY;
+    int log2r = 4;
     int log2e = 4;
     int wgt = 256;
     int gmul = 2;
@@ -28,7 +31,7 @@ struct Decomp {
     std::vector<int> log2l;
     std::vector<int> log2c;
 
-    std::string str() const;  // "copy" | "single:e4:w256:g2:r1" | "multi:8c4,8c4,8c4"
+    std::string str() const;  // "copy" | "single:e4:w256:g2:r1" | "multi:8c4,8c4,8c4" | "ops:r4"
     static bool parse(const std::string& s, Decomp* out);
     bool operator==(const Decomp& o) const { return str() == o.str(); }
 };
@@ -54,8 +57,26 @@ const SingleKernel* single_kernel_for(int rb, int log2n, const Decomp& d, bool s
 // true when every kernel the decomposition needs exists for this layout
 bool decomposition_available(const Decomp& d, int log2n, fft_layout layout, int rb);
 
+// Real-input plans (R2C, or C2R when c2r) of N = 2^log2n real points run on
+// the half length H = N/2: "copy" stands for H = 1 (the pre/post pass alone),
+// "single:..." for the fused single-pass kernel, "multi:..." for the
+// half-length pass chain plus one pre/post pass.  N = 1 has no decomposition.
+const RealKernel* find_real(int rb, int log2h, int log2e, int wgt, bool c2r, bool split, bool twreg);
+Decomp default_real_decomposition(int log2n, int rb);
+bool real_decomposition_available(const Decomp& d, int log2n, fft_layout layout, int rb, bool c2r);
+
+// Column kernel of a multi-dimensional plan for a strided axis of 2^log2l
+// points at stride 2^log2s: the widest compiled column tile that fits the
+// stride; nullptr if the axis is longer than 2^12 points.
+const StridedKernel* strided_kernel_for(int rb, int log2l, int log2s, bool split, bool swap);
+constexpr int kMaxStridedLog2 = 12;
+
 // bytes of one real number for a precision (0 if invalid)
 inline int real_bytes_of(fft_precision p) { return p == FFT_PRECISION_FP32 ? 4 : (p == FFT_PRECISION_FP64 ? 8 : 0); }
+
+// radices (log2) of the per-operator baseline for N = 2^log2n, outermost first:
+// radix 2^log2r at every level, the remainder innermost
+std::vector<int> ops_radices(int log2n, int log2r);
 
 int ilog2_exact(int64_t v);  // log2 of a power of two, -1 otherwise
 

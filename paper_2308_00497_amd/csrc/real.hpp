@@ -1,0 +1,178 @@
+// Real-input transforms (R2C) and their inverse (C2R) for N = 2H real points,
+// computed through the complex transform of half the length.
+//
+// R2C: the real row read as H complex pairs, z[n] = x[2n] + i x[2n+1], is one
+// complex sequence; its DFT Z = DFT_H(z) holds the spectra of the even and
+// the odd samples,
+//     Ev[k] = (Z[k] + conj Z[H-k]) / 2,      Od[k] = -i (Z[k] - conj Z[H-k]) / 2
+// (indices of Z mod H), and the DFT of x is X[k] = Ev[k] + w_N^k Od[k] for
+// k = 0 .. H, with X[H-k] = conj(Ev[k] - w_N^k Od[k]).  A step of Eq. 1 with
+// K = 2 on the real sequence, whose two half-length DFTs share one complex
+// transform.
+//
+// C2R inverts it: with A = X[k] + conj X[H-k] and B = X[k] - conj X[H-k],
+//     Z'[k] = A + i w_N^-k B,   k = 0 .. H-1,
+// (the imaginary parts of X[0] and X[H] do not enter: the output is the real
+// part of the inverse transform of the Hermitian extension), and the
+// unnormalised inverse DFT_H of Z' is N (x[2n] + i x[2n+1]).
+//
+// Single-pass sizes run in one kernel: the half-length engine plus one more
+// exchange through LDS that pairs k with H - k.  Larger sizes run the
+// half-length multi-pass chain and one extra pass over HBM (k_r2c_post,
+// k_c2r_pre).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace fftk {
+
+// Ev[k] and w Od[k] for a = Z[k], mir = Z[(H-k) mod H], w = w_N^k:
+// X[k] = ev + wo and X[H-k] = conj(ev - wo)
+template <class V>
+__device__ __forceinline__ void r2c_parts(V a, V mir, V w, V& ev, V& wo) {
+    using R = typename RealOf<V>::type;
+    const R h = R(0.5);
+    ev = cmk(h * (a.x + mir.x), h * (a.y - mir.y));
+    const V od = cmk(h * (a.y + mir.y), h * (mir.x - a.x));
+    wo = c_mul(od, w);
+}
+
+// Z'[k] for a = X[k], mir = X[H-k], w = w_N^k
+template <class V>
+__device__ __forceinline__ V c2r_point(V a, V mir, V w) {
+    const V c = cmk(mir.x, -mir.y);
+    const V s = c_add(a, c), d = c_sub(a, c);
+    const V wd = c_mul(d, cmk(w.x, -w.y));  // w^-k (a - conj mir)
+    return cmk(s.x - wd.y, s.y + wd.x);      // s + i wd
+}
+
+template <int LOG2H, int LOG2E, int WGT>
+struct RealShape {
+    using SH = SingleShape<LOG2H, LOG2E, WGT>;
+    using SC = typename SH::SC;
+    // the pairing exchange needs the full group stride even for one-stage engines
+    static constexpr int LDS = SH::G * SH::GS;
+};
+
+// One persistent single-pass kernel per direction.  `tw` is the engine's stage
+// table, `twn` holds w_N^k for k < H.  R2C reads the real array as H complex
+// pairs per row and writes H + 1 complex values per row; C2R the reverse.
+template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG>
+__global__ void __launch_bounds__((SingleShape<LOG2H, LOG2E, WGT>::THREADS))
+k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw,
+              const cplx_t<R>* __restrict__ twn, int64_t batch) {
+    using V = cplx_t<R>;
+    using SH = SingleShape<LOG2H, LOG2E, WGT>;
+    using SC = typename SH::SC;
+    using ENG = Engine<SC, SH::G, SH::GS, false, false, SH::WAVE>;
+    constexpr int E = SC::E, T = SC::T, H = SC::L, G = SH::G;
+    static_assert(LOG2H >= 1, "H = 1 runs as a pre/post pass only");
+    __shared__ V lds[RealShape<LOG2H, LOG2E, WGT>::LDS];
+
+    const int tid = threadIdx.x;
+    TwReg<SC, V> twr(tw);
+    if constexpr (TWREG) twr.init(tid % T);
+
+    const int64_t groups = (batch + G - 1) / G;
+    for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+        const V* twl = tw;
+        const V* twnl = twn;
+        int tidl = tid;
+        asm volatile("" : "+v"(tidl));
+        asm volatile("" : "+s"(twnl));
+        if constexpr (!TWREG) asm volatile("" : "+s"(twl));
+        const int tl = tidl % T, gl = tidl / T;
+        const int64_t tr = grp * G + gl;
+        const bool active = tr < batch;
+        V v[E];
+        if constexpr (!C2R) {
+            const int64_t base = tr * H + tl;  // complex pair index in the real row
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = active ? gload_nt<false>(ia, ia, base + T * m) : c_zero<V>();
+            if constexpr (TWREG) ENG::run(v, lds, twr, tidl);
+            else ENG::run(v, lds, TwMem<SC, V>(twl), tidl);
+            stage_sync<SH::WAVE>();  // the engine's last reads of LDS are done
+#pragma unroll
+            for (int m = 0; m < E; ++m) lds[lds_at<SH::GS>(gl, tl + T * m)] = v[m];
+            stage_sync<SH::WAVE>();
+            if (active) {
+                const int64_t ob0 = tr * (H + 1);
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int k = tl + T * m;
+                    const V mir = lds[lds_at<SH::GS>(gl, (H - k) & (H - 1))];
+                    V ev, wo;
+                    r2c_parts(v[m], mir, twnl[k], ev, wo);
+                    gstore_nt<SPLIT>(oa, ob, ob0 + k, c_add(ev, wo));
+                }
+                if (tl == 0) gstore_nt<SPLIT>(oa, ob, ob0 + H, cmk(v[0].x - v[0].y, R(0)));
+            }
+        } else {
+            const int64_t ib0 = tr * (H + 1);
+            V xh = c_zero<V>();
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = active ? gload_nt<SPLIT>(ia, ib, ib0 + tl + T * m) : c_zero<V>();
+            if (active && tl == 0) xh = gload<SPLIT>(ia, ib, ib0 + H);
+            stage_sync<SH::WAVE>();  // the previous transform's reads of LDS are done
+#pragma unroll
+            for (int m = 0; m < E; ++m) lds[lds_at<SH::GS>(gl, tl + T * m)] = v[m];
+            stage_sync<SH::WAVE>();
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int k = tl + T * m;
+                V a = v[m], mir;
+                if (k == 0) {
+                    a = cmk(a.x, R(0));
+                    mir = cmk(xh.x, R(0));
+                } else {
+                    mir = lds[lds_at<SH::GS>(gl, H - k)];
+                }
+                // inverse DFT_H = S DFT_H S: swap on the way in and out
+                v[m] = swap_if<true>(c2r_point(a, mir, twnl[k]));
+            }
+            if constexpr (TWREG) ENG::run(v, lds, twr, tidl);
+            else ENG::run(v, lds, TwMem<SC, V>(twl), tidl);
+            if (active) {
+                const int64_t base = tr * H + tl;
+#pragma unroll
+                for (int m = 0; m < E; ++m) gstore_nt<false>(oa, oa, base + T * m, swap_if<true>(v[m]));
+            }
+        }
+    }
+}
+
+template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG>
+hipError_t launch_real_single(const void* ia, const void* ib, void* oa, void* ob, const void* tw, const void* twn,
+                              int64_t batch, int grid, hipStream_t s) {
+    using SH = SingleShape<LOG2H, LOG2E, WGT>;
+    const int64_t groups = (batch + SH::G - 1) / SH::G;
+    const int64_t blocks = groups < grid ? groups : grid;
+    if (blocks < 1) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG>), dim3(static_cast<unsigned>(blocks)),
+                       dim3(SH::THREADS), 0, s, static_cast<const R*>(ia), static_cast<const R*>(ib),
+                       static_cast<R*>(oa), static_cast<R*>(ob), static_cast<const cplx_t<R>*>(tw),
+                       static_cast<const cplx_t<R>*>(twn), batch);
+    return hipGetLastError();
+}
+
+template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG>
+RealKernel real_entry() {
+    using SH = SingleShape<LOG2H, LOG2E, WGT>;
+    RealKernel k{};
+    k.real_bytes = sizeof(R);
+    k.log2h = LOG2H;
+    k.log2e = SH::SC::LE;
+    k.wgt = WGT;
+    k.c2r = C2R;
+    k.split = SPLIT;
+    k.twreg = TWREG;
+    k.fn = &launch_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG>;
+    k.kernel = reinterpret_cast<const void*>(&k_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG>);
+    k.eng = engine_info<typename SH::SC>();
+    k.threads = SH::THREADS;
+    k.per_wg = SH::G;
+    k.lds_bytes = RealShape<LOG2H, LOG2E, WGT>::LDS * sizeof(cplx_t<R>);
+    return k;
+}
+
+}  // namespace fftk

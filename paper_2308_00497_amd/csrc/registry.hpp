@@ -67,11 +67,74 @@ struct PassKernel {
     size_t lds_bytes;
 };
 
+// Single-pass real-input kernel (R2C, or C2R when c2r): half length
+// H = 2^log2h; `tw` is the engine stage table and `twn` holds w_N^k, k < H,
+// N = 2H, both in the kernel's precision.
+using real_fn = hipError_t (*)(const void* ia, const void* ib, void* oa, void* ob, const void* tw, const void* twn,
+                               int64_t batch, int grid, hipStream_t s);
+
+struct RealKernel {
+    int real_bytes;
+    int log2h;
+    int log2e;
+    int wgt;
+    bool c2r;
+    bool split;     // complex side split into re/im arrays
+    bool twreg;
+    real_fn fn;
+    const void* kernel;
+    EngineInfo eng;
+    int threads;
+    int per_wg;
+    size_t lds_bytes;
+};
+
+// Column transforms of multi-dimensional plans: DFT_(2^log2l) down every
+// column of stride 2^log2s, over blocks_b column blocks, C = 2^log2c columns
+// per workgroup (log2l <= 4: one thread per column, no table, log2c 0).
+using strided_fn = hipError_t (*)(const void* ia, const void* ib, void* oa, void* ob, const void* tw, int log2s,
+                                  int64_t blocks_b, int grid, hipStream_t s);
+
+struct StridedKernel {
+    int real_bytes;
+    int log2l;
+    int log2c;
+    bool split;
+    bool swap;
+    strided_fn fn;
+    const void* kernel;  // nullptr for the one-thread-per-column kernels
+    EngineInfo eng;
+    int threads;
+    size_t lds_bytes;
+};
+
 // tables defined in the kernel translation units (FP32 and FP64 instances)
 const SingleKernel* single_kernels(int* count);
 const PassKernel* pass_kernels(int* count);
 const SingleKernel* single_kernels64(int* count);
 const PassKernel* pass_kernels64(int* count);
+const RealKernel* real_kernels(int* count);
+const RealKernel* real_kernels64(int* count);
+const StridedKernel* strided_kernels(int* count);
+
+// passes over HBM around the multi-pass half-length transform of real plans
+// (z: interleaved half-length data; ta/tb: FP64 tables of w_N, N = 2^(log2h+1))
+hipError_t launch_r2c_post(int rb, bool split, const void* z, void* oa, void* ob, const double2* ta,
+                           const double2* tb, int hbits, int log2h, int64_t batch, hipStream_t s);
+hipError_t launch_c2r_pre(int rb, bool split, const void* ia, const void* ib, void* z, const double2* ta,
+                          const double2* tb, int hbits, int log2h, int64_t batch, hipStream_t s);
+// per-operator baseline (Table 1 operators, one kernel each; interleaved data)
+hipError_t launch_op_kron(int rb, int log2r, const void* x, void* y, int64_t a, int64_t b, bool swap_in,
+                          bool swap_out, hipStream_t s);
+hipError_t launch_op_mul(int rb, const void* x, void* y, const void* d, int64_t a, int log2n, hipStream_t s);
+hipError_t launch_op_perm(int rb, const void* x, void* y, int64_t a, int log2m, int log2n, bool swap_in,
+                          hipStream_t s);
+hipError_t launch_gen_diag(int rb, void* dst, int log2n, int log2m, hipStream_t s);
+// N = 1 real transforms
+hipError_t launch_real1(int rb, bool c2r, bool split, const void* ia, const void* ib, void* oa, void* ob,
+                        int64_t batch, hipStream_t s);
+// dst[i] = w_M^i rounded once to the precision of rb, i < count
+hipError_t launch_gen_pow_round(void* dst, int rb, int log2M, int64_t count, hipStream_t s);
 
 // plain streaming copy (16-byte accesses), bytes % 16 == 0
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);

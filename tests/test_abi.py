@@ -97,6 +97,43 @@ def test_create_ex_validation(lib):
     assert ex(None, 64, 1, 0, -1, 1, None) == 3
 
 
+def test_create_real_validation(lib):
+    """Real-input plans: size, enum and decomposition checks before any HIP call."""
+    h = ctypes.c_void_p()
+    cr = lib.fft_plan_create_real
+    assert cr(ctypes.byref(h), 100, 1, 0, -1, 0, None) == 1
+    assert cr(ctypes.byref(h), 1 << 25, 1, 0, -1, 0, None) == 1
+    assert cr(ctypes.byref(h), 64, 0, 0, -1, 0, None) == 2
+    assert cr(ctypes.byref(h), 64, 1, 3, -1, 0, None) == 2
+    assert cr(ctypes.byref(h), 64, 1, 0, 0, 0, None) == 2
+    assert cr(ctypes.byref(h), 64, 1, 0, -1, 5, None) == 2
+    assert cr(ctypes.byref(h), 64, 1, 0, -1, 0, b"nonsense") == 2
+    assert cr(ctypes.byref(h), 64, 1, 0, -1, 0, b"multi:3c1,2c1") == 7   # sums to log2 n, not log2 n/2
+    assert cr(ctypes.byref(h), 64, 1, 0, -1, 0, b"copy") == 7            # copy is n = 2 only
+    assert cr(ctypes.byref(h), 1, 1, 0, -1, 0, b"copy") == 7             # n = 1 takes none
+    assert cr(ctypes.byref(h), 1 << 16, 1, 1, 1, 1, b"single:e4:w256:g2:r1") == 7   # FP64 half 2^15
+    assert cr(None, 64, 1, 0, -1, 0, None) == 3
+
+
+def test_create_nd_validation(lib):
+    """Multi-dimensional plans: rank, dims and limits checked before any HIP call."""
+    h = ctypes.c_void_p()
+    nd = lib.fft_plan_create_nd
+
+    def dims(*d):
+        return (ctypes.c_int64 * len(d))(*d)
+    assert nd(ctypes.byref(h), 2, None, 1, 0, -1, 0) == 3
+    assert nd(ctypes.byref(h), 0, dims(4), 1, 0, -1, 0) == 2
+    assert nd(ctypes.byref(h), 4, dims(4, 4, 4, 4), 1, 0, -1, 0) == 2
+    assert nd(ctypes.byref(h), 2, dims(4, 6), 1, 0, -1, 0) == 1
+    assert nd(ctypes.byref(h), 2, dims(8192, 4), 1, 0, -1, 0) == 1     # strided axis above 2^12
+    assert nd(ctypes.byref(h), 2, dims(4, 1 << 25), 1, 0, -1, 0) == 1  # last axis above 2^24
+    assert nd(ctypes.byref(h), 3, dims(4, 4, 4), 0, 0, -1, 0) == 2
+    assert nd(ctypes.byref(h), 3, dims(4, 4, 4), 1, 0, -1, 9) == 2
+    assert nd(ctypes.byref(h), 3, dims(4096, 4096, 4096), 1 << 10, 0, -1, 0) == 2  # element bound
+    assert nd(None, 2, dims(4, 4), 1, 0, -1, 0) == 3
+
+
 def test_ragged_validation(lib):
     h = ctypes.c_void_p()
     arr = (ctypes.c_int64 * 3)(64, 100, 256)

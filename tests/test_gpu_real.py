@@ -1,0 +1,176 @@
+"""GPU parity of the real-input transforms: R2C (the half k = 0 .. n/2 of the
+DFT of real rows) and C2R (real part of the unnormalised inverse DFT of the
+Hermitian extension), FP32 and FP64, against the oracle's rfft / irfft."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from fftcheck import TOL, TOL64, assert_parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+PREC = {"fp32": (np.float32, TOL), "fp64": (np.float64, TOL64)}
+
+
+@pytest.fixture(scope="module")
+def fftlib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2308_00497_amd as m
+    return m
+
+
+def batch_for(n: int) -> int:
+    return max(1, min(33, (1 << 20) // n))
+
+
+def real_rows(batch, n, seed, dt):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((batch, n)).astype(dt)
+
+
+def half_spectra(batch, n, seed, dt):
+    """Random rows of n/2 + 1 complex values; the imaginary parts at DC and
+    Nyquist are non-zero on purpose (they must not reach the output)."""
+    re, im = workloads.normal_complex((batch, n // 2 + 1), seed, dtype=dt)
+    return re, im
+
+
+def complex_to_device(re, im, layout):
+    if layout == "split":
+        return (torch.from_numpy(np.ascontiguousarray(re)).cuda(), torch.from_numpy(np.ascontiguousarray(im)).cuda())
+    return torch.from_numpy(workloads.interleave(re, im)).cuda()
+
+
+def complex_from_device(y, layout):
+    torch.cuda.synchronize()
+    if layout == "split":
+        return y[0].cpu().numpy().astype(np.float64) + 1j * y[1].cpu().numpy().astype(np.float64)
+    return y.cpu().numpy().astype(np.complex128)
+
+
+def run_r2c(fftlib, x, layout, precision, decomposition=None):
+    b, n = x.shape
+    with fftlib.RealPlan(n, b, layout, "forward", precision, decomposition) as p:
+        y = complex_from_device(p.execute(torch.from_numpy(x).cuda()), layout)
+        d = p.describe()
+    return y, d
+
+
+def run_c2r(fftlib, re, im, n, layout, precision, decomposition=None):
+    b = re.shape[0]
+    with fftlib.RealPlan(n, b, layout, "inverse", precision, decomposition) as p:
+        y = p.execute(complex_to_device(re, im, layout))
+        torch.cuda.synchronize()
+        d = p.describe()
+    return y.cpu().numpy().astype(np.float64), d
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("layout", ["interleaved", "split"])
+@pytest.mark.parametrize("log2n", range(0, 25))
+def test_r2c_sweep(fftlib, log2n, layout, precision):
+    n = 1 << log2n
+    dt, tol = PREC[precision]
+    x = real_rows(batch_for(n), n, 8000 + log2n, dt)
+    y, d = run_r2c(fftlib, x, layout, precision)
+    assert_parity(y, oracle.rfft(x, threads=8), f"R2C {precision} n=2^{log2n} {layout} {d['decomposition']}", tol)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("layout", ["interleaved", "split"])
+@pytest.mark.parametrize("log2n", range(0, 25))
+def test_c2r_sweep(fftlib, log2n, layout, precision):
+    n = 1 << log2n
+    dt, tol = PREC[precision]
+    re, im = half_spectra(batch_for(n), n, 8100 + log2n, dt)
+    y, d = run_c2r(fftlib, re, im, n, layout, precision)
+    ref = oracle.irfft(re.astype(np.float64) + 1j * im.astype(np.float64), n, threads=8)
+    assert_parity(y, ref, f"C2R {precision} n=2^{log2n} {layout} {d['decomposition']}", tol)
+
+
+@pytest.mark.parametrize("precision,log2n", [(p, k) for p in ("fp32", "fp64") for k in (2, 6, 10, 13, 14, 15)
+                                             if not (p == "fp64" and k == 15)])
+def test_every_real_single_variant(fftlib, log2n, precision):
+    """Both twiddle sources and every compiled shape of the fused kernel (half
+    lengths up to the single-pass limit: 2^14 FP32, 2^13 FP64)."""
+    n = 1 << log2n
+    dt, tol = PREC[precision]
+    x = real_rows(batch_for(n), n, 8200 + log2n, dt)
+    re, im = half_spectra(batch_for(n), n, 8300 + log2n, dt)
+    ref_f = oracle.rfft(x, threads=8)
+    ref_i = oracle.irfft(re.astype(np.float64) + 1j * im.astype(np.float64), n, threads=8)
+    seen = 0
+    for e in (3, 4):
+        for r in (0, 1):
+            dec = f"single:e{e}:w256:g2:r{r}"
+            for layout in ("interleaved", "split"):
+                try:
+                    y, _ = run_r2c(fftlib, x, layout, precision, dec)
+                except fftlib.FFTError as err:
+                    assert err.status == "FFT_ERR_NOT_SUPPORTED"
+                    continue
+                assert_parity(y, ref_f, f"R2C {precision} n=2^{log2n} {layout} {dec}", tol)
+                yi, _ = run_c2r(fftlib, re, im, n, layout, precision, dec)
+                assert_parity(yi, ref_i, f"C2R {precision} n=2^{log2n} {layout} {dec}", tol)
+                seen += 1
+    assert seen > 0
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_real_multi_pass_variants(fftlib, precision):
+    """Half-length pass chains of two and three passes, explicit."""
+    dt, tol = PREC[precision]
+    for n, decs in ((1 << 17, ("multi:8c4,8c4", "multi:9c3,7c5")), (1 << 21, ("multi:7c4,7c4,6c6",))):
+        x = real_rows(2, n, 8400, dt)
+        re, im = half_spectra(2, n, 8401, dt)
+        ref_f = oracle.rfft(x, threads=8)
+        ref_i = oracle.irfft(re.astype(np.float64) + 1j * im.astype(np.float64), n, threads=8)
+        for dec in decs:
+            for layout in ("interleaved", "split"):
+                y, _ = run_r2c(fftlib, x, layout, precision, dec)
+                assert_parity(y, ref_f, f"R2C {precision} n={n} {layout} {dec}", tol)
+                yi, _ = run_c2r(fftlib, re, im, n, layout, precision, dec)
+                assert_parity(yi, ref_i, f"C2R {precision} n={n} {layout} {dec}", tol)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_round_trip(fftlib, precision):
+    """irfft(rfft(x), n) = n x, through the tensor functions."""
+    dt, tol = PREC[precision]
+    for log2n in (1, 5, 12, 15, 19):
+        n = 1 << log2n
+        x = real_rows(3, n, 8500 + log2n, dt)
+        xt = torch.from_numpy(x).cuda()
+        back = fftlib.irfft(fftlib.rfft(xt), n).cpu().numpy().astype(np.float64) / n
+        err = oracle.rel_l2(back.reshape(-1), x.astype(np.float64).reshape(-1))
+        assert err <= tol, (n, err)
+
+
+def test_r2c_batched_4096_sampled(fftlib):
+    """8192 real rows of 4096 (the batched shape of the complex benchmark),
+    64 sampled rows against the oracle."""
+    batch, n = 8192, 4096
+    rng = np.random.default_rng(workloads.SEEDS["c2"])
+    x = rng.standard_normal((batch, n)).astype(np.float32)
+    rows = np.sort(np.random.default_rng(88).choice(batch, size=64, replace=False))
+    with fftlib.RealPlan(n, batch, "interleaved", "forward") as p:
+        y = p.execute(torch.from_numpy(x).cuda())
+        torch.cuda.synchronize()
+        ys = y[rows].cpu().numpy()
+    assert_parity(ys, oracle.rfft(x[rows], threads=8), "R2C 8192 x 4096 (64 sampled rows)")
+
+
+def test_real_plan_errors(fftlib):
+    with fftlib.RealPlan(64, 2, "interleaved", "forward") as p:
+        with pytest.raises(fftlib.FFTError):
+            p.backward(torch.zeros(128, device="cuda"))
+        with pytest.raises(TypeError):
+            p.execute(torch.zeros(128, dtype=torch.float64, device="cuda"))
+        # the complex output may not overlap the real input
+        buf = torch.zeros(1024, dtype=torch.float32, device="cuda")
+        from paper_2308_00497_amd._lib import lib
+        rc = lib.fft_execute(p._handle, buf.data_ptr(), None, buf.data_ptr() + 256, None, None)
+        assert rc == 2
