@@ -71,7 +71,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
             if verbose and err.strip():
                 print(err, file=sys.stderr)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
+    # -z defs: an unresolved symbol fails the build instead of the first load
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Wl,-z,defs", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)

@@ -163,17 +163,19 @@ hipError_t launch_gen_pow_round(void* dst, int rb, int log2M, int64_t count, hip
     return hipGetLastError();
 }
 
-// Single-pass instances: the half-length shapes of the complex default
-// table, twiddles in registers or from the table, both directions, both
-// complex layouts.
+// Single-pass instances: 8 and 16 points per thread, stage twiddles in
+// registers or from the table, both directions, both complex layouts.
 #define FFT_RS1(h, e, r)                                                                                      \
     real_entry<float, h, e, 256, false, false, r>(), real_entry<float, h, e, 256, false, true, r>(),         \
         real_entry<float, h, e, 256, true, false, r>(), real_entry<float, h, e, 256, true, true, r>()
 #define FFT_RS(h, e) FFT_RS1(h, e, false), FFT_RS1(h, e, true)
 
 static const RealKernel kReal[] = {
-    FFT_RS(1, 4), FFT_RS(2, 4), FFT_RS(3, 4), FFT_RS(4, 3), FFT_RS(5, 3), FFT_RS(6, 3), FFT_RS(7, 3),
-    FFT_RS(8, 3), FFT_RS(9, 3), FFT_RS(10, 3), FFT_RS(11, 3), FFT_RS(12, 4), FFT_RS(13, 3),
+    FFT_RS(1, 4), FFT_RS(2, 4), FFT_RS(3, 4),
+    FFT_RS(4, 3), FFT_RS(5, 3), FFT_RS(6, 3), FFT_RS(7, 3), FFT_RS(8, 3), FFT_RS(9, 3), FFT_RS(10, 3),
+    FFT_RS(11, 3), FFT_RS(12, 3), FFT_RS(13, 3),
+    FFT_RS(4, 4), FFT_RS(5, 4), FFT_RS(6, 4), FFT_RS(7, 4), FFT_RS(8, 4), FFT_RS(9, 4), FFT_RS(10, 4),
+    FFT_RS(11, 4), FFT_RS(12, 4), FFT_RS(13, 4),
     FFT_RS1(14, 4, false),
 };
 

@@ -9,8 +9,11 @@ namespace fftk {
 #define FFT_RD(h, e) FFT_RD1(h, e, false), FFT_RD1(h, e, true)
 
 static const RealKernel kReal64[] = {
-    FFT_RD(1, 4), FFT_RD(2, 4), FFT_RD(3, 4), FFT_RD(4, 3), FFT_RD(5, 3), FFT_RD(6, 3), FFT_RD(7, 3),
-    FFT_RD(8, 3), FFT_RD(9, 3), FFT_RD(10, 3), FFT_RD(11, 3), FFT_RD1(12, 3, false), FFT_RD1(13, 3, false),
+    FFT_RD(1, 4), FFT_RD(2, 4), FFT_RD(3, 4),
+    FFT_RD(4, 3), FFT_RD(5, 3), FFT_RD(6, 3), FFT_RD(7, 3), FFT_RD(8, 3), FFT_RD(9, 3), FFT_RD(10, 3),
+    FFT_RD(11, 3), FFT_RD1(12, 3, false), FFT_RD1(13, 3, false),
+    FFT_RD(4, 4), FFT_RD(5, 4), FFT_RD(6, 4), FFT_RD(7, 4), FFT_RD(8, 4), FFT_RD1(9, 4, false),
+    FFT_RD1(10, 4, false), FFT_RD1(11, 4, false), FFT_RD1(12, 4, false), FFT_RD1(13, 4, false),
 };
 
 #undef FFT_RD

@@ -310,22 +310,37 @@ bool real_decomposition_available(const Decomp& d, int log2n, fft_layout layout,
     return false;
 }
 
-// The half length's complex default, with the single-pass shape moved to a
-// compiled real instance if the complex one has none.
+// Real plans: single-pass shapes measured on MI355X (2^25 FP32 or 2^24 FP64
+// reals, the faster of R2C + C2R, interleaved), indexed by log2 N; above the
+// single-pass limit, the half length's complex pass chain.
+struct RealShapeChoice {
+    int log2e, gmul, twreg;
+};
+
 Decomp default_real_decomposition(int log2n, int rb) {
-    Decomp d = default_decomposition(log2n - 1, rb);
-    if (d.kind != Decomp::SINGLE) return d;
+    static const RealShapeChoice r32[16] = {
+        {4, 1, 1}, {4, 1, 1}, {3, 2, 1}, {3, 1, 0}, {4, 1, 0}, {3, 1, 1}, {3, 1, 1}, {3, 2, 1},  // 2^0 .. 2^7
+        {3, 2, 1}, {3, 2, 1}, {3, 2, 1}, {4, 2, 1}, {4, 2, 1}, {3, 2, 1}, {3, 8, 0}, {4, 1, 0},  // 2^8 .. 2^15
+    };
+    static const RealShapeChoice r64[15] = {
+        {4, 1, 1}, {4, 1, 1}, {4, 1, 1}, {4, 1, 0}, {4, 1, 1}, {3, 1, 1}, {3, 1, 1}, {3, 1, 1},  // 2^0 .. 2^7
+        {3, 2, 0}, {3, 2, 1}, {3, 2, 1}, {3, 2, 1}, {3, 2, 1}, {4, 4, 0}, {4, 1, 0},             // 2^8 .. 2^14
+    };
     const int log2h = log2n - 1;
-    if (find_real(rb, log2h, d.log2e, d.wgt, false, false, d.twreg)) return d;
-    for (int r : {1, 0})
-        for (int e : {4, 3})
-            if (find_real(rb, log2h, e, 256, false, false, r == 1)) {
-                d.log2e = e;
-                d.wgt = 256;
-                d.twreg = r == 1;
-                return d;
-            }
-    return default_decomposition(log2n - 1, rb);
+    Decomp d;
+    if (log2h <= 0) {
+        d.kind = Decomp::COPY;
+        return d;
+    }
+    const int lim = rb == 8 ? 14 : 15;
+    if (log2n > lim) return default_decomposition(log2h, rb);
+    const RealShapeChoice& t = rb == 8 ? r64[log2n] : r32[log2n];
+    d.kind = Decomp::SINGLE;
+    d.log2e = t.log2e;
+    d.wgt = 256;
+    d.gmul = t.gmul;
+    d.twreg = t.twreg == 1;
+    return d;
 }
 
 const StridedKernel* strided_kernel_for(int rb, int log2l, int log2s, bool split, bool swap) {

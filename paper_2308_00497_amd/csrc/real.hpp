@@ -46,12 +46,16 @@ __device__ __forceinline__ V c2r_point(V a, V mir, V w) {
     return cmk(s.x - wd.y, s.y + wd.x);      // s + i wd
 }
 
-template <int LOG2H, int LOG2E, int WGT>
+template <class R, int LOG2H, int LOG2E, int WGT>
 struct RealShape {
     using SH = SingleShape<LOG2H, LOG2E, WGT>;
     using SC = typename SH::SC;
-    // the pairing exchange needs the full group stride even for one-stage engines
-    static constexpr int LDS = SH::G * SH::GS;
+    static constexpr int EX = SH::G * SH::GS;  // the pairing exchange: full group stride
+    // a separate exchange region when both fit in 64 KB: the exchange then
+    // needs no barrier against the engine's last LDS reads (the engine's own
+    // stage barriers order one transform's exchange before the next one's)
+    static constexpr bool SEP = SC::NST >= 2 && 2 * EX * sizeof(cplx_t<R>) <= 65536;
+    static constexpr int LDS = SEP ? 2 * EX : EX;
 };
 
 // One persistent single-pass kernel per direction.  `tw` is the engine's stage
@@ -64,22 +68,26 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
     using V = cplx_t<R>;
     using SH = SingleShape<LOG2H, LOG2E, WGT>;
     using SC = typename SH::SC;
+    using RS = RealShape<R, LOG2H, LOG2E, WGT>;
     using ENG = Engine<SC, SH::G, SH::GS, false, false, SH::WAVE>;
     constexpr int E = SC::E, T = SC::T, H = SC::L, G = SH::G;
     static_assert(LOG2H >= 1, "H = 1 runs as a pre/post pass only");
-    __shared__ V lds[RealShape<LOG2H, LOG2E, WGT>::LDS];
+    __shared__ V lds[RS::LDS];
+    V* const xch = RS::SEP ? lds + RS::EX : lds;  // pairing exchange region
 
     const int tid = threadIdx.x;
     TwReg<SC, V> twr(tw);
     if constexpr (TWREG) twr.init(tid % T);
+    // w_N^k of this thread's points, loaded once per workgroup
+    V wn[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) wn[m] = twn[tid % T + T * m];
 
     const int64_t groups = (batch + G - 1) / G;
     for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
         const V* twl = tw;
-        const V* twnl = twn;
         int tidl = tid;
         asm volatile("" : "+v"(tidl));
-        asm volatile("" : "+s"(twnl));
         if constexpr (!TWREG) asm volatile("" : "+s"(twl));
         const int tl = tidl % T, gl = tidl / T;
         const int64_t tr = grp * G + gl;
@@ -91,18 +99,18 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
             for (int m = 0; m < E; ++m) v[m] = active ? gload_nt<false>(ia, ia, base + T * m) : c_zero<V>();
             if constexpr (TWREG) ENG::run(v, lds, twr, tidl);
             else ENG::run(v, lds, TwMem<SC, V>(twl), tidl);
-            stage_sync<SH::WAVE>();  // the engine's last reads of LDS are done
+            if constexpr (!RS::SEP) stage_sync<SH::WAVE>();  // the engine's last reads of LDS are done
 #pragma unroll
-            for (int m = 0; m < E; ++m) lds[lds_at<SH::GS>(gl, tl + T * m)] = v[m];
+            for (int m = 0; m < E; ++m) xch[lds_at<SH::GS>(gl, tl + T * m)] = v[m];
             stage_sync<SH::WAVE>();
             if (active) {
                 const int64_t ob0 = tr * (H + 1);
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int k = tl + T * m;
-                    const V mir = lds[lds_at<SH::GS>(gl, (H - k) & (H - 1))];
+                    const V mir = xch[lds_at<SH::GS>(gl, (H - k) & (H - 1))];
                     V ev, wo;
-                    r2c_parts(v[m], mir, twnl[k], ev, wo);
+                    r2c_parts(v[m], mir, wn[m], ev, wo);
                     gstore_nt<SPLIT>(oa, ob, ob0 + k, c_add(ev, wo));
                 }
                 if (tl == 0) gstore_nt<SPLIT>(oa, ob, ob0 + H, cmk(v[0].x - v[0].y, R(0)));
@@ -113,9 +121,9 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = active ? gload_nt<SPLIT>(ia, ib, ib0 + tl + T * m) : c_zero<V>();
             if (active && tl == 0) xh = gload<SPLIT>(ia, ib, ib0 + H);
-            stage_sync<SH::WAVE>();  // the previous transform's reads of LDS are done
+            if constexpr (!RS::SEP) stage_sync<SH::WAVE>();  // the previous transform's reads of LDS are done
 #pragma unroll
-            for (int m = 0; m < E; ++m) lds[lds_at<SH::GS>(gl, tl + T * m)] = v[m];
+            for (int m = 0; m < E; ++m) xch[lds_at<SH::GS>(gl, tl + T * m)] = v[m];
             stage_sync<SH::WAVE>();
 #pragma unroll
             for (int m = 0; m < E; ++m) {
@@ -125,10 +133,10 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
                     a = cmk(a.x, R(0));
                     mir = cmk(xh.x, R(0));
                 } else {
-                    mir = lds[lds_at<SH::GS>(gl, H - k)];
+                    mir = xch[lds_at<SH::GS>(gl, H - k)];
                 }
                 // inverse DFT_H = S DFT_H S: swap on the way in and out
-                v[m] = swap_if<true>(c2r_point(a, mir, twnl[k]));
+                v[m] = swap_if<true>(c2r_point(a, mir, wn[m]));
             }
             if constexpr (TWREG) ENG::run(v, lds, twr, tidl);
             else ENG::run(v, lds, TwMem<SC, V>(twl), tidl);
@@ -171,7 +179,7 @@ RealKernel real_entry() {
     k.eng = engine_info<typename SH::SC>();
     k.threads = SH::THREADS;
     k.per_wg = SH::G;
-    k.lds_bytes = RealShape<LOG2H, LOG2E, WGT>::LDS * sizeof(cplx_t<R>);
+    k.lds_bytes = RealShape<R, LOG2H, LOG2E, WGT>::LDS * sizeof(cplx_t<R>);
     return k;
 }
 
