@@ -98,8 +98,11 @@ fft_status fft_plan_create(fft_plan *out, int64_t n, int64_t batch,
  * "multi:<log2 L1>c<log2 C1>,<log2 L2>c<log2 C2>,..." (one pass per sub-FFT
  * length L_p with C_p columns per workgroup; the log2 L_p sum to log2 n), or
  * "copy" for n = 1 - the strings fft_plan_describe and
- * fft_query_decomposition report.  FFT_ERR_NOT_SUPPORTED if no compiled
- * kernel matches, FFT_ERR_INVALID_ARG if the string does not parse. */
+ * fft_query_decomposition report - or "ops:r<log2 R>", the per-operator
+ * baseline (Table 1's Permute, FusedIKMV, Mul and FusedMKIV as one kernel each,
+ * composed by Eq. 1 with radix R; interleaved only; never chosen by
+ * default).  FFT_ERR_NOT_SUPPORTED if no compiled kernel matches,
+ * FFT_ERR_INVALID_ARG if the string does not parse. */
 fft_status fft_plan_create_explicit(fft_plan *out, int64_t n, int64_t batch,
                                     fft_layout layout, fft_direction dir,
                                     const char *decomposition);
@@ -218,8 +221,8 @@ fft_status fft_query_decomposition(int64_t n, fft_layout layout,
                                    size_t len);
 
 /* Plain streaming copy of `bytes` bytes (multiple of 16, 16-byte aligned
- * pointers) with the same access width as the FFT kernels: the practical HBM
- * ceiling the benchmark reports beside the FFT. */
+ * pointers; nontemporal 16-byte accesses): the practical HBM ceiling the
+ * benchmark reports beside the FFT. */
 fft_status fft_copy_device(const void *src, void *dst, size_t bytes, void *stream);
 
 /* Static description of a status code. */

@@ -74,9 +74,18 @@ k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ t
     if constexpr (TWREG) twr.init(tid % T);
 
     const int64_t groups = (batch + G - 1) / G;
+    // Interleaved data: visit the groups of the two halves of the batch in
+    // alternation (visit 2i -> group i, 2i + 1 -> group half + i), so the
+    // workgroups in flight read two distant streams, as split data does by
+    // itself; measured 1-2 % faster for interleaved, slower for split.
+    const int64_t half = (groups + 1) / 2;
+    auto group_of = [&](int64_t visit) {
+        if constexpr (SPLIT) return visit;
+        else return (visit & 1) ? half + (visit >> 1) : (visit >> 1);
+    };
     // element index of this thread's first point in group grp (row >= batch: none)
-    auto row_base = [&](int64_t grp, int tidl, bool& active) {
-        const int64_t tr = grp * G + tidl / T;
+    auto row_base = [&](int64_t visit, int tidl, bool& active) {
+        const int64_t tr = group_of(visit) * G + tidl / T;
         active = tr < batch;
         return tr * L + tidl % T;
     };
