@@ -190,7 +190,10 @@ fft_status fft_plan_destroy(fft_plan p);
  * kernels over fixed-size tiles (whole small transforms, or one pass of a
  * large one), one launch per pass level so that pass p - 1 of a large
  * transform finishes before pass p starts.  `sizes` is a host array, read
- * during the call only. */
+ * during the call only.  The plan's choices (pass lengths of the large
+ * transforms, persistent grid size, tile order) come from the autotune cache
+ * for this size histogram if present; FFT_AUTOTUNE=1 times every candidate
+ * configuration at creation and records the fastest, as for fft_plan_create. */
 fft_status fft_plan_create_ragged(fft_plan *out, const int64_t *sizes,
                                   int64_t count, fft_layout layout,
                                   fft_direction dir);

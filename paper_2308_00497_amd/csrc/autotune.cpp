@@ -6,11 +6,13 @@
 // (section 3, step 4).  Here every compiled decomposition of a size is timed
 // with HIP events on scratch buffers and the winner is cached on disk.
 #include "autotune.hpp"
+#include "ragged.hpp"
 
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <sys/stat.h>
 #include <unistd.h>
 
 #include <map>
@@ -97,7 +99,8 @@ bool parse_cache_text(const std::string& s, std::vector<std::pair<std::string, s
         skip_ws(s, i);
         if (!read_string(s, i, &val)) return false;
         Decomp d;
-        if (!Decomp::parse(val, &d)) return false;
+        RaggedConfig rc;
+        if (!Decomp::parse(val, &d) && !RaggedConfig::parse(val, &rc)) return false;
         tmp.emplace_back(k, val);
         skip_ws(s, i);
         if (i < s.size() && s[i] == ',') {
@@ -138,6 +141,26 @@ TuneKey make_key(int device, int log2n, int64_t batch, fft_layout layout, int rb
     return TuneKey{buf};
 }
 
+// Ragged batches are keyed by their size histogram (FNV-1a over the count of
+// each log2 size), not by the order of the transforms.
+TuneKey make_ragged_key(int device, const int64_t* sizes, int64_t count, fft_layout layout) {
+    int64_t hist[kMaxLog2N + 1] = {};
+    for (int64_t i = 0; i < count; ++i) {
+        const int k = ilog2_exact(sizes[i]);
+        if (k >= 0 && k <= kMaxLog2N) ++hist[k];
+    }
+    uint64_t h = 1469598103934665603ull;
+    for (int k = 0; k <= kMaxLog2N; ++k)
+        for (int b = 0; b < 8; ++b) {
+            h ^= uint64_t(hist[k] >> (8 * b)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    TuneKey base = make_key(device, 0, count, layout, 4);
+    char buf[64];
+    snprintf(buf, sizeof buf, "|ragged%016llx", static_cast<unsigned long long>(h));
+    return TuneKey{base.s + buf};
+}
+
 bool autotune_enabled() {
     const char* s = getenv("FFT_AUTOTUNE");
     return s && s[0] == '1';
@@ -150,25 +173,32 @@ std::string autotune_cache_path() {
     return std::string(home ? home : "/tmp") + "/.cache/fft_mi355x_autotune.json";
 }
 
-bool autotune_lookup(const TuneKey& key, Decomp* out) {
+bool autotune_lookup_text(const TuneKey& key, std::string* out) {
     std::lock_guard<std::mutex> lk(g_mu);
     load_locked();
     auto it = g_entries.find(key.s);
     if (it == g_entries.end()) return false;
-    return Decomp::parse(it->second, out);
+    *out = it->second;
+    return true;
 }
 
-void autotune_store(const TuneKey& key, const Decomp& d) {
+bool autotune_lookup(const TuneKey& key, Decomp* out) {
+    std::string v;
+    return autotune_lookup_text(key, &v) && Decomp::parse(v, out);
+}
+
+void autotune_store(const TuneKey& key, const Decomp& d) { autotune_store_text(key, d.str()); }
+
+void autotune_store_text(const TuneKey& key, const std::string& value) {
     std::lock_guard<std::mutex> lk(g_mu);
     load_locked();
-    g_entries[key.s] = d.str();
+    g_entries[key.s] = value;
     std::vector<std::pair<std::string, std::string>> e(g_entries.begin(), g_entries.end());
     const std::string path = autotune_cache_path();
     const size_t slash = path.rfind('/');
-    if (slash != std::string::npos) {
-        std::string dir = path.substr(0, slash);
-        // create the parent directory if missing (one level)
-        (void)!system(("mkdir -p '" + dir + "' 2>/dev/null").c_str());
+    if (slash != std::string::npos && slash > 0) {
+        // create the parent directory if missing (one level; no shell)
+        (void)mkdir(path.substr(0, slash).c_str(), 0755);
     }
     const std::string tmp = path + ".tmp" + std::to_string(getpid());
     FILE* f = fopen(tmp.c_str(), "wb");

@@ -146,6 +146,35 @@ void free_plan_memory(fft_plan p) {
     p->ragged = nullptr;
 }
 
+// Pass i of the P-pass chain `dec` (sub-FFT Ns = 2^log2ns): kernels for the
+// two directions, persistent grid, and the table offsets it appends to the
+// plan's engine and FP64 twiddle tables.  src/dst are left to the caller.
+fft_status make_pass_step(fft_plan p, const Decomp& dec, size_t i, int log2ns, bool split, bool inverse_only,
+                          PassStep* st) {
+    const size_t P = dec.log2l.size();
+    *st = PassStep{};
+    st->k = fftk::pass_kernel_for(p->rb, dec.log2l[i], dec.log2c[i], i, P, split, inverse_only);
+    st->k_inv = inverse_only ? st->k : fftk::pass_kernel_for(p->rb, dec.log2l[i], dec.log2c[i], i, P, split, true);
+    if (!st->k || !st->k_inv) return FFT_ERR_NOT_SUPPORTED;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, st->k->kernel, st->k->threads, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    st->grid = per_cu * p->cus;
+    st->log2ns = log2ns;
+    st->twe_off = p->twe_n;
+    p->twe_n += (st->k->eng.tw_size + 1) & ~size_t(1);  // keep 16-byte alignment
+    if (i > 0) {
+        const int log2m = log2ns + dec.log2l[i];
+        st->hbits = (log2m + 1) / 2;
+        st->ta_off = p->tw64_n;
+        p->tw64_n += size_t(1) << (log2m - st->hbits);
+        st->tb_off = p->tw64_n;
+        p->tw64_n += size_t(1) << st->hbits;
+    }
+    return FFT_OK;
+}
+
 // Resolve kernels, lay out the tables and the workspace for `dec`.
 fft_status resolve(fft_plan p, const Decomp& dec) {
     const bool split = p->layout == FFT_LAYOUT_SPLIT;
@@ -183,28 +212,10 @@ fft_status resolve(fft_plan p, const Decomp& dec) {
             const size_t P = dec.log2l.size();
             int log2ns = 0;
             for (size_t i = 0; i < P; ++i) {
-                PassStep st{};
+                PassStep st;
                 const bool first = i == 0, last = i == P - 1;
-                st.k = fftk::pass_kernel_for(p->rb, dec.log2l[i], dec.log2c[i], i, P, split, false);
-                st.k_inv = fftk::pass_kernel_for(p->rb, dec.log2l[i], dec.log2c[i], i, P, split, true);
-                if (!st.k || !st.k_inv) return FFT_ERR_NOT_SUPPORTED;
-                int per_cu = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, st.k->kernel, st.k->threads, 0) !=
-                        hipSuccess ||
-                    per_cu < 1)
-                    per_cu = 1;
-                st.grid = per_cu * p->cus;
-                st.log2ns = log2ns;
-                st.twe_off = p->twe_n;
-                p->twe_n += (st.k->eng.tw_size + 1) & ~size_t(1);  // keep 16-byte alignment
-                if (!first) {
-                    const int log2m = log2ns + dec.log2l[i];
-                    st.hbits = (log2m + 1) / 2;
-                    st.ta_off = p->tw64_n;
-                    p->tw64_n += size_t(1) << (log2m - st.hbits);
-                    st.tb_off = p->tw64_n;
-                    p->tw64_n += size_t(1) << st.hbits;
-                }
+                const fft_status rs = make_pass_step(p, dec, i, log2ns, split, false, &st);
+                if (rs != FFT_OK) return rs;
                 // ping-pong between two workspace halves; the last pass writes the output
                 st.src = first ? 0 : ((i - 1) % 2 == 0 ? 1 : 2);
                 st.dst = last ? 3 : (i % 2 == 0 ? 1 : 2);
@@ -255,28 +266,11 @@ fft_status resolve_real(fft_plan p, const Decomp& dec) {
             int log2ns = 0;
             int prev = c2r ? 1 : 0;  // C2R starts from the pre pass's output in workspace A
             for (size_t i = 0; i < P; ++i) {
-                PassStep st{};
-                const bool first = i == 0, last = i == P - 1;
-                st.k = fftk::pass_kernel_for(p->rb, dec.log2l[i], dec.log2c[i], i, P, false, c2r);
-                st.k_inv = st.k;
-                if (!st.k) return FFT_ERR_NOT_SUPPORTED;
-                int per_cu = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, st.k->kernel, st.k->threads, 0) !=
-                        hipSuccess ||
-                    per_cu < 1)
-                    per_cu = 1;
-                st.grid = per_cu * p->cus;
-                st.log2ns = log2ns;
-                st.twe_off = p->twe_n;
-                p->twe_n += (st.k->eng.tw_size + 1) & ~size_t(1);
-                if (!first) {
-                    const int log2m = log2ns + dec.log2l[i];
-                    st.hbits = (log2m + 1) / 2;
-                    st.ta_off = p->tw64_n;
-                    p->tw64_n += size_t(1) << (log2m - st.hbits);
-                    st.tb_off = p->tw64_n;
-                    p->tw64_n += size_t(1) << st.hbits;
-                }
+                PassStep st;
+                const bool last = i == P - 1;
+                // the chain runs in one direction only: forward (R2C) or inverse (C2R)
+                const fft_status rs = make_pass_step(p, dec, i, log2ns, false, c2r, &st);
+                if (rs != FFT_OK) return rs;
                 st.src = prev;
                 st.dst = (c2r && last) ? 3 : (prev == 1 ? 2 : 1);
                 prev = st.dst;
@@ -637,7 +631,7 @@ std::string describe(fft_plan p) {
     s += buf;
     if (p->ragged) {
         s += fftk::ragged_describe(p->ragged);
-        s += "}";
+        s += ", \"source\": \"" + p->source + "\"}";
         return s;
     }
     if (p->rank > 1) {
@@ -995,13 +989,41 @@ fft_status fft_plan_create_ragged(fft_plan* out, const int64_t* sizes, int64_t c
     p->dir = dir;
     p->elements = total;
     p->flops = flops;
-    p->source = "ragged";
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) {
         delete p;
         return fail_hip(e, "hipGetDevice");
     }
-    fft_status st = fftk::ragged_create(sizes, count, layout, &p->ragged, &g_detail);
+    // configuration: the cached winner for this size histogram, else the
+    // default; FFT_AUTOTUNE=1 times every candidate and caches the fastest
+    fftk::RaggedConfig cfg;
+    const fftk::TuneKey key = fftk::make_ragged_key(p->device, sizes, count, layout);
+    std::string cached;
+    p->source = "default";
+    if (fftk::autotune_lookup_text(key, &cached) && fftk::RaggedConfig::parse(cached, &cfg)) {
+        p->source = "cache";
+    } else if (fftk::autotune_enabled()) {
+        float best_ms = 1e30f;
+        fftk::RaggedConfig best = cfg;
+        for (const fftk::RaggedConfig& c : fftk::ragged_candidates()) {
+            fftk::RaggedPlan* trial = nullptr;
+            std::string det;
+            if (fftk::ragged_create(sizes, count, layout, c, &trial, &det) != FFT_OK) continue;
+            float ms = 0.f;
+            const fft_status ts = fftk::ragged_time(trial, &ms, &det);
+            fftk::ragged_destroy(trial);
+            if (ts != FFT_OK) continue;
+            if (getenv("FFT_LOG")) fprintf(stderr, "[fft autotune] %s %s %.4f ms\n", key.s.c_str(), c.str().c_str(), ms);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+        cfg = best;
+        fftk::autotune_store_text(key, cfg.str());
+        p->source = "autotune";
+    }
+    fft_status st = fftk::ragged_create(sizes, count, layout, cfg, &p->ragged, &g_detail);
     if (st != FFT_OK) {
         p->magic = kDeadMagic;
         delete p;

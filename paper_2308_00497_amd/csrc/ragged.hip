@@ -246,6 +246,7 @@ int engine_tw_size() {
 }  // namespace
 
 struct RaggedPlan {
+    RaggedConfig cfg;
     int64_t count = 0, total = 0;
     fft_layout layout = FFT_LAYOUT_INTERLEAVED;
     int device = 0;
@@ -360,11 +361,45 @@ fft_status build_graph(RaggedPlan* r, int variant, std::string* detail) {
 
 }  // namespace
 
-fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout, RaggedPlan** out,
-                         std::string* detail) {
+std::string RaggedConfig::str() const {
+    char buf[48];
+    snprintf(buf, sizeof buf, "ragged:p%d:g%d:o%d", max_pass_log2, grid_eighths, smallest_first ? 1 : 0);
+    return buf;
+}
+
+bool RaggedConfig::parse(const std::string& s, RaggedConfig* out) {
+    int p = 0, g = 0, o = 0, used = 0;
+    if (sscanf(s.c_str(), "ragged:p%d:g%d:o%d%n", &p, &g, &o, &used) != 3 || used != static_cast<int>(s.size()))
+        return false;
+    if (p < 6 || p > kMaxPassLog2 || g < 1 || g > 8 || (o != 0 && o != 1)) return false;
+    out->max_pass_log2 = p;
+    out->grid_eighths = g;
+    out->smallest_first = o == 1;
+    return true;
+}
+
+std::vector<RaggedConfig> ragged_candidates() {
+    std::vector<RaggedConfig> v;
+    for (int p : {8, 7, 6})
+        for (int g : {8, 6, 4})
+            for (int o : {0, 1}) {
+                RaggedConfig c;
+                c.max_pass_log2 = p;
+                c.grid_eighths = g;
+                c.smallest_first = o == 1;
+                v.push_back(c);
+            }
+    return v;
+}
+
+const RaggedConfig& ragged_config(const RaggedPlan* r) { return r->cfg; }
+
+fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout, const RaggedConfig& cfg,
+                         RaggedPlan** out, std::string* detail) {
     *out = nullptr;
     RaggedPlan* r = new (std::nothrow) RaggedPlan;
     if (!r) return FFT_ERR_ALLOC;
+    r->cfg = cfg;
     r->count = count;
     r->layout = layout;
     hipError_t e = hipGetDevice(&r->device);
@@ -436,7 +471,11 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
         ws_elems += sizes[i];
         const int n = lg[i];
         if (parts[n].empty()) {
-            parts[n] = even_parts(n, (n + kMaxPassLog2 - 1) / kMaxPassLog2);
+            // passes of at most 2^max_pass_log2 points (and at least 2^5, at most
+            // three passes, at most 2^8 points)
+            int np = std::max((n + cfg.max_pass_log2 - 1) / cfg.max_pass_log2, (n + kMaxPassLog2 - 1) / kMaxPassLog2);
+            np = std::min(np, std::min(RaggedPlan::kMaxLevels, n / kMinPassLog2));
+            parts[n] = even_parts(n, np);
             int log2ns = 0;
             for (size_t p = 0; p < parts[n].size(); ++p) {
                 PassTab t{};
@@ -460,7 +499,9 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
     std::vector<RaggedTile>& tiles = r->htiles;
     std::vector<int64_t> toffs;
     // largest transforms first within each phase
-    std::stable_sort(multi.begin(), multi.end(), [&](int64_t a, int64_t b) { return lg[a] > lg[b]; });
+    std::stable_sort(multi.begin(), multi.end(), [&](int64_t a, int64_t b) {
+        return cfg.smallest_first ? lg[a] < lg[b] : lg[a] > lg[b];
+    });
     auto pass_tiles = [&](size_t p) {
         for (int64_t i : multi) {
             const int n = lg[i];
@@ -574,7 +615,7 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel_for(layout == FFT_LAYOUT_SPLIT, false)),
                                                      kThreads, 0);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
-    const int64_t want = int64_t(per_cu) * cus;
+    const int64_t want = std::max<int64_t>(1, int64_t(per_cu) * cus * cfg.grid_eighths / 8);
     for (int l = 0; l < r->nlevels; ++l) {
         const int64_t nt = int64_t(r->level_begin[l + 1]) - r->level_begin[l];
         r->level_grid[l] = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, nt)));
@@ -636,6 +677,40 @@ fft_status ragged_execute(RaggedPlan* r, const float* ia, const float* ib, float
     return FFT_OK;
 }
 
+fft_status ragged_time(RaggedPlan* r, float* ms, std::string* detail) {
+    const size_t bytes = size_t(r->total) * sizeof(float2);
+    void *in = nullptr, *out = nullptr;
+    hipError_t e = hipMalloc(&in, bytes);
+    if (e == hipSuccess) e = hipMalloc(&out, bytes);
+    if (e == hipSuccess) e = hipMemset(in, 0, bytes);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    fft_status st = e == hipSuccess ? FFT_OK : hip_err(e, "ragged autotune scratch", detail);
+    const bool split = r->layout == FFT_LAYOUT_SPLIT;
+    const float* ia = static_cast<const float*>(in);
+    const float* ib = split ? ia + r->total : nullptr;
+    float* oa = static_cast<float*>(out);
+    float* ob = split ? oa + r->total : nullptr;
+    for (int i = 0; i < 2 && st == FFT_OK; ++i) st = ragged_execute(r, ia, ib, oa, ob, false, nullptr, detail);
+    const int reps = 5;
+    if (st == FFT_OK) {
+        e = hipEventRecord(e0, nullptr);
+        for (int i = 0; i < reps && st == FFT_OK; ++i) st = ragged_execute(r, ia, ib, oa, ob, false, nullptr, detail);
+        if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        *ms = t / reps;
+        if (st == FFT_OK && e != hipSuccess) st = hip_err(e, "ragged autotune timing", detail);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (in) (void)hipFree(in);
+    if (out) (void)hipFree(out);
+    return st;
+}
+
 void ragged_destroy(RaggedPlan* r) {
     if (!r) return;
     (void)hipDeviceSynchronize();
@@ -677,7 +752,7 @@ std::string ragged_describe(const RaggedPlan* r) {
              (long long)r->count, (long long)r->total, r->htiles.size(), r->nsingle_tiles, r->npass_tiles,
              r->ncopy_tiles, r->nmulti, r->nlevels, r->grid, kThreads, size_t(kLds) * sizeof(float2),
              r->ws_half * r->ws_regions);
-    return std::string(buf) + r->classes + "}";
+    return std::string(buf) + r->classes + "}, \"config\": \"" + r->cfg.str() + "\"";
 }
 
 }  // namespace fftk

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/fft.h"
 
@@ -13,8 +14,28 @@ namespace fftk {
 
 struct RaggedPlan;
 
-fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout, RaggedPlan** out,
-                         std::string* detail);
+// The tunable choices of a ragged plan (the autotuner times combinations):
+//   max_pass_log2   longest pass sub-FFT of the multi-pass transforms, 2^6 .. 2^8
+//                   (more, shorter passes trade HBM passes for wider column tiles)
+//   grid_eighths    persistent workgroups per launch, in eighths of the number
+//                   that can be resident at once
+//   smallest_first  order of the multi-pass transforms within a level
+struct RaggedConfig {
+    int max_pass_log2 = 8;
+    int grid_eighths = 8;
+    bool smallest_first = false;
+    std::string str() const;  // "ragged:p8:g8:o0"
+    static bool parse(const std::string& s, RaggedConfig* out);
+};
+
+// every configuration the autotuner tries
+std::vector<RaggedConfig> ragged_candidates();
+
+fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout, const RaggedConfig& cfg,
+                         RaggedPlan** out, std::string* detail);
+// average time of one execution on scratch buffers of the plan's size
+fft_status ragged_time(RaggedPlan* r, float* ms, std::string* detail);
+const RaggedConfig& ragged_config(const RaggedPlan* r);
 // swap: exchange re/im of interleaved data in the kernel (the inverse); split
 // callers already exchanged their pointers
 fft_status ragged_execute(RaggedPlan* r, const float* ia, const float* ib, float* oa, float* ob, bool swap,

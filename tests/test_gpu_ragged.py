@@ -156,3 +156,38 @@ def test_ragged_workspace_override(fftlib):
         plan.set_workspace(ws)
         y = from_device(plan.execute(to_device(re, im, "interleaved")), "interleaved")
     assert per_item_errors(y, ragged_oracle(sizes, offsets, re, im, "forward"), sizes, offsets).max() <= TOL
+
+
+def test_ragged_autotune_and_every_config(fftlib, tmp_path, monkeypatch):
+    """FFT_AUTOTUNE=1 times every ragged configuration and caches the winner
+    under the batch's size histogram; each configuration, forced through a
+    cache file, computes the same transforms to the oracle's tolerance."""
+    import json
+    sizes, offsets, re, im = make([1 << k for k in (6, 14, 9, 16, 12, 18, 15, 20)] * 3, 48)
+    ref = ragged_oracle(sizes, offsets, re, im, "forward")
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("FFT_AUTOTUNE_CACHE", str(cache))
+    monkeypatch.setenv("FFT_AUTOTUNE", "1")
+    with fftlib.RaggedPlan(sizes, "interleaved", "forward") as plan:
+        d = plan.describe()
+        y = from_device(plan.execute(to_device(re, im, "interleaved")), "interleaved")
+    assert d["source"] == "autotune"
+    assert per_item_errors(y, ref, sizes, offsets).max() <= TOL
+    entries = json.loads(cache.read_text())["entries"]
+    keys = [k for k in entries if "ragged" in k]
+    assert len(keys) == 1 and entries[keys[0]] == d["config"]
+    monkeypatch.setenv("FFT_AUTOTUNE", "0")
+    i = 0
+    for p in (8, 7, 6):
+        for g in (8, 6, 4):
+            for o in (0, 1):
+                cfg = f"ragged:p{p}:g{g}:o{o}"
+                forced = tmp_path / f"forced{i}.json"
+                i += 1
+                forced.write_text(json.dumps({"version": 1, "entries": {keys[0]: cfg}}))
+                monkeypatch.setenv("FFT_AUTOTUNE_CACHE", str(forced))
+                with fftlib.RaggedPlan(sizes, "interleaved", "forward") as plan:
+                    d = plan.describe()
+                    y = from_device(plan.execute(to_device(re, im, "interleaved")), "interleaved")
+                assert d["source"] == "cache" and d["config"] == cfg
+                assert per_item_errors(y, ref, sizes, offsets).max() <= TOL, cfg
