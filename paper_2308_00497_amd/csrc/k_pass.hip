@@ -19,8 +19,8 @@ namespace fftk {
 
 static const PassKernel kPass[] = {
     FFT_P(6, 4), FFT_P(6, 6), FFT_P(6, 7),
-    FFT_P(7, 4), FFT_P(7, 5), FFT_P(7, 6),
-    FFT_P(8, 3), FFT_P(8, 4), FFT_P(8, 5),
+    FFT_P(7, 4), FFT_P(7, 5), FFT_P(7, 6), FFT_P(7, 7),
+    FFT_P(8, 3), FFT_P(8, 4), FFT_P(8, 5), FFT_P(8, 6),
     FFT_P(9, 3), FFT_P(9, 4),
     FFT_P(10, 2), FFT_P(10, 3),
     FFT_P(11, 2),

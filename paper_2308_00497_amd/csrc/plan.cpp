@@ -246,20 +246,21 @@ Decomp default_decomposition(int log2n, int rb) {
         d.twreg = table[log2n].twreg == 1;
         return d;
     }
-    // multi-pass chains measured fastest on MI355X (batches of 2^25 elements)
+    // multi-pass chains measured fastest on MI355X (batches of 2^25 elements,
+    // the lower mean over both layouts)
     static const char* measured[kMaxLog2N + 1] = {
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
         nullptr, nullptr, nullptr, nullptr, nullptr,
         "multi:9c4,6c6",          // 2^15
-        "multi:8c5,8c4",          // 2^16
+        "multi:8c5,8c6",          // 2^16
         "multi:9c4,8c5",          // 2^17
-        "multi:9c4,9c4",          // 2^18
-        "multi:11c2,8c5",         // 2^19
-        "multi:8c5,6c6,6c7",      // 2^20
-        "multi:7c6,7c6,7c6",      // 2^21
-        "multi:8c5,7c6,7c6",      // 2^22
-        "multi:8c5,8c5,7c6",      // 2^23
-        "multi:8c5,8c5,8c5",      // 2^24
+        "multi:10c3,8c6",         // 2^18
+        "multi:7c7,6c6,6c7",      // 2^19
+        "multi:8c6,6c6,6c7",      // 2^20
+        "multi:7c7,7c6,7c7",      // 2^21
+        "multi:8c6,7c7,7c6",      // 2^22
+        "multi:8c6,8c6,7c6",      // 2^23
+        "multi:8c5,8c6,8c5",      // 2^24
     };
     if (measured[log2n] && Decomp::parse(measured[log2n], &d)) return d;
     // otherwise passes of at most 2^9 points with 16-column tiles (128-byte runs)
