@@ -30,6 +30,11 @@ static const SingleKernel kSingle[] = {
     FFT_S(12, 4, 256), FFT_S(12, 3, 256),
     FFT_S(13, 4, 256), FFT_S(13, 3, 256),
     FFT_S1(14, 4, 256, false),
+    // one workgroup per CU at 2^14 (LDS): prefetching the next transform pays there
+    single_entry<float, 14, 4, 256, false, false, false, true>(), single_entry<float, 14, 4, 256, false, true, false, true>(),
+    single_entry<float, 14, 4, 256, true, false, false, true>(),
+    single_entry<float, 13, 4, 256, false, false, true, true>(), single_entry<float, 13, 4, 256, false, true, true, true>(),
+    single_entry<float, 13, 4, 256, true, false, true, true>(),
 };
 
 #undef FFT_S

@@ -28,6 +28,11 @@ static const SingleKernel kSingle64[] = {
     FFT_D(11, 4, 256), FFT_D(11, 3, 256),
     FFT_D1(12, 4, 256, false), FFT_D(12, 3, 256),
     FFT_D1(13, 4, 256, false), FFT_D1(13, 3, 256, false),
+    // prefetching variants where LDS allows one or two workgroups per CU
+    single_entry<double, 13, 4, 256, false, false, false, true>(), single_entry<double, 13, 4, 256, false, true, false, true>(),
+    single_entry<double, 13, 4, 256, true, false, false, true>(),
+    single_entry<double, 12, 3, 256, false, false, true, true>(), single_entry<double, 12, 3, 256, false, true, true, true>(),
+    single_entry<double, 12, 3, 256, true, false, true, true>(),
 };
 
 #undef FFT_D

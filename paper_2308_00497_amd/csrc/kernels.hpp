@@ -165,7 +165,7 @@ EngineInfo engine_info() {
     return e;
 }
 
-template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG>
+template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false>
 SingleKernel single_entry() {
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
     SingleKernel k{};
@@ -176,8 +176,9 @@ SingleKernel single_entry() {
     k.split = SPLIT;
     k.swap = SWAP;
     k.twreg = TWREG;
-    k.fn = &launch_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG>;
-    k.kernel = reinterpret_cast<const void*>(&k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG>);
+    k.pf = PF;
+    k.fn = &launch_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF>;
+    k.kernel = reinterpret_cast<const void*>(&k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF>);
     k.eng = engine_info<typename SH::SC>();
     k.threads = SH::THREADS;
     k.per_wg = SH::G;

@@ -27,7 +27,7 @@ std::string Decomp::str() const {
         case COPY:
             return "copy";
         case SINGLE:
-            snprintf(buf, sizeof buf, "single:e%d:w%d:g%d:r%d", log2e, wgt, gmul, twreg ? 1 : 0);
+            snprintf(buf, sizeof buf, "single:e%d:w%d:g%d:r%d%s", log2e, wgt, gmul, twreg ? 1 : 0, pf ? ":p1" : "");
             return buf;
         case OPS:
             snprintf(buf, sizeof buf, "ops:r%d", log2r);
@@ -51,14 +51,18 @@ bool Decomp::parse(const std::string& s, Decomp* out) {
         *out = d;
         return true;
     }
-    int e = 0, w = 0, g = 0, r = 0, used = 0;
-    if (sscanf(s.c_str(), "single:e%d:w%d:g%d:r%d%n", &e, &w, &g, &r, &used) == 4 && used == (int)s.size()) {
+    int e = 0, w = 0, g = 0, r = 0, pf = 0, used = 0;
+    const bool five = sscanf(s.c_str(), "single:e%d:w%d:g%d:r%d:p%d%n", &e, &w, &g, &r, &pf, &used) == 5 &&
+                      used == (int)s.size();
+    if (five || (sscanf(s.c_str(), "single:e%d:w%d:g%d:r%d%n", &e, &w, &g, &r, &used) == 4 && used == (int)s.size())) {
         if (g < 1 || g > 64 || (r != 0 && r != 1)) return false;
+        if (five && pf != 1) return false;  // ":p0" is spelled by leaving the field out
         d.kind = SINGLE;
         d.log2e = e;
         d.wgt = w;
         d.gmul = g;
         d.twreg = r == 1;
+        d.pf = five;
         *out = d;
         return true;
     }
@@ -89,13 +93,13 @@ bool Decomp::parse(const std::string& s, Decomp* out) {
     return false;
 }
 
-const SingleKernel* find_single(int rb, int log2n, int log2e, int wgt, bool split, bool swap, bool twreg) {
+const SingleKernel* find_single(int rb, int log2n, int log2e, int wgt, bool split, bool swap, bool twreg, bool pf) {
     int cnt = 0;
     const SingleKernel* t = rb == 8 ? single_kernels64(&cnt) : single_kernels(&cnt);
     const int le = log2e < log2n ? log2e : log2n;
     for (int i = 0; i < cnt; ++i)
         if (t[i].log2n == log2n && t[i].log2e == le && t[i].wgt == wgt && t[i].split == split && t[i].swap == swap &&
-            t[i].twreg == twreg)
+            t[i].twreg == twreg && t[i].pf == pf)
             return &t[i];
     return nullptr;
 }
@@ -118,7 +122,7 @@ const PassKernel* pass_kernel_for(int rb, int log2l, int log2c, size_t p, size_t
 }
 
 const SingleKernel* single_kernel_for(int rb, int log2n, const Decomp& d, bool split, bool inverse) {
-    return find_single(rb, log2n, d.log2e, d.wgt, split, inverse && !split, d.twreg);
+    return find_single(rb, log2n, d.log2e, d.wgt, split, inverse && !split, d.twreg, d.pf);
 }
 
 // column tile for a sub-FFT length: the widest compiled one up to 128-byte
@@ -189,10 +193,10 @@ static std::vector<int> even_split(int log2n, int parts) {
 // FP64 defaults, measured on MI355X (batches of 2^24 elements, the faster on
 // average over both layouts): single-pass up to 2^13, then passes
 static Decomp default_decomposition64(int log2n) {
-    static const struct { int log2e, wgt, gmul, twreg; } single[14] = {
-        {4, 256, 1, 1}, {4, 256, 2, 0}, {4, 64, 3, 0}, {4, 64, 1, 0}, {3, 256, 8, 1},  // 2^0 .. 2^4
-        {3, 256, 8, 1}, {3, 256, 1, 1}, {3, 64, 3, 1}, {3, 64, 3, 1}, {3, 64, 4, 1},   // 2^5 .. 2^9
-        {3, 256, 2, 1}, {3, 256, 2, 1}, {3, 256, 1, 1}, {4, 256, 2, 0},                // 2^10 .. 2^13
+    static const struct { int log2e, wgt, gmul, twreg, pf; } single[14] = {
+        {4, 256, 1, 1, 0}, {4, 256, 2, 0, 0}, {4, 64, 3, 0, 0}, {4, 64, 1, 0, 0}, {3, 256, 8, 1, 0},  // 2^0 .. 2^4
+        {3, 256, 8, 1, 0}, {3, 256, 1, 1, 0}, {3, 64, 3, 1, 0}, {3, 64, 3, 1, 0}, {3, 64, 4, 1, 0},   // 2^5 .. 2^9
+        {3, 256, 2, 1, 0}, {3, 256, 2, 1, 0}, {3, 256, 1, 1, 1}, {4, 256, 1, 0, 1},                   // 2^10 .. 2^13
     };
     static const char* multi[kMaxLog2N + 1] = {
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
@@ -218,6 +222,7 @@ static Decomp default_decomposition64(int log2n) {
         d.wgt = single[log2n].wgt;
         d.gmul = single[log2n].gmul;
         d.twreg = single[log2n].twreg == 1;
+        d.pf = single[log2n].pf == 1;
     } else {
         Decomp::parse(multi[log2n], &d);
     }
@@ -234,16 +239,17 @@ Decomp default_decomposition(int log2n, int rb) {
     if (log2n <= 14) {
         // single-pass shapes measured fastest on MI355X (batches of 2^25
         // elements, both layouts); the autotuner refines them per device
-        static const struct { int log2e, gmul, twreg; } table[15] = {
-            {4, 1, 1}, {4, 8, 1}, {4, 8, 1}, {4, 8, 1}, {3, 8, 1},  // 2^0 .. 2^4
-            {3, 8, 1}, {3, 8, 1}, {3, 2, 1}, {3, 2, 1}, {3, 2, 1},  // 2^5 .. 2^9
-            {3, 2, 1}, {3, 2, 1}, {4, 2, 1}, {4, 3, 1}, {4, 8, 0},  // 2^10 .. 2^14
+        static const struct { int log2e, gmul, twreg, pf; } table[15] = {
+            {4, 1, 1, 0}, {4, 8, 1, 0}, {4, 8, 1, 0}, {4, 8, 1, 0}, {3, 8, 1, 0},  // 2^0 .. 2^4
+            {3, 8, 1, 0}, {3, 8, 1, 0}, {3, 2, 1, 0}, {3, 2, 1, 0}, {3, 2, 1, 0},  // 2^5 .. 2^9
+            {3, 2, 1, 0}, {3, 2, 1, 0}, {4, 2, 1, 0}, {4, 4, 1, 0}, {4, 4, 0, 1},  // 2^10 .. 2^14
         };
         d.kind = Decomp::SINGLE;
         d.log2e = table[log2n].log2e;
         d.wgt = 256;
         d.gmul = table[log2n].gmul;
         d.twreg = table[log2n].twreg == 1;
+        d.pf = table[log2n].pf == 1;
         return d;
     }
     // multi-pass chains measured fastest on MI355X (batches of 2^25 elements,
@@ -368,23 +374,25 @@ std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int r
     std::vector<const SingleKernel*> shapes;
     for (int e : {4, 3})
         for (int w : {256, 64})
-            for (int r : {1, 0}) {
-                const SingleKernel* k = find_single(rb, log2n, e, w, false, false, r == 1);
-                if (!k) continue;
-                bool dup = false;
-                for (auto* o : shapes) dup |= (o == k);
-                if (dup) continue;
-                shapes.push_back(k);
-                for (int g : {1, 2, 3, 4, 8}) {
-                    Decomp d;
-                    d.kind = Decomp::SINGLE;
-                    d.log2e = e;
-                    d.wgt = w;
-                    d.gmul = g;
-                    d.twreg = r == 1;
-                    if (decomposition_available(d, log2n, layout, rb)) out.push_back(d);
+            for (int r : {1, 0})
+                for (int pf : {0, 1}) {
+                    const SingleKernel* k = find_single(rb, log2n, e, w, false, false, r == 1, pf == 1);
+                    if (!k) continue;
+                    bool dup = false;
+                    for (auto* o : shapes) dup |= (o == k);
+                    if (dup) continue;
+                    shapes.push_back(k);
+                    for (int g : {1, 2, 3, 4, 8}) {
+                        Decomp d;
+                        d.kind = Decomp::SINGLE;
+                        d.log2e = e;
+                        d.wgt = w;
+                        d.gmul = g;
+                        d.twreg = r == 1;
+                        d.pf = pf == 1;
+                        if (decomposition_available(d, log2n, layout, rb)) out.push_back(d);
+                    }
                 }
-            }
     // multi-pass chains with 2 or 3 passes, every sub-length and tile compiled
     int cnt = 0;
     const PassKernel* t = rb == 8 ? pass_kernels64(&cnt) : pass_kernels(&cnt);

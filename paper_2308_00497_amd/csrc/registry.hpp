@@ -37,6 +37,7 @@ struct SingleKernel {
     bool split;
     bool swap;      // swaps re/im of interleaved data on load and store (inverse)
     bool twreg;     // stage twiddles held in registers
+    bool pf;        // next transform's loads issued before the current one's stages
     single_fn fn;
     const void* kernel;  // the __global__ function (occupancy queries)
     EngineInfo eng;
