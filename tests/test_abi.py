@@ -82,6 +82,21 @@ def test_explicit_decomposition_validation(lib):
     assert lib.fft_plan_create_explicit(ctypes.byref(h), 4096, 1, 0, -1, None) == 3
 
 
+def test_prefetch_decomposition_strings(lib, fftlib):
+    """":p1" selects the prefetching single-pass kernel; it exists only where
+    compiled (FP32 2^13, 2^14; FP64 2^12, 2^13) and ":p0" is not a spelling."""
+    h = ctypes.c_void_p()
+    ex = lib.fft_plan_create_ex
+    assert ex(ctypes.byref(h), 4096, 1, 0, -1, 0, b"single:e4:w256:g2:r1:p0") == 2
+    assert ex(ctypes.byref(h), 4096, 1, 0, -1, 0, b"single:e4:w256:g2:r1:p2") == 2
+    assert ex(ctypes.byref(h), 4096, 1, 0, -1, 0, b"single:e4:w256:g2:r1:p1") == 7
+    assert ex(ctypes.byref(h), 1 << 14, 1, 0, -1, 1, b"single:e4:w256:g1:r0:p1") == 7   # FP64 has no 2^14
+    q32 = fftlib.query_decomposition(1 << 14, "split", "fp32")
+    assert q32["default"].endswith(":p1") and any(c.endswith(":p1") for c in q32["candidates"])
+    q64 = fftlib.query_decomposition(1 << 12, "interleaved", "fp64")
+    assert q64["default"] == "single:e3:w256:g1:r1:p1"
+
+
 def test_create_ex_validation(lib):
     """Precision argument: unknown values are rejected; FP64 has its own kernel
     set (single-pass up to 2^13, 8-column pass tiles), checked before any HIP call."""
