@@ -198,6 +198,21 @@ fft_status fft_plan_create_ragged(fft_plan *out, const int64_t *sizes,
                                   int64_t count, fft_layout layout,
                                   fft_direction dir);
 
+/* fft_plan_create_ragged with an explicit configuration (the autotuner's
+ * choices, bypassing cache and tuning): "ragged:p<P>:g<G>:o<O>[:w<W>]" with
+ *   P  longest pass sub-FFT of the multi-pass transforms, 2^6 .. 2^8 (6..8)
+ *   G  persistent workgroups per level, in eighths of the resident maximum (1..8)
+ *   O  1: smallest multi-pass transforms first within a level, 0: largest
+ *   W  pipelined groups of at most W MiB of workspace (8..65536): group g's
+ *      pass p runs in level g + p, so each level reads what the previous one
+ *      wrote while it can still be cached; the workspace is a ring of two
+ *      group-sized slots.  Absent: every pass p in level p.
+ * config NULL behaves as fft_plan_create_ragged.  A string that does not
+ * parse is FFT_ERR_INVALID_ARG. */
+fft_status fft_plan_create_ragged_ex(fft_plan *out, const int64_t *sizes,
+                                     int64_t count, fft_layout layout,
+                                     fft_direction dir, const char *config);
+
 /* Bytes of device workspace the plan uses (0 for single-pass plans). */
 fft_status fft_plan_workspace_bytes(fft_plan p, size_t *bytes);
 

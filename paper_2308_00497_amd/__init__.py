@@ -196,15 +196,19 @@ class PlanND(_PlanBase):
 
 
 class RaggedPlan(_PlanBase):
-    """Transforms of the given power-of-two sizes packed back to back, one launch."""
+    """Transforms of the given power-of-two sizes packed back to back, one graph launch.
 
-    def __init__(self, sizes, layout: str = "interleaved", direction: str = "forward"):
+    `config` ("ragged:p8:g8:o0[:w64]") fixes the plan's configuration instead
+    of the cached, default or autotuned one."""
+
+    def __init__(self, sizes, layout: str = "interleaved", direction: str = "forward", config: str | None = None):
         super().__init__(layout, direction)
         sizes = [int(s) for s in sizes]
         arr = (ctypes.c_int64 * len(sizes))(*sizes)
         h = ctypes.c_void_p()
-        check(lib.fft_plan_create_ragged(ctypes.byref(h), arr, len(sizes), _LAYOUTS[layout], _DIRS[direction]),
-              "fft_plan_create_ragged")
+        check(lib.fft_plan_create_ragged_ex(ctypes.byref(h), arr, len(sizes), _LAYOUTS[layout], _DIRS[direction],
+                                            None if config is None else config.encode()),
+              "fft_plan_create_ragged_ex")
         self._handle = h
         self.sizes_list = sizes
 

@@ -41,6 +41,7 @@ EXPORTS = [
     "fft_execute_backward",
     "fft_plan_destroy",
     "fft_plan_create_ragged",
+    "fft_plan_create_ragged_ex",
     "fft_plan_workspace_bytes",
     "fft_plan_set_workspace",
     "fft_plan_sizes",
@@ -75,6 +76,7 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.fft_execute_backward.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.fft_plan_destroy.argtypes = [vp]
     lib.fft_plan_create_ragged.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), i64, ci, ci]
+    lib.fft_plan_create_ragged_ex.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), i64, ci, ci, ctypes.c_char_p]
     lib.fft_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.fft_plan_set_workspace.argtypes = [vp, vp]
     lib.fft_plan_sizes.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]

@@ -434,9 +434,10 @@ fft_status run_real(fft_plan p, const void* ia, const void* ib, void* oa, void* 
             for (const PassStep& st : p->steps) {
                 const void* src = st.src == 0 ? ia : ws[st.src];
                 void* dst = st.dst == 3 ? oa : ws[st.dst];
+                const int stream = (st.src == 0 ? fftk::kStreamIn : 0) | (st.dst == 3 ? fftk::kStreamOut : 0);
                 e = st.k->fn(src, nullptr, dst, nullptr, static_cast<const char*>(p->twe) + st.twe_off * p->cbytes(),
                              p->tw64 + st.ta_off, p->tw64 + st.tb_off, p->log2h, st.log2ns, st.hbits, p->batch,
-                             st.grid, s);
+                             st.grid, stream, s);
                 if (e != hipSuccess) return fail_hip(e, "pass launch");
                 last = st.dst;
             }
@@ -608,10 +609,13 @@ fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, v
                     da = stp.dst == 1 ? wsa : wsb;
                 }
                 const fftk::PassKernel* k = inverse ? stp.k_inv : stp.k;
+                // the caller's buffers are streamed; the workspace between
+                // passes stays cacheable for the next pass
+                const int stream = (stp.src == 0 ? fftk::kStreamIn : 0) | (stp.dst == 3 ? fftk::kStreamOut : 0);
                 e = k->fn(sa, sb, da, db, static_cast<const char*>(p->twe) + stp.twe_off * p->cbytes(),
                           p->tw64 ? p->tw64 + stp.ta_off : nullptr,
                           p->tw64 ? p->tw64 + stp.tb_off : nullptr, p->log2n, stp.log2ns, stp.hbits, p->batch,
-                          stp.grid, s);
+                          stp.grid, stream, s);
                 if (e != hipSuccess) return fail_hip(e, "pass launch");
             }
             (void)split;
@@ -742,7 +746,7 @@ static fft_status create_impl(fft_plan* out, int64_t n, int64_t batch, fft_layou
         return fail_hip(e, "hipGetDevice");
     }
 
-    Decomp dec = fftk::default_decomposition(log2n, rb);
+    Decomp dec = fftk::default_decomposition(log2n, rb, layout);
     p->source = "default";
     fftk::TuneKey key = fftk::make_key(p->device, log2n, batch, layout, rb);
     Decomp cached;
@@ -966,12 +970,17 @@ fft_status fft_plan_destroy(fft_plan p) {
     return FFT_OK;
 }
 
-fft_status fft_plan_create_ragged(fft_plan* out, const int64_t* sizes, int64_t count, fft_layout layout,
-                                  fft_direction dir) {
+static fft_status create_ragged_impl(fft_plan* out, const int64_t* sizes, int64_t count, fft_layout layout,
+                                     fft_direction dir, const char* config) {
     if (!out) return FFT_ERR_NULL_POINTER;
     *out = nullptr;
     if (!sizes) return FFT_ERR_NULL_POINTER;
     if (count < 1 || !valid_layout(layout) || !valid_dir(dir)) return FFT_ERR_INVALID_ARG;
+    fftk::RaggedConfig explicit_cfg;
+    if (config && !fftk::RaggedConfig::parse(config, &explicit_cfg)) {
+        g_detail = std::string("unknown ragged configuration: ") + config;
+        return FFT_ERR_INVALID_ARG;
+    }
     int64_t total = 0;
     double flops = 0.0;
     for (int64_t i = 0; i < count; ++i) {
@@ -1000,7 +1009,10 @@ fft_status fft_plan_create_ragged(fft_plan* out, const int64_t* sizes, int64_t c
     const fftk::TuneKey key = fftk::make_ragged_key(p->device, sizes, count, layout);
     std::string cached;
     p->source = "default";
-    if (fftk::autotune_lookup_text(key, &cached) && fftk::RaggedConfig::parse(cached, &cfg)) {
+    if (config) {
+        cfg = explicit_cfg;
+        p->source = "explicit";
+    } else if (fftk::autotune_lookup_text(key, &cached) && fftk::RaggedConfig::parse(cached, &cfg)) {
         p->source = "cache";
     } else if (fftk::autotune_enabled()) {
         float best_ms = 1e30f;
@@ -1032,6 +1044,16 @@ fft_status fft_plan_create_ragged(fft_plan* out, const int64_t* sizes, int64_t c
     p->ws_bytes = fftk::ragged_workspace_bytes(p->ragged);
     *out = p;
     return FFT_OK;
+}
+
+fft_status fft_plan_create_ragged(fft_plan* out, const int64_t* sizes, int64_t count, fft_layout layout,
+                                  fft_direction dir) {
+    return create_ragged_impl(out, sizes, count, layout, dir, nullptr);
+}
+
+fft_status fft_plan_create_ragged_ex(fft_plan* out, const int64_t* sizes, int64_t count, fft_layout layout,
+                                     fft_direction dir, const char* config) {
+    return create_ragged_impl(out, sizes, count, layout, dir, config);
 }
 
 fft_status fft_plan_workspace_bytes(fft_plan p, size_t* bytes) {
@@ -1078,7 +1100,7 @@ fft_status fft_query_decomposition(int64_t n, fft_layout layout, fft_precision p
     if (log2n < 0 || log2n > fftk::kMaxLog2N) return FFT_ERR_INVALID_SIZE;
     const int rb = fftk::real_bytes_of(precision);
     if (!valid_layout(layout) || rb == 0) return FFT_ERR_INVALID_ARG;
-    const Decomp d = fftk::default_decomposition(log2n, rb);
+    const Decomp d = fftk::default_decomposition(log2n, rb, layout);
     std::string s = "{\"n\": " + std::to_string(n) + ", \"precision\": \"" + (rb == 8 ? "fp64" : "fp32") +
                     "\", \"default\": \"" + d.str() + "\", \"available\": " +
                     (fftk::decomposition_available(d, log2n, layout, rb) ? "true" : "false") + ", \"candidates\": [";

@@ -203,8 +203,12 @@ struct PassShape {
 // One tile of one pass: C consecutive butterfly columns j0 .. j0+C-1 of the
 // transform starting at element tbase.  Shared by the pass kernel and the
 // ragged persistent kernel.  `lds` holds PassShape::LDS complex elements; TW
-// supplies the sub-FFT's stage twiddles.  NT selects streaming (nontemporal)
-// data access.  R (float or double) is deduced from `ia`.
+// supplies the sub-FFT's stage twiddles.  `stream` (kStreamIn | kStreamOut)
+// marks the loads and the stores that touch the caller's buffers: those use
+// streaming (nontemporal) access, since they are read or written once.  The
+// intermediate buffers between passes are accessed normally, so the next pass
+// can find them in the memory-side cache.  R (float or double) is deduced
+// from `ia`.
 //
 // The pass twiddle of input r of column j (k = j mod Ns) is w_M^(r k), M = Ns L.
 // A thread holds r = tp + T m (m < E), so w_M^(r k) = w_M^(tp k) (w_M^(T k))^m:
@@ -217,12 +221,12 @@ struct PassShape {
 template <class T> struct nodeduce { using type = T; };
 
 template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN, bool SWAP_OUT,
-          bool NT, class TW, class R, bool PASSTW = true>
+          class TW, class R, bool PASSTW = true>
 __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R>::type* ib,
                                           typename nodeduce<R>::type* oa, typename nodeduce<R>::type* ob,
                                           const TW& tw, const double2* __restrict__ ta,
                                           const double2* __restrict__ tb, int log2N, int log2Ns, int hbits,
-                                          int64_t tbase, int64_t j0, cplx_t<R>* lds, int tid) {
+                                          int64_t tbase, int64_t j0, cplx_t<R>* lds, int tid, int stream) {
     using V = cplx_t<R>;
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     using SC = typename SH::SC;
@@ -237,10 +241,13 @@ __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R
         const int c = tid & (C - 1), tp = tid >> LOG2C;
         const int64_t j = j0 + c;
         const int64_t k = j & NsMask;
+        const int64_t i0 = tbase + j + tp * stride;
+        if (stream & kStreamIn) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int64_t i = tbase + j + (tp + T * m) * stride;
-            v[m] = swap_if<SWAP_IN>(NT ? gload_nt<SPLIT_IN>(ia, ib, i) : gload<SPLIT_IN>(ia, ib, i));
+            for (int m = 0; m < E; ++m) v[m] = swap_if<SWAP_IN>(gload_nt<SPLIT_IN>(ia, ib, i0 + T * m * stride));
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = swap_if<SWAP_IN>(gload<SPLIT_IN>(ia, ib, i0 + T * m * stride));
         }
         if constexpr (!FIRST && PASSTW) {
             double2 w = twiddle_2level64(ta, tb, k * tp, hbits);
@@ -261,35 +268,39 @@ __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R
         const int t = tid % T, c = tid / T;
         const int64_t j = j0 + c;
         const int64_t obase = tbase + (j << LOG2L) + t;
+        if (stream & kStreamOut) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const V o = swap_if<SWAP_OUT>(v[m]);
-            if constexpr (NT) gstore_nt<SPLIT_OUT>(oa, ob, obase + T * m, o);
-            else gstore<SPLIT_OUT>(oa, ob, obase + T * m, o);
+            for (int m = 0; m < E; ++m) gstore_nt<SPLIT_OUT>(oa, ob, obase + T * m, swap_if<SWAP_OUT>(v[m]));
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m) gstore<SPLIT_OUT>(oa, ob, obase + T * m, swap_if<SWAP_OUT>(v[m]));
         }
     } else {
         const int c = tid & (C - 1), tp = tid >> LOG2C;
         const int64_t j = j0 + c;
         const int64_t k = j & NsMask;
         const int64_t obase = tbase + ((j >> log2Ns) << (log2Ns + LOG2L)) + k;
+        if (stream & kStreamOut) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int64_t q = tp + T * m;
-            const V o = swap_if<SWAP_OUT>(v[m]);
-            if constexpr (NT) gstore_nt<SPLIT_OUT>(oa, ob, obase + (q << log2Ns), o);
-            else gstore<SPLIT_OUT>(oa, ob, obase + (q << log2Ns), o);
+            for (int m = 0; m < E; ++m)
+                gstore_nt<SPLIT_OUT>(oa, ob, obase + (int64_t(tp + T * m) << log2Ns), swap_if<SWAP_OUT>(v[m]));
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                gstore<SPLIT_OUT>(oa, ob, obase + (int64_t(tp + T * m) << log2Ns), swap_if<SWAP_OUT>(v[m]));
         }
     }
 }
 
 // Persistent pass kernel: workgroup w takes tiles w, w + grid, ... (mapped
 // so that the tiles one XCD works on are consecutive), with the sub-FFT's stage
-// twiddles held in registers across tiles and streaming data access.
+// twiddles held in registers across tiles.  `stream` says which side is the
+// caller's data (streaming access); the workspace between passes is not.
 template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN,
           bool SWAP_OUT>
 __global__ void __launch_bounds__((PassShape<LOG2L, LOG2E, LOG2C>::THREADS))
 k_pass(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw, const double2* __restrict__ ta,
-       const double2* __restrict__ tb, int log2N, int log2Ns, int hbits, int64_t tiles) {
+       const double2* __restrict__ tb, int log2N, int log2Ns, int hbits, int64_t tiles, int stream) {
     using V = cplx_t<R>;
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     using SC = typename SH::SC;
@@ -312,18 +323,19 @@ k_pass(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw,
         const int64_t b = tile >> log2TilesPerT;
         const int64_t j0 = (tile & ((int64_t(1) << log2TilesPerT) - 1)) << LOG2C;
         if constexpr (REGTW)
-            pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT, true>(
-                ia, ib, oa, ob, twr, ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl);
+            pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>(
+                ia, ib, oa, ob, twr, ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl, stream);
         else
-            pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT, true>(
-                ia, ib, oa, ob, TwMem<SC, V>(tw), ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl);
+            pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>(
+                ia, ib, oa, ob, TwMem<SC, V>(tw), ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl, stream);
     }
 }
 
 template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN,
           bool SWAP_OUT>
 hipError_t launch_pass(const void* ia, const void* ib, void* oa, void* ob, const void* tw, const double2* ta,
-                       const double2* tb, int log2N, int log2Ns, int hbits, int64_t batch, int grid, hipStream_t s) {
+                       const double2* tb, int log2N, int log2Ns, int hbits, int64_t batch, int grid, int stream,
+                       hipStream_t s) {
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     if (log2N < LOG2L + LOG2C) return hipErrorInvalidConfiguration;
     const int64_t tiles = (int64_t(1) << (log2N - LOG2L - LOG2C)) * batch;
@@ -332,7 +344,7 @@ hipError_t launch_pass(const void* ia, const void* ib, void* oa, void* ob, const
     hipLaunchKernelGGL((k_pass<R, LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>),
                        dim3(static_cast<unsigned>(blocks)), dim3(SH::THREADS), 0, s, static_cast<const R*>(ia),
                        static_cast<const R*>(ib), static_cast<R*>(oa), static_cast<R*>(ob),
-                       static_cast<const cplx_t<R>*>(tw), ta, tb, log2N, log2Ns, hbits, tiles);
+                       static_cast<const cplx_t<R>*>(tw), ta, tb, log2N, log2Ns, hbits, tiles, stream);
     return hipGetLastError();
 }
 

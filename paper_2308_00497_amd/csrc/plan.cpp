@@ -190,29 +190,46 @@ static std::vector<int> even_split(int log2n, int parts) {
     return v;
 }
 
-// FP64 defaults, measured on MI355X (batches of 2^24 elements, the faster on
-// average over both layouts): single-pass up to 2^13, then passes
-static Decomp default_decomposition64(int log2n) {
+// FP64 defaults, measured on MI355X (batches of 2^24 elements): single-pass
+// up to 2^13 (the faster on average over both layouts), then pass chains per
+// layout, timed on inputs that are not in any cache
+static Decomp default_decomposition64(int log2n, fft_layout layout) {
     static const struct { int log2e, wgt, gmul, twreg, pf; } single[14] = {
         {4, 256, 1, 1, 0}, {4, 256, 2, 0, 0}, {4, 64, 3, 0, 0}, {4, 64, 1, 0, 0}, {3, 256, 8, 1, 0},  // 2^0 .. 2^4
         {3, 256, 8, 1, 0}, {3, 256, 1, 1, 0}, {3, 64, 3, 1, 0}, {3, 64, 3, 1, 0}, {3, 64, 4, 1, 0},   // 2^5 .. 2^9
         {3, 256, 2, 1, 0}, {3, 256, 2, 1, 0}, {3, 256, 1, 1, 1}, {4, 256, 1, 0, 1},                   // 2^10 .. 2^13
     };
-    static const char* multi[kMaxLog2N + 1] = {
+    static const char* multi_il[kMaxLog2N + 1] = {
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
         nullptr, nullptr, nullptr, nullptr,
         "multi:7c5,7c5",          // 2^14
         "multi:8c4,7c5",          // 2^15
         "multi:8c4,8c4",          // 2^16
-        "multi:9c4,8c5",          // 2^17
+        "multi:9c3,8c4",          // 2^17
         "multi:10c3,8c5",         // 2^18
         "multi:10c3,9c4",         // 2^19
         "multi:10c3,10c3",        // 2^20
-        "multi:7c5,7c6,7c5",      // 2^21
-        "multi:8c5,8c5,6c7",      // 2^22
+        "multi:11c2,10c3",        // 2^21
+        "multi:8c4,8c5,6c6",      // 2^22
         "multi:8c4,8c4,7c5",      // 2^23
-        "multi:9c4,8c5,7c4",      // 2^24
+        "multi:8c5,8c5,8c5",      // 2^24
     };
+    static const char* multi_sp[kMaxLog2N + 1] = {
+        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+        nullptr, nullptr, nullptr, nullptr,
+        "multi:7c6,7c6",          // 2^14
+        "multi:8c4,7c5",          // 2^15
+        "multi:8c5,8c5",          // 2^16
+        "multi:9c4,8c5",          // 2^17
+        "multi:9c4,9c4",          // 2^18
+        "multi:10c3,9c4",         // 2^19
+        "multi:7c5,7c6,6c6",      // 2^20
+        "multi:7c6,7c5,7c5",      // 2^21
+        "multi:8c4,7c5,7c5",      // 2^22
+        "multi:8c4,8c4,7c5",      // 2^23
+        "multi:8c4,8c5,8c5",      // 2^24
+    };
+    const char* const* multi = layout == FFT_LAYOUT_SPLIT ? multi_sp : multi_il;
     Decomp d;
     if (log2n <= 0) {
         d.kind = Decomp::COPY;
@@ -229,8 +246,8 @@ static Decomp default_decomposition64(int log2n) {
     return d;
 }
 
-Decomp default_decomposition(int log2n, int rb) {
-    if (rb == 8) return default_decomposition64(log2n);
+Decomp default_decomposition(int log2n, int rb, fft_layout layout) {
+    if (rb == 8) return default_decomposition64(log2n, layout);
     Decomp d;
     if (log2n <= 0) {
         d.kind = Decomp::COPY;
@@ -252,22 +269,40 @@ Decomp default_decomposition(int log2n, int rb) {
         d.pf = table[log2n].pf == 1;
         return d;
     }
-    // multi-pass chains measured fastest on MI355X (batches of 2^25 elements,
-    // the lower mean over both layouts)
-    static const char* measured[kMaxLog2N + 1] = {
+    // multi-pass chains measured fastest on MI355X per layout (batches of 2^25
+    // elements from inputs not in any cache; the workspace between passes is
+    // read back through the memory-side cache, which favours two passes for
+    // interleaved 2^18 .. 2^20, and wider tiles where split arrays halve the
+    // contiguous runs)
+    static const char* measured_il[kMaxLog2N + 1] = {
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
         nullptr, nullptr, nullptr, nullptr, nullptr,
-        "multi:9c4,6c6",          // 2^15
-        "multi:8c5,8c6",          // 2^16
+        "multi:8c4,7c5",          // 2^15
+        "multi:8c5,8c5",          // 2^16
         "multi:9c4,8c5",          // 2^17
-        "multi:10c3,8c6",         // 2^18
-        "multi:7c7,6c6,6c7",      // 2^19
-        "multi:8c6,6c6,6c7",      // 2^20
-        "multi:7c7,7c6,7c7",      // 2^21
-        "multi:8c6,7c7,7c6",      // 2^22
-        "multi:8c6,8c6,7c6",      // 2^23
-        "multi:8c5,8c6,8c5",      // 2^24
+        "multi:9c4,9c4",          // 2^18
+        "multi:10c3,9c4",         // 2^19
+        "multi:10c3,10c3",        // 2^20
+        "multi:7c5,7c6,7c6",      // 2^21
+        "multi:8c5,8c6,6c6",      // 2^22
+        "multi:8c5,8c6,7c6",      // 2^23
+        "multi:8c5,8c5,8c5",      // 2^24
     };
+    static const char* measured_sp[kMaxLog2N + 1] = {
+        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+        nullptr, nullptr, nullptr, nullptr, nullptr,
+        "multi:8c6,7c7",          // 2^15
+        "multi:8c6,8c6",          // 2^16
+        "multi:9c4,8c6",          // 2^17
+        "multi:10c3,8c6",         // 2^18
+        "multi:7c7,6c7,6c7",      // 2^19
+        "multi:7c7,7c6,6c6",      // 2^20
+        "multi:7c6,7c6,7c6",      // 2^21
+        "multi:8c6,8c5,6c7",      // 2^22
+        "multi:8c5,8c6,7c6",      // 2^23
+        "multi:8c5,8c5,8c5",      // 2^24
+    };
+    const char* const* measured = layout == FFT_LAYOUT_SPLIT ? measured_sp : measured_il;
     if (measured[log2n] && Decomp::parse(measured[log2n], &d)) return d;
     // otherwise passes of at most 2^9 points with 16-column tiles (128-byte runs)
     int parts = (log2n + 8) / 9;

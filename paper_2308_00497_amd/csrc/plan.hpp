@@ -38,9 +38,10 @@ struct Decomp {
 };
 
 // Largest size, and the default (untuned) choice.  `rb` is the bytes of one
-// real number: 4 (FP32) or 8 (FP64).
+// real number: 4 (FP32) or 8 (FP64); the multi-pass choice depends on the
+// layout of the caller's arrays.
 constexpr int kMaxLog2N = 24;
-Decomp default_decomposition(int log2n, int rb);
+Decomp default_decomposition(int log2n, int rb, fft_layout layout = FFT_LAYOUT_INTERLEAVED);
 
 // every decomposition the library can run for log2n (autotuner candidates)
 std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int rb);

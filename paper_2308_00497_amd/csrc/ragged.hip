@@ -12,15 +12,19 @@
 //                 split into P = ceil(log2 N / 8) passes of L <= 256 points
 //                 (the multi-pass scheme of Eq. 1 with M, K the pass lengths)
 // Tiles are grouped in levels: level 0 holds every first-pass tile and then
-// every single/copy tile, level p > 0 the p-th pass tiles.  Each level is one
-// launch of the persistent kernel; the kernel boundary orders pass p - 1
-// before pass p, so no workgroup ever waits for another.  Within a level the
+// every single/copy tile, level p > 0 the p-th pass tiles.  With pipelined
+// groups (RaggedConfig::group_mib) the multi-pass transforms are cut into
+// groups and level k holds pass p of group k - p, so each level's workspace
+// output is consumed by the next level.  Each level is one launch of the
+// persistent kernel; the kernel boundary orders pass p - 1 before pass p, so
+// no workgroup ever waits for another.  Within a level the
 // tiles are sorted by class and dealt round-robin to the resident workgroups
 // (tile w, w + grid, ...), and a workgroup keeps running one class's code, with
 // that class's stage twiddles in registers, while its next tile is of the same
 // class.  Descriptors carry every offset a tile needs, so a tile's data loads
 // depend on one descriptor read at most.
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -40,6 +44,7 @@ namespace {
 constexpr int kThreads = 512;
 constexpr int kTileLog2 = 13;  // 8192 elements per tile
 constexpr int kMinPassLog2 = 5, kMaxPassLog2 = 8;
+constexpr int kMaxPasses = 3;  // passes of one multi-pass transform
 
 enum : uint32_t { CODE_COPY = 0, CODE_PASS_FIRST = 16, CODE_PASS_MID = 20, CODE_PASS_LAST = 24 };
 
@@ -193,18 +198,20 @@ __device__ __forceinline__ uint32_t run_pass(const RaggedArgs& a, uint32_t ti, f
         float* wdst = (d.dst == 2 ? a.wsb : a.wsa) + 2 * woff;
         const double2* ta = a.tw64 + d.ta;
         const double2* tb = a.tw64 + d.tb;
+        // the caller's data is streamed; the workspace between levels is not,
+        // so the next level can find it in the memory-side cache
         if constexpr (FIRST) {
-            pass_tile<LOG2L, 4, LOG2C, true, SPLIT, false, SWAP, false, true>(ia, ib, wdst, nullptr, twr, ta, tb,
-                                                                               d.log2n, d.log2ns, d.hbits, 0, d.col,
-                                                                               lds, tidl);
+            pass_tile<LOG2L, 4, LOG2C, true, SPLIT, false, SWAP, false>(ia, ib, wdst, nullptr, twr, ta, tb, d.log2n,
+                                                                         d.log2ns, d.hbits, 0, d.col, lds, tidl,
+                                                                         kStreamIn);
         } else if constexpr (LAST) {
-            pass_tile<LOG2L, 4, LOG2C, false, false, SPLIT, false, SWAP, true>(wsrc, nullptr, oa, ob, twr, ta, tb,
-                                                                                d.log2n, d.log2ns, d.hbits, 0, d.col,
-                                                                                lds, tidl);
+            pass_tile<LOG2L, 4, LOG2C, false, false, SPLIT, false, SWAP>(wsrc, nullptr, oa, ob, twr, ta, tb, d.log2n,
+                                                                          d.log2ns, d.hbits, 0, d.col, lds, tidl,
+                                                                          kStreamOut);
         } else {
-            pass_tile<LOG2L, 4, LOG2C, false, false, false, false, false, true>(wsrc, nullptr, wdst, nullptr, twr, ta,
-                                                                                 tb, d.log2n, d.log2ns, d.hbits, 0,
-                                                                                 d.col, lds, tidl);
+            pass_tile<LOG2L, 4, LOG2C, false, false, false, false, false>(wsrc, nullptr, wdst, nullptr, twr, ta, tb,
+                                                                           d.log2n, d.log2ns, d.hbits, 0, d.col, lds,
+                                                                           tidl, 0);
         }
         ti += gridDim.x;
     } while (same_class(a, ti, code));
@@ -263,13 +270,13 @@ struct RaggedPlan {
     hipStream_t cap = nullptr;     // capture stream
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
-    static constexpr int kMaxLevels = 3;
+    static constexpr int kMaxLevels = 24;  // pass levels of the pipelined groups
     int nlevels = 0;
     uint32_t level_begin[kMaxLevels + 1] = {};     // tile index ranges of the levels
     int level_grid[kMaxLevels] = {};
     hipGraphNode_t node[2][kMaxLevels] = {};
     RaggedArgs args[2][kMaxLevels];
-    int nsingle_tiles = 0, npass_tiles = 0, ncopy_tiles = 0, nmulti = 0;
+    int nsingle_tiles = 0, npass_tiles = 0, ncopy_tiles = 0, nmulti = 0, ngroups = 0;
     std::string classes;
 
     void* ws() const { return ws_user ? ws_user : ws_own; }
@@ -362,33 +369,41 @@ fft_status build_graph(RaggedPlan* r, int variant, std::string* detail) {
 }  // namespace
 
 std::string RaggedConfig::str() const {
-    char buf[48];
-    snprintf(buf, sizeof buf, "ragged:p%d:g%d:o%d", max_pass_log2, grid_eighths, smallest_first ? 1 : 0);
+    char buf[64];
+    if (group_mib > 0)
+        snprintf(buf, sizeof buf, "ragged:p%d:g%d:o%d:w%d", max_pass_log2, grid_eighths, smallest_first ? 1 : 0,
+                 group_mib);
+    else
+        snprintf(buf, sizeof buf, "ragged:p%d:g%d:o%d", max_pass_log2, grid_eighths, smallest_first ? 1 : 0);
     return buf;
 }
 
 bool RaggedConfig::parse(const std::string& s, RaggedConfig* out) {
-    int p = 0, g = 0, o = 0, used = 0;
-    if (sscanf(s.c_str(), "ragged:p%d:g%d:o%d%n", &p, &g, &o, &used) != 3 || used != static_cast<int>(s.size()))
-        return false;
+    int p = 0, g = 0, o = 0, w = 0, used = 0;
+    const int n = sscanf(s.c_str(), "ragged:p%d:g%d:o%d%n:w%d%n", &p, &g, &o, &used, &w, &used);
+    if ((n != 3 && n != 4) || used != static_cast<int>(s.size())) return false;
     if (p < 6 || p > kMaxPassLog2 || g < 1 || g > 8 || (o != 0 && o != 1)) return false;
+    if (n == 4 && (w < 8 || w > 65536)) return false;
     out->max_pass_log2 = p;
     out->grid_eighths = g;
     out->smallest_first = o == 1;
+    out->group_mib = n == 4 ? w : 0;
     return true;
 }
 
 std::vector<RaggedConfig> ragged_candidates() {
     std::vector<RaggedConfig> v;
-    for (int p : {8, 7, 6})
-        for (int g : {8, 6, 4})
-            for (int o : {0, 1}) {
-                RaggedConfig c;
-                c.max_pass_log2 = p;
-                c.grid_eighths = g;
-                c.smallest_first = o == 1;
-                v.push_back(c);
-            }
+    for (int w : {128, 0, 64, 192, 256})
+        for (int p : {8, 7, 6})
+            for (int g : {8, 6, 4})
+                for (int o : {0, 1}) {
+                    RaggedConfig c;
+                    c.max_pass_log2 = p;
+                    c.grid_eighths = g;
+                    c.smallest_first = o == 1;
+                    c.group_mib = w;
+                    v.push_back(c);
+                }
     return v;
 }
 
@@ -461,20 +476,17 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
     std::vector<std::vector<PassTab>> ptab(kMaxLog2N + 1);
     size_t tw64_n = 0;
     std::vector<int64_t> wsoff(count, 0);
-    int64_t ws_elems = 0;
     int max_passes = 0;
     std::vector<int64_t> multi;
     for (int64_t i = 0; i < count; ++i) {
         if (lg[i] <= kTileLog2) continue;
         multi.push_back(i);
-        wsoff[i] = ws_elems;
-        ws_elems += sizes[i];
         const int n = lg[i];
         if (parts[n].empty()) {
             // passes of at most 2^max_pass_log2 points (and at least 2^5, at most
             // three passes, at most 2^8 points)
             int np = std::max((n + cfg.max_pass_log2 - 1) / cfg.max_pass_log2, (n + kMaxPassLog2 - 1) / kMaxPassLog2);
-            np = std::min(np, std::min(RaggedPlan::kMaxLevels, n / kMinPassLog2));
+            np = std::min(np, std::min(kMaxPasses, n / kMinPassLog2));
             parts[n] = even_parts(n, np);
             int log2ns = 0;
             for (size_t p = 0; p < parts[n].size(); ++p) {
@@ -502,8 +514,39 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
     std::stable_sort(multi.begin(), multi.end(), [&](int64_t a, int64_t b) {
         return cfg.smallest_first ? lg[a] < lg[b] : lg[a] > lg[b];
     });
-    auto pass_tiles = [&](size_t p) {
-        for (int64_t i : multi) {
+    // groups of consecutive multi-pass transforms with at most group_mib MiB
+    // of workspace each (one group without pipelining); so many groups that
+    // the levels would not fit are merged by growing the group size
+    std::vector<size_t> group_begin;  // index into `multi` of each group's first transform
+    int64_t slot_elems = 0;           // workspace elements of the largest group
+    for (int64_t cap = cfg.group_mib > 0 ? (int64_t(cfg.group_mib) << 20) / int64_t(sizeof(float2)) : INT64_MAX;;
+         cap *= 2) {
+        group_begin.clear();
+        slot_elems = 0;
+        int64_t cur = 0;
+        for (size_t m = 0; m < multi.size(); ++m) {
+            const int64_t sz = sizes[multi[m]];
+            if (group_begin.empty() || (cur > 0 && cur + sz > cap)) {
+                group_begin.push_back(m);
+                cur = 0;
+            }
+            wsoff[multi[m]] = cur;  // offset inside the group's slot
+            cur += sz;
+            slot_elems = std::max(slot_elems, cur);
+        }
+        if (group_begin.size() + std::max(max_passes, 1) - 1 <= size_t(RaggedPlan::kMaxLevels)) break;
+    }
+    const int ngroups = static_cast<int>(group_begin.size());
+    const int slots = ngroups > 1 ? 2 : 1;  // ring: group g uses slot g % 2
+    for (int gi = 0; gi < ngroups; ++gi) {
+        const size_t end = gi + 1 < ngroups ? group_begin[gi + 1] : multi.size();
+        for (size_t m = group_begin[gi]; m < end; ++m) wsoff[multi[m]] += int64_t(gi % 2) * slot_elems;
+    }
+    r->ngroups = ngroups;
+    auto pass_tiles = [&](size_t p, int gi) {
+        const size_t mbeg = group_begin[gi], mend = gi + 1 < ngroups ? group_begin[gi + 1] : multi.size();
+        for (size_t m = mbeg; m < mend; ++m) {
+            const int64_t i = multi[m];
             const int n = lg[i];
             if (p >= parts[n].size()) continue;
             const int l = parts[n][p];
@@ -533,9 +576,9 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
             }
         }
     };
-    // level 0: first passes, then the whole small transforms
+    // level 0: first passes (of group 0), then the whole small transforms
     r->level_begin[0] = 0;
-    pass_tiles(0);
+    if (ngroups > 0) pass_tiles(0, 0);
     for (int n = kTileLog2; n >= 0; --n) {
         std::vector<uint32_t> cls;
         for (int64_t i = 0; i < count; ++i)
@@ -560,12 +603,18 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
         snprintf(buf, sizeof buf, "%s\"2^%d\": %zu", r->classes.empty() ? "" : ", ", n, cls.size());
         r->classes += buf;
     }
+    // level k > 0: pass p of group k - p, later passes first
     r->nlevels = 1;
-    for (int p = 1; p < max_passes; ++p) {
-        r->level_begin[p] = static_cast<uint32_t>(tiles.size());
-        pass_tiles(p);
-        r->nlevels = p + 1;
+    const int nlev = ngroups > 0 ? ngroups + max_passes - 1 : 1;
+    for (int k = 1; k < nlev; ++k) {
+        r->level_begin[k] = static_cast<uint32_t>(tiles.size());
+        for (int p = std::min(k, max_passes - 1); p >= 0; --p)
+            if (k - p < ngroups) pass_tiles(size_t(p), k - p);
+        r->nlevels = k + 1;
     }
+    // the last group may lack the longest chains: drop empty trailing levels
+    // (every level then has tiles, and a distinct first descriptor)
+    while (r->nlevels > 1 && r->level_begin[r->nlevels - 1] == tiles.size()) --r->nlevels;
     r->level_begin[r->nlevels] = static_cast<uint32_t>(tiles.size());
     for (int n = kTileLog2 + 1; n <= kMaxLog2N; ++n) {
         int64_t c = 0;
@@ -582,7 +631,7 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
     if (e == hipSuccess) e = upload(&r->toffs, toffs);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&r->tw32), std::max<size_t>(2, tw32_n) * sizeof(float2));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&r->tw64), std::max<size_t>(2, tw64_n) * sizeof(double2));
-    r->ws_half = size_t(ws_elems) * sizeof(float2);
+    r->ws_half = size_t(slot_elems) * slots * sizeof(float2);
     r->ws_regions = max_passes >= 3 ? 2 : (max_passes == 2 ? 1 : 0);
     if (e == hipSuccess && r->ws_half) e = hipMalloc(&r->ws_own, r->ws_half * r->ws_regions);
     if (e != hipSuccess) {
@@ -747,10 +796,10 @@ std::string ragged_describe(const RaggedPlan* r) {
     snprintf(buf, sizeof buf,
              "\"kernel\": \"ragged persistent\", \"transforms\": %lld, \"elements\": %lld, \"tiles\": %zu, "
              "\"single_tiles\": %d, \"pass_tiles\": %d, \"copy_tiles\": %d, \"multi_pass_transforms\": %d, "
-             "\"levels\": %d, \"workgroups\": %d, \"threads\": %d, \"lds_bytes\": %zu, \"workspace_bytes\": %zu, "
-             "\"classes\": {",
+             "\"levels\": %d, \"groups\": %d, \"workgroups\": %d, \"threads\": %d, \"lds_bytes\": %zu, "
+             "\"workspace_bytes\": %zu, \"classes\": {",
              (long long)r->count, (long long)r->total, r->htiles.size(), r->nsingle_tiles, r->npass_tiles,
-             r->ncopy_tiles, r->nmulti, r->nlevels, r->grid, kThreads, size_t(kLds) * sizeof(float2),
+             r->ncopy_tiles, r->nmulti, r->nlevels, r->ngroups, r->grid, kThreads, size_t(kLds) * sizeof(float2),
              r->ws_half * r->ws_regions);
     return std::string(buf) + r->classes + "}, \"config\": \"" + r->cfg.str() + "\"";
 }

@@ -20,11 +20,19 @@ struct RaggedPlan;
 //   grid_eighths    persistent workgroups per launch, in eighths of the number
 //                   that can be resident at once
 //   smallest_first  order of the multi-pass transforms within a level
+//   group_mib       0: every multi-pass transform's pass p in level p.  Else
+//                   the multi-pass transforms are cut into groups of at most
+//                   this many MiB of workspace, and group g's pass p runs in
+//                   level g + p (a software pipeline over levels): what one
+//                   level writes to the workspace is read by the next while it
+//                   can still be in the memory-side cache, and the workspace
+//                   is a ring of two group-sized slots
 struct RaggedConfig {
     int max_pass_log2 = 8;
     int grid_eighths = 8;
     bool smallest_first = false;
-    std::string str() const;  // "ragged:p8:g8:o0"
+    int group_mib = 128;  // measured best on the 2^6..2^16 mix (two 128 MiB slots)
+    std::string str() const;  // "ragged:p8:g8:o0" or "ragged:p8:g8:o0:w128"
     static bool parse(const std::string& s, RaggedConfig* out);
 };
 

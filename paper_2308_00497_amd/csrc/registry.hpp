@@ -46,10 +46,16 @@ struct SingleKernel {
     size_t lds_bytes;
 };
 
-// grid = number of persistent workgroups (clamped to the number of tiles)
+// sides of a pass that are the caller's buffers: read or written once, with
+// streaming (nontemporal) access
+constexpr int kStreamIn = 1, kStreamOut = 2;
+
+// grid = number of persistent workgroups (clamped to the number of tiles);
+// stream = kStreamIn | kStreamOut for the sides that are the caller's buffers
+// (streaming access), 0 for workspace on both sides
 using pass_fn = hipError_t (*)(const void* ia, const void* ib, void* oa, void* ob, const void* tw, const double2* ta,
                                const double2* tb, int log2N, int log2Ns, int hbits, int64_t batch, int grid,
-                               hipStream_t s);
+                               int stream, hipStream_t s);
 
 struct PassKernel {
     int real_bytes; // 4 (FP32) or 8 (FP64)

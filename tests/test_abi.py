@@ -157,6 +157,10 @@ def test_ragged_validation(lib):
     assert lib.fft_plan_create_ragged(ctypes.byref(h), arr, 0, 0, -1) == 2
     assert lib.fft_plan_create_ragged(ctypes.byref(h), None, 2, 0, -1) == 3
     assert lib.fft_plan_create_ragged(ctypes.byref(h), arr, 2, 7, -1) == 2
+    # explicit configurations that do not parse are rejected before any device call
+    for bad in (b"bogus", b"ragged:p9:g8:o0", b"ragged:p5:g8:o0", b"ragged:p8:g0:o0", b"ragged:p8:g8:o2",
+                b"ragged:p8:g8:o0:w4", b"ragged:p8:g8:o0:w", b"ragged:p8:g8:o0:w64x", b"ragged:p8:g8"):
+        assert lib.fft_plan_create_ragged_ex(ctypes.byref(h), arr, 2, 0, -1, bad) == 2, bad
 
 
 def test_execute_rejects_null_plan(lib):

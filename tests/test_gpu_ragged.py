@@ -191,3 +191,41 @@ def test_ragged_autotune_and_every_config(fftlib, tmp_path, monkeypatch):
                     y = from_device(plan.execute(to_device(re, im, "interleaved")), "interleaved")
                 assert d["source"] == "cache" and d["config"] == cfg
                 assert per_item_errors(y, ref, sizes, offsets).max() <= TOL, cfg
+
+
+@pytest.mark.parametrize("cfg", ["ragged:p8:g8:o0:w8", "ragged:p7:g6:o1:w8", "ragged:p6:g4:o0:w16"])
+def test_ragged_pipelined_groups(fftlib, cfg):
+    """Multi-pass transforms cut into groups of at most w MiB of workspace,
+    group g's pass p in level g + p, the workspace a ring of two slots: three-
+    and two-pass chains in different groups, single tiles in level 0, both
+    layouts and directions; new buffers on the second run reuse the graph."""
+    sizes, offsets, re, im = make([1 << 20, 1 << 18, 1 << 6, 1 << 18, 1 << 16, 1 << 14, 1 << 18, 1 << 12,
+                                   1 << 16, 1 << 16, 1 << 14, 1 << 16, 1 << 9], 49)
+    for direction in ("forward", "inverse"):
+        ref = ragged_oracle(sizes, offsets, re, im, direction)
+        for layout in ("interleaved", "split"):
+            with fftlib.RaggedPlan(sizes, layout, direction, config=cfg) as plan:
+                d = plan.describe()
+                print(f"[case] {cfg} {layout} {direction}: groups {d['groups']} levels {d['levels']}", flush=True)
+                assert d["config"] == cfg and d["source"] == "explicit", d
+                assert d["groups"] > 1 and d["levels"] >= d["groups"] + 1, d
+                for rep in range(2):
+                    y = from_device(plan.execute(to_device(re, im, layout)), layout)
+                    errs = per_item_errors(y, ref, sizes, offsets)
+                    print(f"[parity] {cfg} {layout} {direction} rep {rep}: max rel-L2 {errs.max():.3e}", flush=True)
+                    assert errs.max() <= TOL, (cfg, layout, direction, rep)
+
+
+def test_ragged_pipelined_matches_plain_levels(fftlib):
+    """The same batch with and without pipelined groups gives the same
+    transforms (each to the oracle's tolerance, and to each other)."""
+    sizes, offsets, re, im = make([1 << 17, 1 << 15, 1 << 19, 1 << 10, 1 << 15, 1 << 17, 1 << 16], 50)
+    ys = {}
+    for cfg in ("ragged:p8:g8:o0", "ragged:p8:g8:o0:w8"):
+        with fftlib.RaggedPlan(sizes, "split", "forward", config=cfg) as plan:
+            ys[cfg] = from_device(plan.execute(to_device(re, im, "split")), "split")
+    ref = ragged_oracle(sizes, offsets, re, im, "forward")
+    for y in ys.values():
+        assert per_item_errors(y, ref, sizes, offsets).max() <= TOL
+    a, b = ys.values()
+    assert per_item_errors(a, b, sizes, offsets).max() <= TOL
