@@ -136,7 +136,14 @@ fft_status fft_plan_create_ex(fft_plan *out, int64_t n, int64_t batch,
  *   ignored; out = complex array(s) [batch][n/2 + 1] in `layout`.  C2R in =
  *   complex array(s) [batch][n/2 + 1], out_re_or_z = real array [batch][n],
  *   out_im ignored.  The real and complex buffers may not overlap (no in-place).
- *   fft_execute_backward returns FFT_ERR_NOT_SUPPORTED.  fft_plan_sizes
+ *   fft_execute_backward applies the adjoint under the real inner products
+ *   (sum x y on the real side, Re sum conj(X) Y on the complex side), the
+ *   vector-Jacobian product of the plan: for R2C it maps a complex gradient
+ *   g (n/2 + 1 values per row, same layout) to the real
+ *   x[m] = Re sum_{k<=n/2} g[k] exp(+2 pi i k m / n), which is C2R of g with
+ *   the bins k = 1 .. n/2-1 halved; for C2R it maps a real gradient to R2C of
+ *   it with those bins doubled.  Its buffers are those of fft_execute with the
+ *   roles exchanged (R2C backward: in = complex, out = real).  fft_plan_sizes
  *   reports n*batch elements and 2.5 n log2 n flops per row.
  * `decomposition` is NULL (default) or a decomposition string of the half
  * length ("copy" for n = 2); n = 1 takes none. */
@@ -174,7 +181,7 @@ fft_status fft_execute(fft_plan p, const void *in_re_or_z, const void *in_im,
  * transform) for a forward plan, F for an inverse plan.  This is the vector-
  * Jacobian product of fft_execute, so fft_execute followed by
  * fft_execute_backward multiplies the input by N.  Same buffers and rules as
- * fft_execute. */
+ * fft_execute (real-input plans: see fft_plan_create_real). */
 fft_status fft_execute_backward(fft_plan p, const void *grad_out_re_or_z,
                                 const void *grad_out_im, void *grad_in_re_or_z,
                                 void *grad_in_im, void *stream);

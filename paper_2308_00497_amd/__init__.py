@@ -29,7 +29,8 @@ from ._lib import (FFT_FORWARD, FFT_INVERSE, FFT_LAYOUT_INTERLEAVED, FFT_LAYOUT_
                    FFT_PRECISION_FP64, FFTError, check, lib)
 
 __all__ = ["Plan", "RaggedPlan", "RealPlan", "PlanND", "fft", "ifft", "rfft", "irfft", "fftn", "ifftn",
-           "FFTFunction", "fft_autograd", "copy_device", "query_decomposition", "FFTError"]
+           "FFTFunction", "fft_autograd", "rfft_autograd", "irfft_autograd", "copy_device", "query_decomposition",
+           "FFTError"]
 
 _LAYOUTS = {"interleaved": FFT_LAYOUT_INTERLEAVED, "split": FFT_LAYOUT_SPLIT}
 _DIRS = {"forward": FFT_FORWARD, "inverse": FFT_INVERSE}
@@ -219,7 +220,9 @@ class RealPlan(_PlanBase):
     direction "forward" is real-to-complex: real [batch][n] -> complex
     [batch][n/2 + 1] (X[k] for k = 0 .. n/2); "inverse" is complex-to-real,
     unnormalised (C2R(R2C(x)) = n x).  `layout` is the complex side's
-    (interleaved complex tensor, or a (re, im) pair).  No backward.
+    (interleaved complex tensor, or a (re, im) pair).  `backward` applies the
+    adjoint (the vector-Jacobian product): R2C's maps a complex gradient to a
+    real one, C2R's a real gradient to a complex one.
     """
 
     def __init__(self, n: int, batch: int = 1, layout: str = "interleaved", direction: str = "forward",
@@ -256,10 +259,10 @@ class RealPlan(_PlanBase):
             raise ValueError(f"expected {count} complex values, got {x.numel()}")
         return _ptr(x), None
 
-    def execute(self, x, out=None, stream=None):
+    def _run(self, fn, name, x, out, stream, real_in):
         rdt, cdt = _DTYPES[self.precision]
         nc = self.half * self.batch
-        if self.direction == "forward":
+        if real_in:
             self._check_real(x, self.n * self.batch)
             if out is None:
                 shape = tuple(x.shape[:-1]) + (self.half,)
@@ -277,13 +280,18 @@ class RealPlan(_PlanBase):
                 out = torch.empty(tuple(ref.shape[:-1]) + (self.n,), dtype=rdt, device=ref.device)
             self._check_real(out, self.n * self.batch)
             oa, ob = _ptr(out), None
-        check(lib.fft_execute(self._handle, ia, ib, oa, ob, _stream_handle(stream)), "fft_execute")
+        check(fn(self._handle, ia, ib, oa, ob, _stream_handle(stream)), name)
         return out
+
+    def execute(self, x, out=None, stream=None):
+        return self._run(lib.fft_execute, "fft_execute", x, out, stream, self.direction == "forward")
 
     __call__ = execute
 
     def backward(self, g, out=None, stream=None):
-        raise FFTError(7, "RealPlan.backward", "real-input plans have no backward")
+        """Adjoint of execute: complex gradient -> real (R2C plan), real -> complex (C2R plan)."""
+        return self._run(lib.fft_execute_backward, "fft_execute_backward", g, out, stream,
+                         self.direction == "inverse")
 
 
 _plan_cache: dict = {}
@@ -413,6 +421,45 @@ class _ComplexFFTFunction(torch.autograd.Function):
 def fft_autograd(z: torch.Tensor) -> torch.Tensor:
     """Differentiable forward FFT of a complex64 or complex128 tensor [..., N]."""
     return _ComplexFFTFunction.apply(z)
+
+
+class _RFFTFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x: torch.Tensor):
+        n = x.shape[-1]
+        plan = _cached_real_plan(n, x.numel() // n, "forward", _precision_of(x.dtype))
+        ctx.plan = plan
+        return plan.execute(x.contiguous())
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        return ctx.plan.backward(g.contiguous())
+
+
+class _IRFFTFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, z: torch.Tensor, n: int):
+        plan = _cached_real_plan(n, z.numel() // (n // 2 + 1), "inverse", _precision_of(z.dtype))
+        ctx.plan = plan
+        return plan.execute(z.contiguous())
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        return ctx.plan.backward(g.contiguous()), None
+
+
+def rfft_autograd(x: torch.Tensor) -> torch.Tensor:
+    """Differentiable R2C of a float32/float64 tensor [..., n] -> complex [..., n/2 + 1].
+    The gradient of a real loss L is x_grad[m] = Re sum_k g[k] exp(+2 pi i k m / n),
+    g = dL/dRe X + i dL/dIm X (torch's convention), from the adjoint kernel."""
+    return _RFFTFunction.apply(x)
+
+
+def irfft_autograd(z: torch.Tensor, n: int) -> torch.Tensor:
+    """Differentiable C2R (unnormalised) of a complex tensor [..., n/2 + 1] -> real [..., n]."""
+    if z.shape[-1] != n // 2 + 1:
+        raise ValueError(f"last axis must hold n/2 + 1 = {n // 2 + 1} values")
+    return _IRFFTFunction.apply(z, n)
 
 
 def copy_device(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:

@@ -108,7 +108,8 @@ struct fft_plan_s {
     // through the half length H = n/2 (log2h); `dec` describes the half length
     bool real = false;
     int log2h = 0;
-    const fftk::RealKernel* rk = nullptr;  // single-pass kernel
+    const fftk::RealKernel* rk = nullptr;      // single-pass kernel
+    const fftk::RealKernel* rk_adj = nullptr;  // the same shape in the other direction (backward)
     void* twn = nullptr;                   // w_n^k, k < H, in the plan's precision
     size_t rta_off = 0, rtb_off = 0;       // FP64 tables of w_n (pre/post pass)
     int rhbits = 0;
@@ -232,11 +233,14 @@ fft_status resolve(fft_plan p, const Decomp& dec) {
 
 // Real plans: the half-length chain (interleaved data; R2C forward, C2R
 // inverse), the fused single-pass kernel, or H = 1 (pre/post pass alone).
+// Kernels of both directions are resolved: the backward (adjoint) of an R2C
+// plan runs the C2R kernels and vice versa, on the same tables.
 fft_status resolve_real(fft_plan p, const Decomp& dec) {
     const bool split = p->layout == FFT_LAYOUT_SPLIT;
     const bool c2r = p->dir == FFT_INVERSE;
     p->dec = dec;
     p->rk = nullptr;
+    p->rk_adj = nullptr;
     p->steps.clear();
     p->twe_n = 0;
     p->tw64_n = 0;
@@ -258,22 +262,19 @@ fft_status resolve_real(fft_plan p, const Decomp& dec) {
             break;
         case Decomp::SINGLE:
             p->rk = fftk::find_real(p->rb, p->log2h, dec.log2e, dec.wgt, c2r, split, dec.twreg);
-            if (!p->rk) return FFT_ERR_NOT_SUPPORTED;
+            p->rk_adj = fftk::find_real(p->rb, p->log2h, dec.log2e, dec.wgt, !c2r, split, dec.twreg);
+            if (!p->rk || !p->rk_adj) return FFT_ERR_NOT_SUPPORTED;
             p->twe_n = p->rk->eng.tw_size;
             break;
         case Decomp::MULTI: {
             const size_t P = dec.log2l.size();
             int log2ns = 0;
-            int prev = c2r ? 1 : 0;  // C2R starts from the pre pass's output in workspace A
             for (size_t i = 0; i < P; ++i) {
                 PassStep st;
-                const bool last = i == P - 1;
-                // the chain runs in one direction only: forward (R2C) or inverse (C2R)
-                const fft_status rs = make_pass_step(p, dec, i, log2ns, false, c2r, &st);
+                // forward kernels (R2C) and inverse kernels (C2R) of each pass;
+                // the buffers of each pass are chosen at execution (run_real)
+                const fft_status rs = make_pass_step(p, dec, i, log2ns, false, false, &st);
                 if (rs != FFT_OK) return rs;
-                st.src = prev;
-                st.dst = (c2r && last) ? 3 : (prev == 1 ? 2 : 1);
-                prev = st.dst;
                 p->steps.push_back(st);
                 log2ns += dec.log2l[i];
             }
@@ -380,9 +381,9 @@ struct DeviceGuard {
 
 // Checks shared by execute and execute_backward (before any HIP call).
 // Real plans: the real array and the complex array(s) must not overlap at all.
-fft_status check_real_buffers(fft_plan p, const void* ia, const void* ib, const void* oa, const void* ob) {
+fft_status check_real_buffers(fft_plan p, const void* ia, const void* ib, const void* oa, const void* ob,
+                              bool c2r) {
     const bool split = p->layout == FFT_LAYOUT_SPLIT;
-    const bool c2r = p->dir == FFT_INVERSE;
     const void* ca = c2r ? ia : oa;  // complex side
     const void* cb = c2r ? ib : ob;
     const void* ra = c2r ? oa : ia;  // real side
@@ -399,9 +400,12 @@ fft_status check_real_buffers(fft_plan p, const void* ia, const void* ib, const 
     return FFT_OK;
 }
 
-fft_status run_real(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, hipStream_t s) {
+// One real transform in direction c2r (the plan's own, or the other one for
+// the backward); iscale scales the interior bins of the complex side (1, or
+// 1/2 and 2 for the adjoints of R2C and C2R).
+fft_status run_real(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, bool c2r, double iscale,
+                    hipStream_t s) {
     const bool split = p->layout == FFT_LAYOUT_SPLIT;
-    const bool c2r = p->dir == FFT_INVERSE;
     hipError_t e = hipSuccess;
     if (p->log2n == 0) {
         e = fftk::launch_real1(p->rb, c2r, split, ia, ib, oa, ob, p->batch, s);
@@ -412,13 +416,15 @@ fft_status run_real(fft_plan p, const void* ia, const void* ib, void* oa, void* 
     switch (p->dec.kind) {
         case Decomp::OPS:
             return FFT_ERR_NOT_SUPPORTED;
-        case Decomp::COPY:  // H = 1: the pre/post pass is the whole transform
-            e = c2r ? fftk::launch_c2r_pre(p->rb, split, ia, ib, oa, ta, tb, p->rhbits, 0, p->batch, s)
-                    : fftk::launch_r2c_post(p->rb, split, ia, oa, ob, ta, tb, p->rhbits, 0, p->batch, s);
+        case Decomp::COPY:  // H = 1: the pre/post pass is the whole transform (no interior bins)
+            e = c2r ? fftk::launch_c2r_pre(p->rb, split, ia, ib, oa, ta, tb, p->rhbits, 0, p->batch, iscale, s)
+                    : fftk::launch_r2c_post(p->rb, split, ia, oa, ob, ta, tb, p->rhbits, 0, p->batch, iscale, s);
             return e == hipSuccess ? FFT_OK : fail_hip(e, "real pre/post launch");
-        case Decomp::SINGLE:
-            e = p->rk->fn(ia, ib, oa, ob, p->twe, p->twn, p->batch, p->dec.gmul * p->cus, s);
+        case Decomp::SINGLE: {
+            const fftk::RealKernel* k = c2r == p->rk->c2r ? p->rk : p->rk_adj;
+            e = k->fn(ia, ib, oa, ob, p->twe, p->twn, p->batch, p->dec.gmul * p->cus, iscale, s);
             return e == hipSuccess ? FFT_OK : fail_hip(e, "real single-pass launch");
+        }
         case Decomp::MULTI: {
             if (!p->ws()) {
                 g_detail = "no workspace";
@@ -426,23 +432,30 @@ fft_status run_real(fft_plan p, const void* ia, const void* ib, void* oa, void* 
             }
             const size_t half = (size_t(1) << p->log2h) * size_t(p->batch) * p->cbytes();
             void* ws[3] = {nullptr, p->ws(), static_cast<char*>(p->ws()) + half};
+            // buffers: 0 the caller's input, 1/2 the workspace halves, 3 the
+            // caller's output; C2R starts from the pre pass's output in half 1
+            int prev = 0;
             if (c2r) {
-                e = fftk::launch_c2r_pre(p->rb, split, ia, ib, ws[1], ta, tb, p->rhbits, p->log2h, p->batch, s);
+                e = fftk::launch_c2r_pre(p->rb, split, ia, ib, ws[1], ta, tb, p->rhbits, p->log2h, p->batch, iscale, s);
                 if (e != hipSuccess) return fail_hip(e, "C2R pre-pass launch");
+                prev = 1;
             }
-            int last = 0;
-            for (const PassStep& st : p->steps) {
-                const void* src = st.src == 0 ? ia : ws[st.src];
-                void* dst = st.dst == 3 ? oa : ws[st.dst];
-                const int stream = (st.src == 0 ? fftk::kStreamIn : 0) | (st.dst == 3 ? fftk::kStreamOut : 0);
-                e = st.k->fn(src, nullptr, dst, nullptr, static_cast<const char*>(p->twe) + st.twe_off * p->cbytes(),
-                             p->tw64 + st.ta_off, p->tw64 + st.tb_off, p->log2h, st.log2ns, st.hbits, p->batch,
-                             st.grid, stream, s);
+            for (size_t i = 0; i < p->steps.size(); ++i) {
+                const PassStep& st = p->steps[i];
+                const int dst = (c2r && i + 1 == p->steps.size()) ? 3 : (prev == 1 ? 2 : 1);
+                const void* src = prev == 0 ? ia : ws[prev];
+                void* out = dst == 3 ? oa : ws[dst];
+                const int stream = (prev == 0 ? fftk::kStreamIn : 0) | (dst == 3 ? fftk::kStreamOut : 0);
+                const fftk::PassKernel* k = c2r ? st.k_inv : st.k;
+                e = k->fn(src, nullptr, out, nullptr, static_cast<const char*>(p->twe) + st.twe_off * p->cbytes(),
+                          p->tw64 + st.ta_off, p->tw64 + st.tb_off, p->log2h, st.log2ns, st.hbits, p->batch,
+                          st.grid, stream, s);
                 if (e != hipSuccess) return fail_hip(e, "pass launch");
-                last = st.dst;
+                prev = dst;
             }
             if (!c2r) {
-                e = fftk::launch_r2c_post(p->rb, split, ws[last], oa, ob, ta, tb, p->rhbits, p->log2h, p->batch, s);
+                e = fftk::launch_r2c_post(p->rb, split, ws[prev], oa, ob, ta, tb, p->rhbits, p->log2h, p->batch,
+                                          iscale, s);
                 if (e != hipSuccess) return fail_hip(e, "R2C post-pass launch");
             }
             return FFT_OK;
@@ -451,9 +464,10 @@ fft_status run_real(fft_plan p, const void* ia, const void* ib, void* oa, void* 
     return FFT_ERR_INVALID_ARG;
 }
 
-fft_status check_buffers(fft_plan p, const void* ia, const void* ib, const void* oa, const void* ob) {
+fft_status check_buffers(fft_plan p, const void* ia, const void* ib, const void* oa, const void* ob,
+                         bool adjoint) {
     if (!plan_ok(p)) return FFT_ERR_INVALID_ARG;
-    if (p->real) return check_real_buffers(p, ia, ib, oa, ob);
+    if (p->real) return check_real_buffers(p, ia, ib, oa, ob, (p->dir == FFT_INVERSE) != adjoint);
     const bool split = p->layout == FFT_LAYOUT_SPLIT;
     if (!ia || !oa || (split && (!ib || !ob))) return FFT_ERR_NULL_POINTER;
     auto mis = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) != 0; };
@@ -496,16 +510,17 @@ fft_status run_nd(fft_plan p, const void* ia, const void* ib, void* oa, void* ob
 }
 
 fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, void* stream, bool adjoint) {
-    if (plan_ok(p) && p->real && adjoint) {
-        g_detail = "real-input plans have no backward";
-        return FFT_ERR_NOT_SUPPORTED;
-    }
-    fft_status st = check_buffers(p, ia, ib, oa, ob);
+    fft_status st = check_buffers(p, ia, ib, oa, ob, adjoint);
     if (st != FFT_OK) return st;
     DeviceGuard guard(p->device);
     if (p->rank > 1) return run_nd(p, ia, ib, oa, ob, stream, adjoint);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (p->real) return run_real(p, ia, ib, oa, ob, s);
+    if (p->real) {
+        // the backward of R2C is C2R with the interior bins halved, of C2R
+        // R2C with them doubled (the adjoints under the real inner product)
+        const bool c2r = (p->dir == FFT_INVERSE) != adjoint;
+        return run_real(p, ia, ib, oa, ob, c2r, adjoint ? (c2r ? 0.5 : 2.0) : 1.0, s);
+    }
     // forward kernels everywhere; the inverse swaps re and im on the way in and
     // out: split arrays by exchanging the pointers, interleaved data in-kernel
     const bool inverse = (p->dir == FFT_INVERSE) != adjoint;

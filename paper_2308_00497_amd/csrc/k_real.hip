@@ -11,7 +11,7 @@ namespace fftk {
 template <class R, bool SPLIT>
 __global__ void __launch_bounds__(256) k_r2c_post(const R* __restrict__ z, R* oa, R* ob, const double2* __restrict__ ta,
                                                   const double2* __restrict__ tb, int hbits, int log2h,
-                                                  int64_t batch) {
+                                                  int64_t batch, R iscale) {
     using V = cplx_t<R>;
     const int64_t H = int64_t(1) << log2h;
     const int64_t pairs = H / 2 + 1;
@@ -26,12 +26,16 @@ __global__ void __launch_bounds__(256) k_r2c_post(const R* __restrict__ z, R* oa
         V ev, wo;
         r2c_parts(a, mir, w, ev, wo);
         const int64_t o = b * (H + 1);
-        gstore<SPLIT>(oa, ob, o + k, c_add(ev, wo));
         if (k == 0) {
+            gstore<SPLIT>(oa, ob, o, c_add(ev, wo));
             gstore<SPLIT>(oa, ob, o + H, cmk(a.x - a.y, R(0)));
-        } else if (H - k != k) {
-            const V d = c_sub(ev, wo);
-            gstore<SPLIT>(oa, ob, o + H - k, cmk(d.x, -d.y));
+        } else {
+            // interior bins k and H - k (scaled for the adjoint of C2R)
+            gstore<SPLIT>(oa, ob, o + k, c_scale(c_add(ev, wo), iscale));
+            if (H - k != k) {
+                const V d = c_sub(ev, wo);
+                gstore<SPLIT>(oa, ob, o + H - k, c_scale(cmk(d.x, -d.y), iscale));
+            }
         }
     }
 }
@@ -41,7 +45,7 @@ __global__ void __launch_bounds__(256) k_r2c_post(const R* __restrict__ z, R* oa
 template <class R, bool SPLIT>
 __global__ void __launch_bounds__(256) k_c2r_pre(const R* ia, const R* ib, R* __restrict__ z,
                                                  const double2* __restrict__ ta, const double2* __restrict__ tb,
-                                                 int hbits, int log2h, int64_t batch) {
+                                                 int hbits, int log2h, int64_t batch, R iscale) {
     using V = cplx_t<R>;
     const int64_t H = int64_t(1) << log2h;
     const int64_t pairs = H / 2 + 1;
@@ -57,8 +61,9 @@ __global__ void __launch_bounds__(256) k_c2r_pre(const R* ia, const R* ib, R* __
         if (k == 0) {
             zr[0] = c2r_point(cmk(a.x, R(0)), cmk(mir.x, R(0)), w);
         } else {
-            zr[k] = c2r_point(a, mir, w);
-            if (H - k != k) zr[H - k] = c2r_point(mir, a, cmk(-w.x, w.y));
+            // interior bins only (scaled for the adjoint of R2C)
+            zr[k] = c_scale(c2r_point(a, mir, w), iscale);
+            if (H - k != k) zr[H - k] = c_scale(c2r_point(mir, a, cmk(-w.x, w.y)), iscale);
         }
     }
 }
@@ -91,11 +96,11 @@ static unsigned elementwise_blocks(int64_t items) {
 }
 
 hipError_t launch_r2c_post(int rb, bool split, const void* z, void* oa, void* ob, const double2* ta,
-                           const double2* tb, int hbits, int log2h, int64_t batch, hipStream_t s) {
+                           const double2* tb, int hbits, int log2h, int64_t batch, double iscale, hipStream_t s) {
     const unsigned blocks = elementwise_blocks(((int64_t(1) << log2h) / 2 + 1) * batch);
 #define FFT_POST(R, S)                                                                                          \
     hipLaunchKernelGGL((k_r2c_post<R, S>), dim3(blocks), dim3(256), 0, s, static_cast<const R*>(z),             \
-                       static_cast<R*>(oa), static_cast<R*>(ob), ta, tb, hbits, log2h, batch)
+                       static_cast<R*>(oa), static_cast<R*>(ob), ta, tb, hbits, log2h, batch, static_cast<R>(iscale))
     if (rb == 8) {
         if (split) FFT_POST(double, true);
         else FFT_POST(double, false);
@@ -108,11 +113,11 @@ hipError_t launch_r2c_post(int rb, bool split, const void* z, void* oa, void* ob
 }
 
 hipError_t launch_c2r_pre(int rb, bool split, const void* ia, const void* ib, void* z, const double2* ta,
-                          const double2* tb, int hbits, int log2h, int64_t batch, hipStream_t s) {
+                          const double2* tb, int hbits, int log2h, int64_t batch, double iscale, hipStream_t s) {
     const unsigned blocks = elementwise_blocks(((int64_t(1) << log2h) / 2 + 1) * batch);
 #define FFT_PRE(R, S)                                                                                           \
     hipLaunchKernelGGL((k_c2r_pre<R, S>), dim3(blocks), dim3(256), 0, s, static_cast<const R*>(ia),             \
-                       static_cast<const R*>(ib), static_cast<R*>(z), ta, tb, hbits, log2h, batch)
+                       static_cast<const R*>(ib), static_cast<R*>(z), ta, tb, hbits, log2h, batch, static_cast<R>(iscale))
     if (rb == 8) {
         if (split) FFT_PRE(double, true);
         else FFT_PRE(double, false);

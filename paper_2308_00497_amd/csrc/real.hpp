@@ -20,11 +20,23 @@
 // exchange through LDS that pairs k with H - k.  Larger sizes run the
 // half-length multi-pass chain and one extra pass over HBM (k_r2c_post,
 // k_c2r_pre).
+//
+// Adjoints (the backward of a real plan): with the real inner product on the
+// complex side, the adjoint of R2C maps g (H + 1 values) to
+// x[n] = Re sum_{k=0..H} g[k] w_N^-kn, which is C2R of g with the interior
+// bins k = 1 .. H-1 halved; the adjoint of C2R is R2C with the interior bins
+// doubled.  Every kernel below takes that interior scale (1 for the plain
+// transforms).
 #pragma once
 
 #include "kernels.hpp"
 
 namespace fftk {
+
+template <class V>
+__device__ __forceinline__ V c_scale(V a, typename RealOf<V>::type s) {
+    return cmk(a.x * s, a.y * s);
+}
 
 // Ev[k] and w Od[k] for a = Z[k], mir = Z[(H-k) mod H], w = w_N^k:
 // X[k] = ev + wo and X[H-k] = conj(ev - wo)
@@ -64,7 +76,7 @@ struct RealShape {
 template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG>
 __global__ void __launch_bounds__((SingleShape<LOG2H, LOG2E, WGT>::THREADS))
 k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw,
-              const cplx_t<R>* __restrict__ twn, int64_t batch) {
+              const cplx_t<R>* __restrict__ twn, int64_t batch, R iscale) {
     using V = cplx_t<R>;
     using SH = SingleShape<LOG2H, LOG2E, WGT>;
     using SC = typename SH::SC;
@@ -111,7 +123,8 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
                     const V mir = xch[lds_at<SH::GS>(gl, (H - k) & (H - 1))];
                     V ev, wo;
                     r2c_parts(v[m], mir, wn[m], ev, wo);
-                    gstore_nt<SPLIT>(oa, ob, ob0 + k, c_add(ev, wo));
+                    const V xk = c_add(ev, wo);
+                    gstore_nt<SPLIT>(oa, ob, ob0 + k, k == 0 ? xk : c_scale(xk, iscale));
                 }
                 if (tl == 0) gstore_nt<SPLIT>(oa, ob, ob0 + H, cmk(v[0].x - v[0].y, R(0)));
             }
@@ -135,8 +148,10 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
                 } else {
                     mir = xch[lds_at<SH::GS>(gl, H - k)];
                 }
-                // inverse DFT_H = S DFT_H S: swap on the way in and out
-                v[m] = swap_if<true>(c2r_point(a, mir, wn[m]));
+                // inverse DFT_H = S DFT_H S: swap on the way in and out;
+                // Z'[k], k > 0, is built from interior bins only
+                const V zk = c2r_point(a, mir, wn[m]);
+                v[m] = swap_if<true>(k == 0 ? zk : c_scale(zk, iscale));
             }
             if constexpr (TWREG) ENG::run(v, lds, twr, tidl);
             else ENG::run(v, lds, TwMem<SC, V>(twl), tidl);
@@ -151,7 +166,7 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
 
 template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG>
 hipError_t launch_real_single(const void* ia, const void* ib, void* oa, void* ob, const void* tw, const void* twn,
-                              int64_t batch, int grid, hipStream_t s) {
+                              int64_t batch, int grid, double iscale, hipStream_t s) {
     using SH = SingleShape<LOG2H, LOG2E, WGT>;
     const int64_t groups = (batch + SH::G - 1) / SH::G;
     const int64_t blocks = groups < grid ? groups : grid;
@@ -159,7 +174,7 @@ hipError_t launch_real_single(const void* ia, const void* ib, void* oa, void* ob
     hipLaunchKernelGGL((k_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG>), dim3(static_cast<unsigned>(blocks)),
                        dim3(SH::THREADS), 0, s, static_cast<const R*>(ia), static_cast<const R*>(ib),
                        static_cast<R*>(oa), static_cast<R*>(ob), static_cast<const cplx_t<R>*>(tw),
-                       static_cast<const cplx_t<R>*>(twn), batch);
+                       static_cast<const cplx_t<R>*>(twn), batch, static_cast<R>(iscale));
     return hipGetLastError();
 }
 

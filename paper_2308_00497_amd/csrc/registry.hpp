@@ -77,8 +77,10 @@ struct PassKernel {
 // Single-pass real-input kernel (R2C, or C2R when c2r): half length
 // H = 2^log2h; `tw` is the engine stage table and `twn` holds w_N^k, k < H,
 // N = 2H, both in the kernel's precision.
+// iscale multiplies the interior bins k = 1 .. H-1 of the complex side (1 for
+// the transforms themselves; 1/2 and 2 give the adjoints of R2C and C2R).
 using real_fn = hipError_t (*)(const void* ia, const void* ib, void* oa, void* ob, const void* tw, const void* twn,
-                               int64_t batch, int grid, hipStream_t s);
+                               int64_t batch, int grid, double iscale, hipStream_t s);
 
 struct RealKernel {
     int real_bytes;
@@ -126,10 +128,11 @@ const StridedKernel* strided_kernels(int* count);
 
 // passes over HBM around the multi-pass half-length transform of real plans
 // (z: interleaved half-length data; ta/tb: FP64 tables of w_N, N = 2^(log2h+1))
+// (iscale: the interior-bin scale of real_fn)
 hipError_t launch_r2c_post(int rb, bool split, const void* z, void* oa, void* ob, const double2* ta,
-                           const double2* tb, int hbits, int log2h, int64_t batch, hipStream_t s);
+                           const double2* tb, int hbits, int log2h, int64_t batch, double iscale, hipStream_t s);
 hipError_t launch_c2r_pre(int rb, bool split, const void* ia, const void* ib, void* z, const double2* ta,
-                          const double2* tb, int hbits, int log2h, int64_t batch, hipStream_t s);
+                          const double2* tb, int hbits, int log2h, int64_t batch, double iscale, hipStream_t s);
 // per-operator baseline (Table 1 operators, one kernel each; interleaved data)
 hipError_t launch_op_kron(int rb, int log2r, const void* x, void* y, int64_t a, int64_t b, bool swap_in,
                           bool swap_out, hipStream_t s);

@@ -48,3 +48,24 @@ def assert_parity(y: np.ndarray, ref: np.ndarray, what: str, tol: float = TOL) -
     print(f"[parity] {what}: max per-transform rel-L2 {worst:.3e}", flush=True)
     assert worst <= tol, f"{what}: rel-L2 {worst:.3e} > {tol}"
     return worst
+
+
+def r2c_vjp_definition(g: np.ndarray, n: int) -> np.ndarray:
+    """x[m] = Re sum_{k=0..n/2} g[k] exp(+2 pi i k m / n): the vector-Jacobian
+    product of R2C from its definition (dX_k/dx_m = exp(-2 pi i k m / n)),
+    through the oracle's complex DFT of g padded with zeros to length n."""
+    b = g.shape[0]
+    pad = np.zeros((b, n), dtype=np.complex128)
+    pad[:, :n // 2 + 1] = g[:, :n // 2 + 1]
+    return oracle.fft(pad, +1, threads=8).real
+
+
+def c2r_vjp_bruteforce(g: np.ndarray, n: int) -> np.ndarray:
+    """The vector-Jacobian product of C2R by brute force: column k of the
+    Jacobian is the oracle's irfft of the unit vector e_k (real part) or
+    i e_k (imaginary part), so G_k = <g, irfft(e_k)> + i <g, irfft(i e_k)>."""
+    h = n // 2 + 1
+    units = np.concatenate([np.eye(h), 1j * np.eye(h)]).astype(np.complex128)
+    cols = oracle.irfft(units, n, threads=8)  # (2h, n)
+    dots = g.astype(np.float64) @ cols.T      # (b, 2h)
+    return dots[:, :h] + 1j * dots[:, h:]

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import workloads
-from fftcheck import TOL, TOL64, assert_parity
+from fftcheck import TOL, TOL64, assert_parity, c2r_vjp_bruteforce, r2c_vjp_definition
 
 pytestmark = pytest.mark.gpu
 
@@ -165,12 +165,98 @@ def test_r2c_batched_4096_sampled(fftlib):
 
 def test_real_plan_errors(fftlib):
     with fftlib.RealPlan(64, 2, "interleaved", "forward") as p:
-        with pytest.raises(fftlib.FFTError):
+        with pytest.raises(TypeError):  # the backward of R2C takes the complex side
             p.backward(torch.zeros(128, device="cuda"))
         with pytest.raises(TypeError):
             p.execute(torch.zeros(128, dtype=torch.float64, device="cuda"))
+        # backward buffers: complex in, real out, no overlap either
+        buf = torch.zeros(1024, dtype=torch.float32, device="cuda")
+        from paper_2308_00497_amd._lib import lib as clib
+        assert clib.fft_execute_backward(p._handle, buf.data_ptr(), None, buf.data_ptr() + 256, None, None) == 2
         # the complex output may not overlap the real input
         buf = torch.zeros(1024, dtype=torch.float32, device="cuda")
         from paper_2308_00497_amd._lib import lib
         rc = lib.fft_execute(p._handle, buf.data_ptr(), None, buf.data_ptr() + 256, None, None)
         assert rc == 2
+
+
+# ---- backward (adjoint) of real plans -------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("layout", ["interleaved", "split"])
+@pytest.mark.parametrize("log2n", [0, 1, 2, 3, 5, 9, 12, 13, 14, 15, 17, 20])
+def test_r2c_backward_matches_definition(fftlib, log2n, layout, precision):
+    n = 1 << log2n
+    dt, tol = PREC[precision]
+    b = batch_for(n)
+    re, im = half_spectra(b, n, 8600 + log2n, dt)
+    with fftlib.RealPlan(n, b, layout, "forward", precision) as p:
+        x = p.backward(complex_to_device(re, im, layout))
+        torch.cuda.synchronize()
+        d = p.describe()["decomposition"]
+    ref = r2c_vjp_definition(re.astype(np.float64) + 1j * im.astype(np.float64), n)
+    assert_parity(x.cpu().numpy().astype(np.float64), ref, f"R2C backward {precision} n=2^{log2n} {layout} {d}", tol)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("layout", ["interleaved", "split"])
+@pytest.mark.parametrize("log2n", [0, 1, 2, 3, 5, 8, 10])
+def test_c2r_backward_bruteforce(fftlib, log2n, layout, precision):
+    n = 1 << log2n
+    dt, tol = PREC[precision]
+    g = real_rows(5, n, 8700 + log2n, dt)
+    with fftlib.RealPlan(n, 5, layout, "inverse", precision) as p:
+        G = complex_from_device(p.backward(torch.from_numpy(g).cuda()), layout)
+    assert_parity(G, c2r_vjp_bruteforce(g, n), f"C2R backward {precision} n=2^{log2n} {layout}", tol)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("log2n", [4, 11, 13, 14, 15, 16, 19, 22])
+def test_real_adjoint_dot(fftlib, log2n, precision):
+    """<R2C x, Y> = <x, R2C^H Y> and <C2R Y, x> = <Y, C2R^H x> (real inner
+    products), single-pass and multi-pass sizes, every plan on the GPU."""
+    n = 1 << log2n
+    dt, tol = PREC[precision]
+    b = 2
+    x = real_rows(b, n, 8800 + log2n, dt)
+    re, im = half_spectra(b, n, 8900 + log2n, dt)
+    Y = re.astype(np.float64) + 1j * im.astype(np.float64)
+    xt = torch.from_numpy(x).cuda()
+    Yt = complex_to_device(re, im, "interleaved")
+    with fftlib.RealPlan(n, b, "interleaved", "forward", precision) as f, \
+            fftlib.RealPlan(n, b, "interleaved", "inverse", precision) as c:
+        X = complex_from_device(f.execute(xt), "interleaved")
+        xa = f.backward(Yt).cpu().numpy().astype(np.float64)
+        xc = c.execute(Yt).cpu().numpy().astype(np.float64)
+        Ya = complex_from_device(c.backward(xt), "interleaved")
+    x64 = x.astype(np.float64)
+    for lhs, rhs, what in ((np.sum(np.real(np.conj(X) * Y)), np.sum(x64 * xa), "R2C"),
+                           (np.sum(xc * x64), np.sum(np.real(np.conj(Y) * Ya)), "C2R")):
+        scale = np.sqrt(n) * np.linalg.norm(x64) * np.linalg.norm(Y)
+        assert abs(lhs - rhs) <= 8 * tol * scale, (what, n, lhs, rhs)
+
+
+@pytest.mark.parametrize("n", [2, 8, 32])
+def test_real_autograd_gradcheck(fftlib, n):
+    """torch.autograd.gradcheck (FP64 finite differences against the backward
+    kernels) for rfft_autograd and irfft_autograd."""
+    x = torch.randn(3, n, dtype=torch.float64, device="cuda", requires_grad=True)
+    assert torch.autograd.gradcheck(fftlib.rfft_autograd, (x,), eps=1e-6, atol=1e-8, rtol=1e-6)
+    z = torch.randn(3, n // 2 + 1, dtype=torch.complex128, device="cuda", requires_grad=True)
+    assert torch.autograd.gradcheck(lambda t: fftlib.irfft_autograd(t, n), (z,), eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+def test_real_autograd_loss_gradient(fftlib):
+    """L = sum w |rfft(x)|^2 over batch 256 x 4096 (FP32): x.grad against the
+    oracle's vector-Jacobian product of R2C applied to 2 w X."""
+    b, n = 256, 4096
+    rng = np.random.default_rng(8950)
+    x = rng.standard_normal((b, n)).astype(np.float32)
+    w = rng.uniform(0.0, 1.0, (b, n // 2 + 1)).astype(np.float32)
+    xt = torch.from_numpy(x).cuda().requires_grad_(True)
+    wt = torch.from_numpy(w).cuda()
+    X = fftlib.rfft_autograd(xt)
+    (wt * (X.real * X.real + X.imag * X.imag)).sum().backward()
+    Xo = oracle.rfft(x, threads=8)
+    ref = r2c_vjp_definition(2.0 * w.astype(np.float64) * Xo, n)
+    assert_parity(xt.grad.cpu().numpy().astype(np.float64), ref, "rfft autograd 256 x 4096", TOL)

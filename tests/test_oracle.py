@@ -473,6 +473,39 @@ def test_rfft_dc_and_nyquist(n):
     assert np.all(got[:, 0].imag == 0) and np.all(got[:, -1].imag == 0)
 
 
+@pytest.mark.parametrize("n", [1, 2, 4, 16, 64])
+def test_real_vjp_references(n):
+    """The references the GPU tests hold the backward of real plans to.
+    R2C: the definition-based product equals the brute-force vector-Jacobian
+    product (Jacobian rows from rfft of unit vectors), and satisfies
+    Re<rfft x, g> = <x, vjp(g)>.  C2R: the brute-force product satisfies
+    <irfft X, g> = Re<X, vjp(g)> and has real DC and Nyquist bins.  Both also
+    match the forms the kernels use: C2R of g with bins 1 .. n/2-1 halved, and
+    R2C of g with those bins doubled."""
+    from fftcheck import c2r_vjp_bruteforce, r2c_vjp_definition
+    rng = np.random.default_rng(1300 + n)
+    h = n // 2 + 1
+    g = rng.standard_normal((3, h)) + 1j * rng.standard_normal((3, h))
+    x = rng.standard_normal((3, n))
+    jac = oracle.rfft(np.eye(n))                            # (n, h): dX_k/dx_m
+    brute = np.real(np.conj(g) @ jac.T)                     # torch convention
+    vjp = r2c_vjp_definition(g, n)
+    assert np.abs(vjp - brute).max() <= 1e-12 * n
+    lhs = np.sum(np.real(np.conj(oracle.rfft(x)) * g))
+    assert abs(lhs - np.sum(x * vjp)) <= 1e-10 * n
+    half = g.copy()
+    half[:, 1:n // 2] *= 0.5
+    assert np.abs(oracle.irfft(half, n) - vjp).max() <= 1e-12 * n
+    gr = rng.standard_normal((3, n))
+    G = c2r_vjp_bruteforce(gr, n)
+    X = rng.standard_normal((3, h)) + 1j * rng.standard_normal((3, h))
+    assert abs(np.sum(oracle.irfft(X, n) * gr) - np.sum(np.real(np.conj(X) * G))) <= 1e-10 * n
+    assert np.abs(G[:, 0].imag).max() <= 1e-12 and np.abs(G[:, -1].imag).max() <= 1e-12
+    dbl = oracle.rfft(gr)
+    dbl[:, 1:n // 2] *= 2.0
+    assert np.abs(dbl - G).max() <= 1e-12 * n
+
+
 @pytest.mark.parametrize("n", [1, 2, 64, 4096])
 def test_real_round_trip(n):
     x = np.random.default_rng(1200 + n).standard_normal((3, n))
