@@ -35,6 +35,16 @@ static const SingleKernel kSingle[] = {
     single_entry<float, 14, 4, 256, true, false, false, true>(),
     single_entry<float, 13, 4, 256, false, false, true, true>(), single_entry<float, 13, 4, 256, false, true, true, true>(),
     single_entry<float, 13, 4, 256, true, false, true, true>(),
+    // small transforms (each inside one wavefront): contiguous loads and
+    // stores staged through LDS
+#define FFT_ST(n, e)                                                                                        \
+    single_entry<float, n, e, 256, false, false, true, false, true>(),                                      \
+        single_entry<float, n, e, 256, false, true, true, false, true>(),                                   \
+        single_entry<float, n, e, 256, true, false, true, false, true>()
+    FFT_ST(1, 4), FFT_ST(2, 4), FFT_ST(3, 4),
+    FFT_ST(4, 4), FFT_ST(4, 3), FFT_ST(5, 4), FFT_ST(5, 3), FFT_ST(6, 4), FFT_ST(6, 3),
+    FFT_ST(7, 4), FFT_ST(7, 3), FFT_ST(8, 4), FFT_ST(8, 3), FFT_ST(9, 4), FFT_ST(9, 3),
+#undef FFT_ST
 };
 
 #undef FFT_S

@@ -51,6 +51,14 @@ struct SingleShape {
     static constexpr bool WAVE = SC::T <= 64;
 };
 
+// LDS elements of a single-pass workgroup: the engine's exchange, or with
+// staging the whole group (every group padded as in the engine)
+template <int LOG2N, int LOG2E, int WGT, bool STG>
+constexpr int single_lds() {
+    using SH = SingleShape<LOG2N, LOG2E, WGT>;
+    return STG && SH::G * SH::GS > SH::LDS ? SH::G * SH::GS : SH::LDS;
+}
+
 // Persistent: each workgroup loops over groups of G transforms
 // (grp = blockIdx.x, blockIdx.x + gridDim.x, ...), so per-thread state such as
 // register-resident twiddles is loaded once per workgroup.  Data is read and
@@ -59,15 +67,23 @@ struct SingleShape {
 // transform; split arrays get the same effect from swapped pointers).  With PF
 // the loads of the workgroup's next group are issued before the stages of the
 // current one run, so HBM reads overlap the LDS work (the stage barriers
-// order LDS only and leave them in flight).
-template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false>
+// order LDS only and leave them in flight).  With STG (small transforms, each
+// inside one wavefront) a wavefront's transforms, which are contiguous in
+// memory, are read and written as one contiguous run (lane l takes elements
+// l, l + 64, ...) and staged through LDS into the engine's layout, instead of
+// each lane reading its own points at stride T.
+template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false,
+          bool STG = false>
 __global__ void __launch_bounds__((SingleShape<LOG2N, LOG2E, WGT>::THREADS))
 k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw, int64_t batch) {
     using V = cplx_t<R>;
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
     using SC = typename SH::SC;
     constexpr int E = SC::E, T = SC::T, L = SC::L, G = SH::G;
-    __shared__ V lds[SH::LDS];
+    static_assert(!(STG && PF), "staging and prefetching are separate variants");
+    static_assert(!STG || (SH::WAVE && (64 % T) == 0 && SH::THREADS % 64 == 0),
+                  "staging needs every transform inside one wavefront");
+    __shared__ V lds[single_lds<LOG2N, LOG2E, WGT, STG>()];
 
     const int tid = threadIdx.x;
     TwReg<SC, V> twr(tw);
@@ -108,6 +124,41 @@ k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ t
         int tidl = tid;
         asm volatile("" : "+v"(tidl));
         if constexpr (!TWREG) asm volatile("" : "+s"(twl));
+        if constexpr (STG) {
+            // this wavefront's transforms: elements w0 .. w0 + 64 E - 1 of the group
+            const int lane = tidl & 63, w0 = (tidl >> 6) * 64 * E;
+            const int64_t row0 = group_of(grp) * G;
+            const int64_t ebase = row0 * L;
+            V v[E];
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int i = w0 + lane + 64 * m;
+                v[m] = row0 + i / L < batch ? swap_if<SWAP>(gload_nt<SPLIT>(ia, ib, ebase + i)) : c_zero<V>();
+            }
+            stage_sync<true>();  // this wavefront's reads of the previous group are done
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int i = w0 + lane + 64 * m;
+                lds[lds_at<SH::GS>(i / L, i % L)] = v[m];
+            }
+            stage_sync<true>();
+            const int t = tidl % T, g = tidl / T;  // the engine's first mapping
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = lds[lds_at<SH::GS>(g, t + T * m)];
+            if constexpr (TWREG) Engine<SC, G, SH::GS, false, false, true>::run(v, lds, twr, tidl);
+            else Engine<SC, G, SH::GS, false, false, true>::run(v, lds, TwMem<SC, V>(twl), tidl);
+            stage_sync<true>();  // the engine's (or the staging's) last reads are done
+#pragma unroll
+            for (int m = 0; m < E; ++m) lds[lds_at<SH::GS>(g, t + T * m)] = v[m];
+            stage_sync<true>();
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int i = w0 + lane + 64 * m;
+                if (row0 + i / L < batch)
+                    gstore_nt<SPLIT>(oa, ob, ebase + i, swap_if<SWAP>(lds[lds_at<SH::GS>(i / L, i % L)]));
+            }
+            continue;
+        }
         bool active;
         const int64_t base = row_base(grp, tidl, active);
         V v[E];
@@ -136,14 +187,14 @@ k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ t
     }
 }
 
-template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false>
+template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false, bool STG = false>
 hipError_t launch_single(const void* ia, const void* ib, void* oa, void* ob, const void* tw, int64_t batch, int grid,
                          hipStream_t s) {
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
     const int64_t groups = (batch + SH::G - 1) / SH::G;
     const int64_t blocks = groups < grid ? groups : grid;
     if (blocks < 1) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF>), dim3(static_cast<unsigned>(blocks)),
+    hipLaunchKernelGGL((k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG>), dim3(static_cast<unsigned>(blocks)),
                        dim3(SH::THREADS), 0, s, static_cast<const R*>(ia), static_cast<const R*>(ib),
                        static_cast<R*>(oa), static_cast<R*>(ob), static_cast<const cplx_t<R>*>(tw), batch);
     return hipGetLastError();
@@ -165,7 +216,7 @@ EngineInfo engine_info() {
     return e;
 }
 
-template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false>
+template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false, bool STG = false>
 SingleKernel single_entry() {
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
     SingleKernel k{};
@@ -177,12 +228,13 @@ SingleKernel single_entry() {
     k.swap = SWAP;
     k.twreg = TWREG;
     k.pf = PF;
-    k.fn = &launch_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF>;
-    k.kernel = reinterpret_cast<const void*>(&k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF>);
+    k.stg = STG;
+    k.fn = &launch_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG>;
+    k.kernel = reinterpret_cast<const void*>(&k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG>);
     k.eng = engine_info<typename SH::SC>();
     k.threads = SH::THREADS;
     k.per_wg = SH::G;
-    k.lds_bytes = SH::LDS * sizeof(cplx_t<R>);
+    k.lds_bytes = single_lds<LOG2N, LOG2E, WGT, STG>() * sizeof(cplx_t<R>);
     return k;
 }
 

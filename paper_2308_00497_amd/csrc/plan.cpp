@@ -27,7 +27,8 @@ std::string Decomp::str() const {
         case COPY:
             return "copy";
         case SINGLE:
-            snprintf(buf, sizeof buf, "single:e%d:w%d:g%d:r%d%s", log2e, wgt, gmul, twreg ? 1 : 0, pf ? ":p1" : "");
+            snprintf(buf, sizeof buf, "single:e%d:w%d:g%d:r%d%s", log2e, wgt, gmul, twreg ? 1 : 0,
+                     pf ? ":p1" : (stg ? ":s1" : ""));
             return buf;
         case OPS:
             snprintf(buf, sizeof buf, "ops:r%d", log2r);
@@ -51,18 +52,20 @@ bool Decomp::parse(const std::string& s, Decomp* out) {
         *out = d;
         return true;
     }
-    int e = 0, w = 0, g = 0, r = 0, pf = 0, used = 0;
-    const bool five = sscanf(s.c_str(), "single:e%d:w%d:g%d:r%d:p%d%n", &e, &w, &g, &r, &pf, &used) == 5 &&
-                      used == (int)s.size();
-    if (five || (sscanf(s.c_str(), "single:e%d:w%d:g%d:r%d%n", &e, &w, &g, &r, &used) == 4 && used == (int)s.size())) {
+    int e = 0, w = 0, g = 0, r = 0, used = 0;
+    if (sscanf(s.c_str(), "single:e%d:w%d:g%d:r%d%n", &e, &w, &g, &r, &used) == 4) {
+        // optional variant: ":p1" prefetching, ":s1" staged (":p0"/":s0" are
+        // spelled by leaving the field out)
+        const std::string rest = s.substr(used);
+        if (!rest.empty() && rest != ":p1" && rest != ":s1") return false;
         if (g < 1 || g > 64 || (r != 0 && r != 1)) return false;
-        if (five && pf != 1) return false;  // ":p0" is spelled by leaving the field out
         d.kind = SINGLE;
         d.log2e = e;
         d.wgt = w;
         d.gmul = g;
         d.twreg = r == 1;
-        d.pf = five;
+        d.pf = rest == ":p1";
+        d.stg = rest == ":s1";
         *out = d;
         return true;
     }
@@ -93,13 +96,14 @@ bool Decomp::parse(const std::string& s, Decomp* out) {
     return false;
 }
 
-const SingleKernel* find_single(int rb, int log2n, int log2e, int wgt, bool split, bool swap, bool twreg, bool pf) {
+const SingleKernel* find_single(int rb, int log2n, int log2e, int wgt, bool split, bool swap, bool twreg, bool pf,
+                                bool stg) {
     int cnt = 0;
     const SingleKernel* t = rb == 8 ? single_kernels64(&cnt) : single_kernels(&cnt);
     const int le = log2e < log2n ? log2e : log2n;
     for (int i = 0; i < cnt; ++i)
         if (t[i].log2n == log2n && t[i].log2e == le && t[i].wgt == wgt && t[i].split == split && t[i].swap == swap &&
-            t[i].twreg == twreg && t[i].pf == pf)
+            t[i].twreg == twreg && t[i].pf == pf && t[i].stg == stg)
             return &t[i];
     return nullptr;
 }
@@ -122,7 +126,7 @@ const PassKernel* pass_kernel_for(int rb, int log2l, int log2c, size_t p, size_t
 }
 
 const SingleKernel* single_kernel_for(int rb, int log2n, const Decomp& d, bool split, bool inverse) {
-    return find_single(rb, log2n, d.log2e, d.wgt, split, inverse && !split, d.twreg, d.pf);
+    return find_single(rb, log2n, d.log2e, d.wgt, split, inverse && !split, d.twreg, d.pf, d.stg);
 }
 
 // column tile for a sub-FFT length: the widest compiled one up to 128-byte
@@ -255,11 +259,13 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout) {
     }
     if (log2n <= 14) {
         // single-pass shapes measured fastest on MI355X (batches of 2^25
-        // elements, both layouts); the autotuner refines them per device
-        static const struct { int log2e, gmul, twreg, pf; } table[15] = {
-            {4, 1, 1, 0}, {4, 8, 1, 0}, {4, 8, 1, 0}, {4, 8, 1, 0}, {3, 8, 1, 0},  // 2^0 .. 2^4
-            {3, 8, 1, 0}, {3, 8, 1, 0}, {3, 2, 1, 0}, {3, 2, 1, 0}, {3, 2, 1, 0},  // 2^5 .. 2^9
-            {3, 2, 1, 0}, {3, 2, 1, 0}, {4, 2, 1, 0}, {4, 4, 1, 0}, {4, 4, 0, 1},  // 2^10 .. 2^14
+        // elements from inputs that are not cached, the mean over both
+        // layouts); up to 2^7 the staged kernel, whose loads and stores are
+        // contiguous runs; the autotuner refines them per device
+        static const struct { int log2e, gmul, twreg, pf, stg; } table[15] = {
+            {4, 1, 1, 0, 0}, {4, 4, 1, 0, 1}, {4, 3, 1, 0, 1}, {4, 2, 1, 0, 1}, {4, 8, 1, 0, 1},  // 2^0 .. 2^4
+            {4, 8, 1, 0, 1}, {4, 8, 1, 0, 1}, {4, 8, 1, 0, 1}, {3, 2, 1, 0, 0}, {3, 2, 1, 0, 0},  // 2^5 .. 2^9
+            {3, 2, 1, 0, 0}, {3, 2, 1, 0, 0}, {4, 2, 1, 0, 0}, {4, 4, 1, 0, 0}, {4, 4, 0, 1, 0},  // 2^10 .. 2^14
         };
         d.kind = Decomp::SINGLE;
         d.log2e = table[log2n].log2e;
@@ -267,6 +273,7 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout) {
         d.gmul = table[log2n].gmul;
         d.twreg = table[log2n].twreg == 1;
         d.pf = table[log2n].pf == 1;
+        d.stg = table[log2n].stg == 1;
         return d;
     }
     // multi-pass chains measured fastest on MI355X per layout (batches of 2^25
@@ -410,8 +417,9 @@ std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int r
     for (int e : {4, 3})
         for (int w : {256, 64})
             for (int r : {1, 0})
-                for (int pf : {0, 1}) {
-                    const SingleKernel* k = find_single(rb, log2n, e, w, false, false, r == 1, pf == 1);
+                for (int var : {0, 1, 2}) {  // plain, prefetching, staged
+                    const bool pf = var == 1, stg = var == 2;
+                    const SingleKernel* k = find_single(rb, log2n, e, w, false, false, r == 1, pf, stg);
                     if (!k) continue;
                     bool dup = false;
                     for (auto* o : shapes) dup |= (o == k);
@@ -424,7 +432,8 @@ std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int r
                         d.wgt = w;
                         d.gmul = g;
                         d.twreg = r == 1;
-                        d.pf = pf == 1;
+                        d.pf = pf;
+                        d.stg = stg;
                         if (decomposition_available(d, log2n, layout, rb)) out.push_back(d);
                     }
                 }

@@ -38,6 +38,7 @@ struct SingleKernel {
     bool swap;      // swaps re/im of interleaved data on load and store (inverse)
     bool twreg;     // stage twiddles held in registers
     bool pf;        // next transform's loads issued before the current one's stages
+    bool stg;       // small transforms: contiguous loads/stores staged through LDS
     single_fn fn;
     const void* kernel;  // the __global__ function (occupancy queries)
     EngineInfo eng;

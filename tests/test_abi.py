@@ -97,6 +97,22 @@ def test_prefetch_decomposition_strings(lib, fftlib):
     assert q64["default"] == "single:e3:w256:g1:r1:p1"
 
 
+def test_staged_decomposition_strings(lib, fftlib):
+    """":s1" selects the staged small-transform kernel (FP32, N = 2 .. 512);
+    ":s0" is not a spelling and a kernel cannot be staged and prefetching."""
+    h = ctypes.c_void_p()
+    ex = lib.fft_plan_create_ex
+    for bad in (b"single:e4:w256:g2:r1:s0", b"single:e4:w256:g2:r1:s2", b"single:e4:w256:g2:r1:p1:s1",
+                b"single:e4:w256:g2:r1:s1:p1", b"single:e4:w256:g2:r1:s1x"):
+        assert ex(ctypes.byref(h), 16, 1, 0, -1, 0, bad) == 2, bad
+    assert ex(ctypes.byref(h), 4096, 1, 0, -1, 0, b"single:e4:w256:g2:r1:s1") == 7   # not compiled there
+    assert ex(ctypes.byref(h), 16, 1, 0, -1, 1, b"single:e4:w256:g2:r1:s1") == 7     # nor in FP64
+    for n in (2, 16, 32, 64, 512):
+        c = fftlib.query_decomposition(n, "split", "fp32")["candidates"]
+        assert any(x.endswith(":s1") for x in c), n
+    assert not any(x.endswith(":s1") for x in fftlib.query_decomposition(1024, "split", "fp32")["candidates"])
+
+
 def test_create_ex_validation(lib):
     """Precision argument: unknown values are rejected; FP64 has its own kernel
     set (single-pass up to 2^13, 8-column pass tiles), checked before any HIP call."""
