@@ -182,6 +182,13 @@ static const RealKernel kReal[] = {
     FFT_RS(4, 4), FFT_RS(5, 4), FFT_RS(6, 4), FFT_RS(7, 4), FFT_RS(8, 4), FFT_RS(9, 4), FFT_RS(10, 4),
     FFT_RS(11, 4), FFT_RS(12, 4), FFT_RS(13, 4),
     FFT_RS1(14, 4, false),
+    // short rows (whole rows inside one wavefront): staged through LDS
+#define FFT_RT(h, e)                                                                                          \
+    real_entry<float, h, e, 256, false, false, true, true>(), real_entry<float, h, e, 256, false, true, true, true>(), \
+        real_entry<float, h, e, 256, true, false, true, true>(), real_entry<float, h, e, 256, true, true, true, true>()
+    FFT_RT(1, 4), FFT_RT(2, 4), FFT_RT(3, 4), FFT_RT(4, 4), FFT_RT(4, 3), FFT_RT(5, 4), FFT_RT(5, 3),
+    FFT_RT(6, 4), FFT_RT(6, 3), FFT_RT(7, 4), FFT_RT(7, 3),
+#undef FFT_RT
 };
 
 #undef FFT_RS

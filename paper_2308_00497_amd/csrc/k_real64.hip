@@ -14,6 +14,13 @@ static const RealKernel kReal64[] = {
     FFT_RD(11, 3), FFT_RD1(12, 3, false), FFT_RD1(13, 3, false),
     FFT_RD(4, 4), FFT_RD(5, 4), FFT_RD(6, 4), FFT_RD(7, 4), FFT_RD(8, 4), FFT_RD1(9, 4, false),
     FFT_RD1(10, 4, false), FFT_RD1(11, 4, false), FFT_RD1(12, 4, false), FFT_RD1(13, 4, false),
+    // short rows (whole rows inside one wavefront): staged through LDS
+#define FFT_RT(h, e)                                                                                          \
+    real_entry<double, h, e, 256, false, false, true, true>(), real_entry<double, h, e, 256, false, true, true, true>(), \
+        real_entry<double, h, e, 256, true, false, true, true>(), real_entry<double, h, e, 256, true, true, true, true>()
+    FFT_RT(1, 4), FFT_RT(2, 4), FFT_RT(3, 4), FFT_RT(4, 4), FFT_RT(4, 3), FFT_RT(5, 4), FFT_RT(5, 3),
+    FFT_RT(6, 4), FFT_RT(6, 3), FFT_RT(7, 4), FFT_RT(7, 3),
+#undef FFT_RT
 };
 
 #undef FFT_RD

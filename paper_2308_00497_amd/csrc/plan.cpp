@@ -321,13 +321,13 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout) {
     return d;
 }
 
-const RealKernel* find_real(int rb, int log2h, int log2e, int wgt, bool c2r, bool split, bool twreg) {
+const RealKernel* find_real(int rb, int log2h, int log2e, int wgt, bool c2r, bool split, bool twreg, bool stg) {
     int cnt = 0;
     const RealKernel* t = rb == 8 ? real_kernels64(&cnt) : real_kernels(&cnt);
     const int le = log2e < log2h ? log2e : log2h;
     for (int i = 0; i < cnt; ++i)
         if (t[i].log2h == log2h && t[i].log2e == le && t[i].wgt == wgt && t[i].c2r == c2r && t[i].split == split &&
-            t[i].twreg == twreg)
+            t[i].twreg == twreg && t[i].stg == stg)
             return &t[i];
     return nullptr;
 }
@@ -342,7 +342,7 @@ bool real_decomposition_available(const Decomp& d, int log2n, fft_layout layout,
         case Decomp::COPY:
             return log2h == 0;
         case Decomp::SINGLE:
-            return log2h >= 1 && find_real(rb, log2h, d.log2e, d.wgt, c2r, split, d.twreg) != nullptr;
+            return log2h >= 1 && !d.pf && find_real(rb, log2h, d.log2e, d.wgt, c2r, split, d.twreg, d.stg) != nullptr;
         case Decomp::MULTI: {
             // the half-length chain runs on interleaved data in both directions
             int sum = 0;
@@ -360,20 +360,23 @@ bool real_decomposition_available(const Decomp& d, int log2n, fft_layout layout,
 }
 
 // Real plans: single-pass shapes measured on MI355X (2^25 FP32 or 2^24 FP64
-// reals, the faster of R2C + C2R, interleaved), indexed by log2 N; above the
+// reals, the faster of R2C + C2R; up to 2^8 on inputs that are not cached,
+// both layouts, where the staged kernel wins), indexed by log2 N; above the
 // single-pass limit, the half length's complex pass chain.
 struct RealShapeChoice {
-    int log2e, gmul, twreg;
+    int log2e, gmul, twreg, stg;
 };
 
 Decomp default_real_decomposition(int log2n, int rb) {
     static const RealShapeChoice r32[16] = {
-        {4, 1, 1}, {4, 1, 1}, {3, 2, 1}, {3, 1, 0}, {4, 1, 0}, {3, 1, 1}, {3, 1, 1}, {3, 2, 1},  // 2^0 .. 2^7
-        {3, 2, 1}, {3, 2, 1}, {3, 2, 1}, {4, 2, 1}, {4, 2, 1}, {3, 2, 1}, {3, 8, 0}, {4, 1, 0},  // 2^8 .. 2^15
+        {4, 1, 1, 0}, {4, 1, 1, 0}, {3, 4, 1, 1}, {4, 4, 1, 1}, {3, 3, 1, 1}, {3, 3, 1, 1}, {3, 3, 1, 1},  // 2^0 .. 2^6
+        {3, 3, 1, 1}, {3, 3, 1, 1}, {3, 2, 1, 0}, {3, 2, 1, 0}, {4, 2, 1, 0}, {4, 2, 1, 0}, {3, 2, 1, 0},  // 2^7 .. 2^13
+        {3, 8, 0, 0}, {4, 1, 0, 0},                                                                        // 2^14 .. 2^15
     };
     static const RealShapeChoice r64[15] = {
-        {4, 1, 1}, {4, 1, 1}, {4, 1, 1}, {4, 1, 0}, {4, 1, 1}, {3, 1, 1}, {3, 1, 1}, {3, 1, 1},  // 2^0 .. 2^7
-        {3, 2, 0}, {3, 2, 1}, {3, 2, 1}, {3, 2, 1}, {3, 2, 1}, {4, 4, 0}, {4, 1, 0},             // 2^8 .. 2^14
+        {4, 1, 1, 0}, {4, 1, 1, 0}, {3, 3, 1, 1}, {3, 8, 1, 1}, {3, 8, 1, 1}, {3, 2, 1, 1}, {3, 2, 1, 1},  // 2^0 .. 2^6
+        {3, 2, 1, 1}, {3, 2, 1, 1}, {3, 2, 1, 0}, {3, 2, 1, 0}, {3, 2, 1, 0}, {3, 2, 1, 0}, {4, 4, 0, 0},  // 2^7 .. 2^13
+        {4, 1, 0, 0},                                                                                      // 2^14
     };
     const int log2h = log2n - 1;
     Decomp d;
@@ -389,6 +392,7 @@ Decomp default_real_decomposition(int log2n, int rb) {
     d.wgt = 256;
     d.gmul = t.gmul;
     d.twreg = t.twreg == 1;
+    d.stg = t.stg == 1;
     return d;
 }
 

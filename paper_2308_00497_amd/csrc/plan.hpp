@@ -65,7 +65,8 @@ bool decomposition_available(const Decomp& d, int log2n, fft_layout layout, int 
 // the half length H = N/2: "copy" stands for H = 1 (the pre/post pass alone),
 // "single:..." for the fused single-pass kernel, "multi:..." for the
 // half-length pass chain plus one pre/post pass.  N = 1 has no decomposition.
-const RealKernel* find_real(int rb, int log2h, int log2e, int wgt, bool c2r, bool split, bool twreg);
+const RealKernel* find_real(int rb, int log2h, int log2e, int wgt, bool c2r, bool split, bool twreg,
+                            bool stg = false);
 Decomp default_real_decomposition(int log2n, int rb);
 bool real_decomposition_available(const Decomp& d, int log2n, fft_layout layout, int rb, bool c2r);
 

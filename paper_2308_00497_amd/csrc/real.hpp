@@ -70,10 +70,23 @@ struct RealShape {
     static constexpr int LDS = SEP ? 2 * EX : EX;
 };
 
+// LDS elements of the real kernel: engine and pairing exchange, plus with
+// staging one row of H + 1 complex values per transform of the workgroup
+template <class R, int LOG2H, int LOG2E, int WGT, bool STG>
+constexpr int real_lds() {
+    using RS = RealShape<R, LOG2H, LOG2E, WGT>;
+    return STG ? RS::LDS + SingleShape<LOG2H, LOG2E, WGT>::G * ((1 << LOG2H) + 1) : RS::LDS;
+}
+
 // One persistent single-pass kernel per direction.  `tw` is the engine's stage
 // table, `twn` holds w_N^k for k < H.  R2C reads the real array as H complex
 // pairs per row and writes H + 1 complex values per row; C2R the reverse.
-template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG>
+// With STG (rows short enough that a wavefront holds whole rows) every
+// wavefront reads and writes its rows as one contiguous run per side (lane l
+// takes elements l, l + 64, ...), staged through LDS rows of H + 1 values, so
+// that no access is a short strided one; C2R then pairs X[k] with X[H - k]
+// straight from the staged rows.
+template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG, bool STG = false>
 __global__ void __launch_bounds__((SingleShape<LOG2H, LOG2E, WGT>::THREADS))
 k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw,
               const cplx_t<R>* __restrict__ twn, int64_t batch, R iscale) {
@@ -84,8 +97,13 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
     using ENG = Engine<SC, SH::G, SH::GS, false, false, SH::WAVE>;
     constexpr int E = SC::E, T = SC::T, H = SC::L, G = SH::G;
     static_assert(LOG2H >= 1, "H = 1 runs as a pre/post pass only");
-    __shared__ V lds[RS::LDS];
+    static_assert(!STG || (SH::WAVE && (64 % T) == 0 && SH::THREADS % 64 == 0),
+                  "staging needs whole rows inside one wavefront");
+    __shared__ V lds[real_lds<R, LOG2H, LOG2E, WGT, STG>()];
     V* const xch = RS::SEP ? lds + RS::EX : lds;  // pairing exchange region
+    V* const stg = lds + RS::LDS;                 // staged rows (STG), stride H + 1
+    constexpr int SGS = H + 1;
+    constexpr int RPW = 64 / (T < 64 ? T : 64);   // rows per wavefront (STG)
 
     const int tid = threadIdx.x;
     TwReg<SC, V> twr(tw);
@@ -105,6 +123,97 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
         const int64_t tr = grp * G + gl;
         const bool active = tr < batch;
         V v[E];
+        if constexpr (STG) {
+            const int lane = tidl & 63, r0 = (tidl >> 6) * RPW;  // this wavefront's first row in the group
+            const int64_t grow0 = grp * G + r0;                  // ... and in the batch
+            if constexpr (!C2R) {
+                // the wavefront's real rows as H complex pairs each: 64 E pairs in a row
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int i = lane + 64 * m;
+                    v[m] = grow0 + i / H < batch ? gload_nt<false>(ia, ia, grow0 * H + i) : c_zero<V>();
+                }
+                stage_sync<true>();  // this wavefront's reads of its previous rows are done
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int i = lane + 64 * m;
+                    stg[(r0 + i / H) * SGS + i % H] = v[m];
+                }
+                stage_sync<true>();
+#pragma unroll
+                for (int m = 0; m < E; ++m) v[m] = stg[gl * SGS + tl + T * m];
+                if constexpr (TWREG) ENG::run(v, lds, twr, tidl);
+                else ENG::run(v, lds, TwMem<SC, V>(twl), tidl);
+                if constexpr (!RS::SEP) stage_sync<true>();
+#pragma unroll
+                for (int m = 0; m < E; ++m) xch[lds_at<SH::GS>(gl, tl + T * m)] = v[m];
+                stage_sync<true>();
+                const V xh = cmk(v[0].x - v[0].y, R(0));  // X[H] (used by tl == 0)
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int k = tl + T * m;
+                    const V mir = xch[lds_at<SH::GS>(gl, (H - k) & (H - 1))];
+                    V ev, wo;
+                    r2c_parts(v[m], mir, wn[m], ev, wo);
+                    const V xk = c_add(ev, wo);
+                    v[m] = k == 0 ? xk : c_scale(xk, iscale);
+                }
+#pragma unroll
+                for (int m = 0; m < E; ++m) stg[gl * SGS + tl + T * m] = v[m];
+                if (tl == 0) stg[gl * SGS + H] = xh;
+                stage_sync<true>();
+                // the wavefront's output rows: RPW (H + 1) values in a row
+#pragma unroll
+                for (int m = 0; m <= E; ++m) {
+                    const int j = lane + 64 * m;
+                    if (j < RPW * SGS && grow0 + j / SGS < batch)
+                        gstore_nt<SPLIT>(oa, ob, grow0 * SGS + j, stg[r0 * SGS + j]);
+                }
+            } else {
+                // the wavefront's complex rows: RPW (H + 1) values in a row
+                V in[E + 1];
+#pragma unroll
+                for (int m = 0; m <= E; ++m) {
+                    const int j = lane + 64 * m;
+                    in[m] = j < RPW * SGS && grow0 + j / SGS < batch ? gload_nt<SPLIT>(ia, ib, grow0 * SGS + j)
+                                                                      : c_zero<V>();
+                }
+                stage_sync<true>();
+#pragma unroll
+                for (int m = 0; m <= E; ++m) {
+                    const int j = lane + 64 * m;
+                    if (j < RPW * SGS) stg[r0 * SGS + j] = in[m];
+                }
+                stage_sync<true>();
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int k = tl + T * m;
+                    V a = stg[gl * SGS + k], mir;
+                    if (k == 0) {
+                        a = cmk(a.x, R(0));
+                        mir = cmk(stg[gl * SGS + H].x, R(0));
+                    } else {
+                        mir = stg[gl * SGS + H - k];
+                    }
+                    const V zk = c2r_point(a, mir, wn[m]);
+                    v[m] = swap_if<true>(k == 0 ? zk : c_scale(zk, iscale));
+                }
+                if constexpr (TWREG) ENG::run(v, lds, twr, tidl);
+                else ENG::run(v, lds, TwMem<SC, V>(twl), tidl);
+                stage_sync<true>();  // every lane's reads of the staged input rows are done
+#pragma unroll
+                for (int m = 0; m < E; ++m) stg[gl * SGS + tl + T * m] = swap_if<true>(v[m]);
+                stage_sync<true>();
+                // the wavefront's real rows as pairs: 64 E in a row
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int i = lane + 64 * m;
+                    if (grow0 + i / H < batch)
+                        gstore_nt<false>(oa, oa, grow0 * H + i, stg[(r0 + i / H) * SGS + i % H]);
+                }
+            }
+            continue;
+        }
         if constexpr (!C2R) {
             const int64_t base = tr * H + tl;  // complex pair index in the real row
 #pragma unroll
@@ -164,21 +273,21 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
     }
 }
 
-template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG>
+template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG, bool STG = false>
 hipError_t launch_real_single(const void* ia, const void* ib, void* oa, void* ob, const void* tw, const void* twn,
                               int64_t batch, int grid, double iscale, hipStream_t s) {
     using SH = SingleShape<LOG2H, LOG2E, WGT>;
     const int64_t groups = (batch + SH::G - 1) / SH::G;
     const int64_t blocks = groups < grid ? groups : grid;
     if (blocks < 1) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG>), dim3(static_cast<unsigned>(blocks)),
+    hipLaunchKernelGGL((k_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG, STG>), dim3(static_cast<unsigned>(blocks)),
                        dim3(SH::THREADS), 0, s, static_cast<const R*>(ia), static_cast<const R*>(ib),
                        static_cast<R*>(oa), static_cast<R*>(ob), static_cast<const cplx_t<R>*>(tw),
                        static_cast<const cplx_t<R>*>(twn), batch, static_cast<R>(iscale));
     return hipGetLastError();
 }
 
-template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG>
+template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG, bool STG = false>
 RealKernel real_entry() {
     using SH = SingleShape<LOG2H, LOG2E, WGT>;
     RealKernel k{};
@@ -189,12 +298,13 @@ RealKernel real_entry() {
     k.c2r = C2R;
     k.split = SPLIT;
     k.twreg = TWREG;
-    k.fn = &launch_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG>;
-    k.kernel = reinterpret_cast<const void*>(&k_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG>);
+    k.stg = STG;
+    k.fn = &launch_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG, STG>;
+    k.kernel = reinterpret_cast<const void*>(&k_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG, STG>);
     k.eng = engine_info<typename SH::SC>();
     k.threads = SH::THREADS;
     k.per_wg = SH::G;
-    k.lds_bytes = RealShape<R, LOG2H, LOG2E, WGT>::LDS * sizeof(cplx_t<R>);
+    k.lds_bytes = real_lds<R, LOG2H, LOG2E, WGT, STG>() * sizeof(cplx_t<R>);
     return k;
 }
 

@@ -91,6 +91,7 @@ struct RealKernel {
     bool c2r;
     bool split;     // complex side split into re/im arrays
     bool twreg;
+    bool stg;       // short rows: contiguous loads/stores staged through LDS
     real_fn fn;
     const void* kernel;
     EngineInfo eng;

@@ -91,32 +91,47 @@ def test_c2r_sweep(fftlib, log2n, layout, precision):
     assert_parity(y, ref, f"C2R {precision} n=2^{log2n} {layout} {d['decomposition']}", tol)
 
 
-@pytest.mark.parametrize("precision,log2n", [(p, k) for p in ("fp32", "fp64") for k in (2, 6, 10, 13, 14, 15)
+@pytest.mark.parametrize("precision,log2n", [(p, k) for p in ("fp32", "fp64") for k in (2, 3, 4, 5, 6, 8, 10, 13, 14, 15)
                                              if not (p == "fp64" and k == 15)])
 def test_every_real_single_variant(fftlib, log2n, precision):
-    """Both twiddle sources and every compiled shape of the fused kernel (half
-    lengths up to the single-pass limit: 2^14 FP32, 2^13 FP64)."""
+    """Both twiddle sources, plain and staged (short rows), and every compiled
+    shape of the fused kernel (half lengths up to the single-pass limit: 2^14
+    FP32, 2^13 FP64), forward and backward."""
     n = 1 << log2n
     dt, tol = PREC[precision]
     x = real_rows(batch_for(n), n, 8200 + log2n, dt)
     re, im = half_spectra(batch_for(n), n, 8300 + log2n, dt)
     ref_f = oracle.rfft(x, threads=8)
     ref_i = oracle.irfft(re.astype(np.float64) + 1j * im.astype(np.float64), n, threads=8)
-    seen = 0
+    g_c = re.astype(np.float64) + 1j * im.astype(np.float64)
+    ref_bf = r2c_vjp_definition(g_c, n)           # backward of R2C
+    ref_bi = oracle.rfft(x.astype(np.float64), threads=8)
+    ref_bi[:, 1:n // 2] *= 2.0                     # backward of C2R (pinned on the CPU)
+    seen = staged = 0
     for e in (3, 4):
         for r in (0, 1):
-            dec = f"single:e{e}:w256:g2:r{r}"
-            for layout in ("interleaved", "split"):
-                try:
-                    y, _ = run_r2c(fftlib, x, layout, precision, dec)
-                except fftlib.FFTError as err:
-                    assert err.status == "FFT_ERR_NOT_SUPPORTED"
-                    continue
-                assert_parity(y, ref_f, f"R2C {precision} n=2^{log2n} {layout} {dec}", tol)
-                yi, _ = run_c2r(fftlib, re, im, n, layout, precision, dec)
-                assert_parity(yi, ref_i, f"C2R {precision} n=2^{log2n} {layout} {dec}", tol)
-                seen += 1
+            for var in ("", ":s1"):
+                dec = f"single:e{e}:w256:g2:r{r}{var}"
+                for layout in ("interleaved", "split"):
+                    try:
+                        y, _ = run_r2c(fftlib, x, layout, precision, dec)
+                    except fftlib.FFTError as err:
+                        assert err.status == "FFT_ERR_NOT_SUPPORTED"
+                        continue
+                    assert_parity(y, ref_f, f"R2C {precision} n=2^{log2n} {layout} {dec}", tol)
+                    yi, _ = run_c2r(fftlib, re, im, n, layout, precision, dec)
+                    assert_parity(yi, ref_i, f"C2R {precision} n=2^{log2n} {layout} {dec}", tol)
+                    b = x.shape[0]
+                    with fftlib.RealPlan(n, b, layout, "forward", precision, dec) as p:
+                        xb = p.backward(complex_to_device(re, im, layout)).cpu().numpy().astype(np.float64)
+                    assert_parity(xb, ref_bf, f"R2C backward {precision} n=2^{log2n} {layout} {dec}", tol)
+                    with fftlib.RealPlan(n, b, layout, "inverse", precision, dec) as p:
+                        gb = complex_from_device(p.backward(torch.from_numpy(x).cuda()), layout)
+                    assert_parity(gb, ref_bi, f"C2R backward {precision} n=2^{log2n} {layout} {dec}", tol)
+                    seen += 1
+                    staged += var == ":s1"
     assert seen > 0
+    assert staged > 0 or log2n > 8
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
