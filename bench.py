@@ -373,6 +373,26 @@ def extras(fftlib, torch, workloads, dev):
         "ms": base, "kernels": {f"ops:r{r}": 3 * ((12 + r - 1) // r) - 2 for r in (1, 2, 3, 4)},
         "fusion_speedup_vs_best_ops": round(min(v for k, v in base.items() if k.startswith("ops")) / fused, 2)}
     del z, zo
+    # --- batched 2D / 3D: the last axis by the 1D plan, the others by column passes
+    for dims, batch in (((4096, 4096), 2), ((256, 256, 256), 2)):
+        numel = batch * int(np.prod(dims))
+        for layout in ("interleaved", "split"):
+            if layout == "split":
+                x = (torch.randn(numel, device=dev), torch.randn(numel, device=dev))
+                y = (torch.empty_like(x[0]), torch.empty_like(x[1]))
+            else:
+                x = torch.randn(numel, dtype=torch.complex64, device=dev)
+                y = torch.empty_like(x)
+            with fftlib.PlanND(dims, batch, layout, "forward") as p:
+                d = p.describe()
+                ms = _time(torch, lambda: p.execute(x, out=y), 20)
+                lp = d["last_axis"]
+                passes = (len(lp.get("passes", [])) or 1) + sum(len(c.get("passes", [])) or 1 for c in d["column_passes"])
+                gbs = numel * 16 * passes / (ms * 1e-3) / 1e9
+                out[f"nd_{'x'.join(map(str, dims))}_b{batch}_{layout}"] = {
+                    "ms": round(ms, 4), "gflops": round(p.nominal_flops / (ms * 1e-3) / 1e9, 1), "hbm_passes": passes,
+                    "hbm_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 3)}
+            del x, y
     return out
 
 

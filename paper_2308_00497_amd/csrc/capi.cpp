@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <utility>
 #include <string>
@@ -63,13 +64,34 @@ struct PassStep {
 // One strided axis of a multi-dimensional plan: DFT down the columns of
 // stride 2^log2s, in place on the output.
 struct NdStep {
-    const fftk::StridedKernel* k;      // forward
-    const fftk::StridedKernel* k_inv;  // inverse (interleaved re/im swap)
-    int log2s;
-    int64_t blocks;  // column blocks: batch x the axes before this one
-    size_t twe_off;  // engine stage table (complex entries)
-    int grid;
+    const fftk::StridedKernel* k = nullptr;      // forward (one column pass)
+    const fftk::StridedKernel* k_inv = nullptr;  // inverse (interleaved re/im swap)
+    int log2s = 0;
+    int64_t blocks = 0;  // column blocks: batch x the axes before this one
+    size_t twe_off = 0;  // engine stage table (complex entries)
+    int grid = 0;
+    // long columns (l = log2 length > 0): two passes of the pass kernel along
+    // the column, DFT_L with L = 2^l1 2^l2 as a Stockham chain whose Ns starts
+    // at the column stride 2^log2s (the column index hidden from the pass
+    // twiddles), through the plan's workspace and back
+    int l = 0, l1 = 0, l2 = 0;
+    const fftk::PassKernel *pa = nullptr, *pa_inv = nullptr, *pb = nullptr, *pb_inv = nullptr;
+    size_t twe_a = 0, twe_b = 0, ta_off = 0, tb_off = 0;
+    int hbits = 0, grid_a = 0, grid_b = 0;
 };
+
+// Column lengths that run as two passes of the pass kernel (their one-pass
+// tiles would hold 8 columns or fewer): {l1, c1, l2, c2} for l = 10, 11, 12.
+// Measured on MI355X: two passes win from 2^11 on, and at 2^10 for split
+// arrays and FP64; interleaved FP32 columns of 2^10 are faster in one pass
+// of 8-column tiles.
+bool nd_two_pass_shape(int rb, int l, bool split, int* t) {
+    static const int f32[3][4] = {{5, 8, 5, 8}, {6, 7, 5, 8}, {6, 7, 6, 7}};
+    static const int f64[3][4] = {{5, 7, 5, 7}, {6, 6, 5, 7}, {6, 6, 6, 6}};
+    if (l < 10 || l > 12 || (l == 10 && rb == 4 && !split)) return false;
+    for (int i = 0; i < 4; ++i) t[i] = (rb == 8 ? f64 : f32)[l - 10][i];
+    return true;
+}
 
 bool valid_layout(int l) { return l == FFT_LAYOUT_INTERLEAVED || l == FFT_LAYOUT_SPLIT; }
 bool valid_dir(int d) { return d == FFT_FORWARD || d == FFT_INVERSE; }
@@ -122,6 +144,11 @@ struct fft_plan_s {
 
     void* ws() const { return ws_user ? ws_user : ws_own; }
     size_t cbytes() const { return 2 * size_t(rb); }  // bytes per complex element
+    bool nd_own_ws() const {  // a multi-dimensional plan whose column passes need a workspace
+        for (const NdStep& q : nd)
+            if (q.l) return true;
+        return false;
+    }
 };
 
 namespace {
@@ -449,7 +476,7 @@ fft_status run_real(fft_plan p, const void* ia, const void* ib, void* oa, void* 
                 const fftk::PassKernel* k = c2r ? st.k_inv : st.k;
                 e = k->fn(src, nullptr, out, nullptr, static_cast<const char*>(p->twe) + st.twe_off * p->cbytes(),
                           p->tw64 + st.ta_off, p->tw64 + st.tb_off, p->log2h, st.log2ns, st.hbits, p->batch,
-                          st.grid, stream, s);
+                          st.grid, stream, 0, s);
                 if (e != hipSuccess) return fail_hip(e, "pass launch");
                 prev = dst;
             }
@@ -501,6 +528,26 @@ fft_status run_nd(fft_plan p, const void* ia, const void* ib, void* oa, void* ob
     if (inverse && split) std::swap(a, b);
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (const NdStep& stp : p->nd) {
+        if (stp.l) {
+            // out -> workspace -> out; the pass twiddles see the column's own index only
+            if (!p->ws()) {
+                g_detail = "no workspace";
+                return FFT_ERR_INVALID_ARG;
+            }
+            const fftk::PassKernel* ka = inverse && !split ? stp.pa_inv : stp.pa;
+            const fftk::PassKernel* kb = inverse && !split ? stp.pb_inv : stp.pb;
+            const char* twe = static_cast<const char*>(p->twe);
+            const double2* ta = p->tw64 + stp.ta_off;
+            const double2* tb = p->tw64 + stp.tb_off;
+            const int log2n = stp.l + stp.log2s;
+            hipError_t e = ka->fn(a, b, p->ws(), nullptr, twe + stp.twe_a * p->cbytes(), ta, tb, log2n, stp.log2s,
+                                  stp.hbits, stp.blocks, stp.grid_a, 0, stp.log2s, s);
+            if (e == hipSuccess)
+                e = kb->fn(p->ws(), nullptr, a, b, twe + stp.twe_b * p->cbytes(), ta, tb, log2n, stp.log2s + stp.l1,
+                           stp.hbits, stp.blocks, stp.grid_b, fftk::kStreamOut, stp.log2s, s);
+            if (e != hipSuccess) return fail_hip(e, "column pass launch");
+            continue;
+        }
         const fftk::StridedKernel* k = inverse && !split ? stp.k_inv : stp.k;
         const hipError_t e = k->fn(a, b, a, b, static_cast<const char*>(p->twe) + stp.twe_off * p->cbytes(), stp.log2s,
                                    stp.blocks, stp.grid, s);
@@ -630,7 +677,7 @@ fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, v
                 e = k->fn(sa, sb, da, db, static_cast<const char*>(p->twe) + stp.twe_off * p->cbytes(),
                           p->tw64 ? p->tw64 + stp.ta_off : nullptr,
                           p->tw64 ? p->tw64 + stp.tb_off : nullptr, p->log2n, stp.log2ns, stp.hbits, p->batch,
-                          stp.grid, stream, s);
+                          stp.grid, stream, 0, s);
                 if (e != hipSuccess) return fail_hip(e, "pass launch");
             }
             (void)split;
@@ -658,8 +705,13 @@ std::string describe(fft_plan p) {
         for (int i = 0; i < p->rank; ++i) d += (i ? ", " : "") + std::to_string(p->dims[i]);
         for (size_t i = 0; i < p->nd.size(); ++i) {
             const NdStep& st = p->nd[i];
-            snprintf(buf, sizeof buf, "%s{\"length\": %d, \"stride\": %lld, \"columns_per_wg\": %d}", i ? ", " : "",
-                     1 << st.k->log2l, (long long)(int64_t(1) << st.log2s), 1 << st.k->log2c);
+            if (st.l)
+                snprintf(buf, sizeof buf,
+                         "%s{\"length\": %d, \"stride\": %lld, \"passes\": [\"%dc%d\", \"%dc%d\"]}", i ? ", " : "",
+                         1 << st.l, (long long)(int64_t(1) << st.log2s), st.l1, st.pa->log2c, st.l2, st.pb->log2c);
+            else
+                snprintf(buf, sizeof buf, "%s{\"length\": %d, \"stride\": %lld, \"columns_per_wg\": %d}",
+                         i ? ", " : "", 1 << st.k->log2l, (long long)(int64_t(1) << st.log2s), 1 << st.k->log2c);
             cols += buf;
         }
         s += "\"rank\": " + std::to_string(p->rank) + ", \"dims\": [" + d + "], \"last_axis\": " + describe(p->inner) +
@@ -839,9 +891,24 @@ fft_status fft_plan_create_nd(fft_plan* out, int rank, const int64_t* dims, int6
         int log2s = 0;
         for (int j = k + 1; j < rank; ++j) log2s += log2d[j];
         NdStep st{};
-        st.k = fftk::strided_kernel_for(rb, log2d[k], log2s, split, false);
-        st.k_inv = split ? st.k : fftk::strided_kernel_for(rb, log2d[k], log2s, split, true);
-        if (!st.k || !st.k_inv) return FFT_ERR_NOT_SUPPORTED;
+        int sh[4];
+        const int l = log2d[k];
+        if (nd_two_pass_shape(rb, l, split, sh) && l + log2s >= sh[0] + sh[1] && l + log2s >= sh[2] + sh[3]) {
+            st.pa = fftk::find_pass(rb, sh[0], sh[1], false, split, false, false, false);
+            st.pa_inv = split ? st.pa : fftk::find_pass(rb, sh[0], sh[1], false, false, false, true, false);
+            st.pb = fftk::find_pass(rb, sh[2], sh[3], false, false, split, false, false);
+            st.pb_inv = split ? st.pb : fftk::find_pass(rb, sh[2], sh[3], false, false, false, false, true);
+            if (st.pa && st.pa_inv && st.pb && st.pb_inv) {
+                st.l = l;
+                st.l1 = sh[0];
+                st.l2 = sh[2];
+            }
+        }
+        if (!st.l) {
+            st.k = fftk::strided_kernel_for(rb, log2d[k], log2s, split, false);
+            st.k_inv = split ? st.k : fftk::strided_kernel_for(rb, log2d[k], log2s, split, true);
+            if (!st.k || !st.k_inv) return FFT_ERR_NOT_SUPPORTED;
+        }
         st.log2s = log2s;
         st.blocks = batch;
         for (int j = 0; j < k; ++j) st.blocks *= dims[j];
@@ -869,15 +936,33 @@ fft_status fft_plan_create_nd(fft_plan* out, int rank, const int64_t* dims, int6
     fft_status st = create_impl(&p->inner, dims[rank - 1], p->elements / dims[rank - 1], layout, dir, precision,
                                 nullptr);
     if (st == FFT_OK) {
+        auto occupancy_grid = [&](const void* kernel, int threads) {
+            int per_cu = 1;
+            if (kernel && (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+                           per_cu < 1))
+                per_cu = 1;
+            return per_cu * p->cus;
+        };
+        bool two_pass = false;
         for (NdStep& stp : steps) {
+            if (stp.l) {
+                two_pass = true;
+                stp.twe_a = p->twe_n;
+                p->twe_n += (stp.pa->eng.tw_size + 1) & ~size_t(1);
+                stp.twe_b = p->twe_n;
+                p->twe_n += (stp.pb->eng.tw_size + 1) & ~size_t(1);
+                stp.hbits = (stp.l + 1) / 2;  // pass twiddles w_L^e = A[e >> hbits] B[e & mask]
+                stp.ta_off = p->tw64_n;
+                p->tw64_n += size_t(1) << (stp.l - stp.hbits);
+                stp.tb_off = p->tw64_n;
+                p->tw64_n += size_t(1) << stp.hbits;
+                stp.grid_a = occupancy_grid(stp.pa->kernel, stp.pa->threads);
+                stp.grid_b = occupancy_grid(stp.pb->kernel, stp.pb->threads);
+                continue;
+            }
             stp.twe_off = p->twe_n;
             p->twe_n += (stp.k->eng.tw_size + 1) & ~size_t(1);
-            int per_cu = 1;
-            if (stp.k->kernel &&
-                (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stp.k->kernel, stp.k->threads, 0) != hipSuccess ||
-                 per_cu < 1))
-                per_cu = 1;
-            stp.grid = per_cu * p->cus;
+            stp.grid = occupancy_grid(stp.k->kernel, stp.k->threads);
         }
         p->nd = steps;
         if (p->twe_n) {
@@ -888,17 +973,42 @@ fft_status fft_plan_create_nd(fft_plan* out, int rank, const int64_t* dims, int6
                 st = FFT_ERR_ALLOC;
             }
         }
+        if (st == FFT_OK && p->tw64_n) {
+            e = dev_malloc(reinterpret_cast<void**>(&p->tw64), p->tw64_n * sizeof(double2));
+            if (e != hipSuccess) {
+                p->tw64 = nullptr;
+                g_detail = "twiddle table allocation failed";
+                st = FFT_ERR_ALLOC;
+            }
+        }
+        char* twe = static_cast<char*>(p->twe);
         for (size_t i = 0; st == FFT_OK && i < p->nd.size(); ++i) {
-            if (!p->nd[i].k->eng.tw_size) continue;
-            e = fftk::launch_gen_engine_tw(p->nd[i].k->eng, static_cast<char*>(p->twe) + p->nd[i].twe_off * p->cbytes(),
-                                           rb, nullptr);
+            const NdStep& q = p->nd[i];
+            if (q.l) {
+                if (q.pa->eng.tw_size) e = fftk::launch_gen_engine_tw(q.pa->eng, twe + q.twe_a * p->cbytes(), rb, nullptr);
+                if (e == hipSuccess && q.pb->eng.tw_size)
+                    e = fftk::launch_gen_engine_tw(q.pb->eng, twe + q.twe_b * p->cbytes(), rb, nullptr);
+                if (e == hipSuccess)
+                    e = fftk::launch_gen_pow64(p->tw64 + q.ta_off, q.l, int64_t(1) << q.hbits,
+                                               int64_t(1) << (q.l - q.hbits), nullptr);
+                if (e == hipSuccess) e = fftk::launch_gen_pow64(p->tw64 + q.tb_off, q.l, 1, int64_t(1) << q.hbits, nullptr);
+            } else if (q.k->eng.tw_size) {
+                e = fftk::launch_gen_engine_tw(q.k->eng, twe + q.twe_off * p->cbytes(), rb, nullptr);
+            }
             if (e != hipSuccess) st = fail_hip(e, "twiddle generation");
         }
         if (st == FFT_OK) {
             e = hipStreamSynchronize(nullptr);
             if (e != hipSuccess) st = fail_hip(e, "twiddle generation sync");
         }
+        // the workspace: the last-axis plan's, or with two-pass columns one of
+        // the whole array that the last-axis plan shares (it runs first)
         p->ws_bytes = p->inner ? p->inner->ws_bytes : 0;
+        if (st == FFT_OK && two_pass) {
+            p->ws_bytes = std::max(p->ws_bytes, size_t(p->elements) * p->cbytes());
+            st = alloc_workspace(p);
+            if (st == FFT_OK && p->inner->ws_bytes) st = fft_plan_set_workspace(p->inner, p->ws());
+        }
     }
     if (st != FFT_OK) {
         free_plan_memory(p);
@@ -1083,7 +1193,24 @@ fft_status fft_plan_set_workspace(fft_plan p, void* dev_ptr) {
     if (dev_ptr && (reinterpret_cast<uintptr_t>(dev_ptr) & 15u)) return FFT_ERR_MISALIGNED;
     DeviceGuard guard(p->device);
     if (p->ragged) return fftk::ragged_set_workspace(p->ragged, dev_ptr, &g_detail);
-    if (p->inner) return fft_plan_set_workspace(p->inner, dev_ptr);
+    if (p->inner && !p->nd_own_ws()) return fft_plan_set_workspace(p->inner, dev_ptr);
+    if (p->inner) {
+        // a multi-dimensional plan with two-pass columns: one workspace for
+        // both stages (they run one after the other)
+        if (dev_ptr) {
+            if (p->ws_own) {
+                (void)hipDeviceSynchronize();
+                (void)hipFree(p->ws_own);
+                p->ws_own = nullptr;
+            }
+            p->ws_user = dev_ptr;
+        } else {
+            p->ws_user = nullptr;
+            const fft_status st = alloc_workspace(p);
+            if (st != FFT_OK) return st;
+        }
+        return p->inner->ws_bytes ? fft_plan_set_workspace(p->inner, p->ws()) : FFT_OK;
+    }
     if (dev_ptr) {
         if (p->ws_own) {
             (void)hipDeviceSynchronize();

@@ -25,6 +25,19 @@ static const PassKernel kPass[] = {
     FFT_P(10, 2), FFT_P(10, 3),
     FFT_P(11, 2),
     FFT_P(12, 1), FFT_P(12, 2),
+    // the column passes of multi-dimensional plans: later-pass variants whose
+    // input is the caller's layout (split arrays, or re/im swapped), and a
+    // 32-point pass with 256-column tiles
+#define FFT_PC(l, c)                                                                                       \
+    pass_entry<float, l, 4, c, false, true, false, false, false>(),                                        \
+        pass_entry<float, l, 4, c, false, false, false, true, false>()
+#define FFT_PN(l, c)                                                                                       \
+    pass_entry<float, l, 4, c, false, false, false, false, false>(),                                       \
+        pass_entry<float, l, 4, c, false, false, false, false, true>(),                                    \
+        pass_entry<float, l, 4, c, false, false, true, false, false>()
+    FFT_PC(6, 7), FFT_PN(5, 8), FFT_PC(5, 8),
+#undef FFT_PC
+#undef FFT_PN
 };
 
 #undef FFT_P

@@ -22,6 +22,17 @@ static const PassKernel kPass64[] = {
     FFT_PD(10, 2), FFT_PD(10, 3),
     FFT_PD(11, 1), FFT_PD(11, 2),
     FFT_PD(12, 1),
+    // the column passes of multi-dimensional plans (see the FP32 list)
+#define FFT_PC(l, c)                                                                                       \
+    pass_entry<double, l, 4, c, false, true, false, false, false>(),                                       \
+        pass_entry<double, l, 4, c, false, false, false, true, false>()
+#define FFT_PN(l, c)                                                                                       \
+    pass_entry<double, l, 4, c, false, false, false, false, false>(),                                      \
+        pass_entry<double, l, 4, c, false, false, false, false, true>(),                                   \
+        pass_entry<double, l, 4, c, false, false, true, false, false>()
+    FFT_PC(6, 6), FFT_PN(5, 7), FFT_PC(5, 7),
+#undef FFT_PC
+#undef FFT_PN
 };
 
 #undef FFT_PD

@@ -263,6 +263,10 @@ struct PassShape {
 // from `ia`.
 //
 // The pass twiddle of input r of column j (k = j mod Ns) is w_M^(r k), M = Ns L.
+// With twshift = s > 0 the low s bits of k are a column index that the
+// twiddles must not see: w_M'^(r (k >> s)), M' = (Ns >> s) L (the column
+// passes of a multi-dimensional plan, columns at stride 2^s, run as passes of
+// a chain whose Ns starts at 2^s; the tables are then those of M').
 // A thread holds r = tp + T m (m < E), so w_M^(r k) = w_M^(tp k) (w_M^(T k))^m:
 // two table lookups per thread and an FP64 running product, rounded once per
 // element to the working precision (PASSTW = false leaves the factors out: a
@@ -278,7 +282,8 @@ __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R
                                           typename nodeduce<R>::type* oa, typename nodeduce<R>::type* ob,
                                           const TW& tw, const double2* __restrict__ ta,
                                           const double2* __restrict__ tb, int log2N, int log2Ns, int hbits,
-                                          int64_t tbase, int64_t j0, cplx_t<R>* lds, int tid, int stream) {
+                                          int64_t tbase, int64_t j0, cplx_t<R>* lds, int tid, int stream,
+                                          int twshift = 0) {
     using V = cplx_t<R>;
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     using SC = typename SH::SC;
@@ -302,8 +307,9 @@ __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R
             for (int m = 0; m < E; ++m) v[m] = swap_if<SWAP_IN>(gload<SPLIT_IN>(ia, ib, i0 + T * m * stride));
         }
         if constexpr (!FIRST && PASSTW) {
-            double2 w = twiddle_2level64(ta, tb, k * tp, hbits);
-            const double2 step = twiddle_2level64(ta, tb, k * T, hbits);
+            const int64_t kt = k >> twshift;
+            double2 w = twiddle_2level64(ta, tb, kt * tp, hbits);
+            const double2 step = twiddle_2level64(ta, tb, kt * T, hbits);
 #pragma unroll
             for (int m = 0; m < E; ++m) {
                 if (m > 0) w = z_mul(w, step);
@@ -352,7 +358,7 @@ template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, b
           bool SWAP_OUT>
 __global__ void __launch_bounds__((PassShape<LOG2L, LOG2E, LOG2C>::THREADS))
 k_pass(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw, const double2* __restrict__ ta,
-       const double2* __restrict__ tb, int log2N, int log2Ns, int hbits, int64_t tiles, int stream) {
+       const double2* __restrict__ tb, int log2N, int log2Ns, int hbits, int64_t tiles, int stream, int twshift) {
     using V = cplx_t<R>;
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     using SC = typename SH::SC;
@@ -376,10 +382,11 @@ k_pass(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw,
         const int64_t j0 = (tile & ((int64_t(1) << log2TilesPerT) - 1)) << LOG2C;
         if constexpr (REGTW)
             pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>(
-                ia, ib, oa, ob, twr, ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl, stream);
+                ia, ib, oa, ob, twr, ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl, stream, twshift);
         else
             pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>(
-                ia, ib, oa, ob, TwMem<SC, V>(tw), ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl, stream);
+                ia, ib, oa, ob, TwMem<SC, V>(tw), ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl, stream,
+                twshift);
     }
 }
 
@@ -387,7 +394,7 @@ template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, b
           bool SWAP_OUT>
 hipError_t launch_pass(const void* ia, const void* ib, void* oa, void* ob, const void* tw, const double2* ta,
                        const double2* tb, int log2N, int log2Ns, int hbits, int64_t batch, int grid, int stream,
-                       hipStream_t s) {
+                       int twshift, hipStream_t s) {
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     if (log2N < LOG2L + LOG2C) return hipErrorInvalidConfiguration;
     const int64_t tiles = (int64_t(1) << (log2N - LOG2L - LOG2C)) * batch;
@@ -396,7 +403,7 @@ hipError_t launch_pass(const void* ia, const void* ib, void* oa, void* ob, const
     hipLaunchKernelGGL((k_pass<R, LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>),
                        dim3(static_cast<unsigned>(blocks)), dim3(SH::THREADS), 0, s, static_cast<const R*>(ia),
                        static_cast<const R*>(ib), static_cast<R*>(oa), static_cast<R*>(ob),
-                       static_cast<const cplx_t<R>*>(tw), ta, tb, log2N, log2Ns, hbits, tiles, stream);
+                       static_cast<const cplx_t<R>*>(tw), ta, tb, log2N, log2Ns, hbits, tiles, stream, twshift);
     return hipGetLastError();
 }
 

@@ -33,7 +33,10 @@ def from_dev(y, layout):
 
 
 SHAPES = [(2, 2), (4, 64), (16, 1024), (64, 64), (256, 128), (4096, 4), (32, 1 << 14), (1024, 1024),
-          (2, 4, 8), (8, 8, 8), (16, 32, 64), (64, 64, 64), (128, 16, 2), (4, 4096, 2)]
+          (2, 4, 8), (8, 8, 8), (16, 32, 64), (64, 64, 64), (128, 16, 2), (4, 4096, 2),
+          # long columns (2^10 .. 2^12) as two passes of the pass kernel, and
+          # the ones too narrow for it (one column pass)
+          (2048, 64), (4096, 512), (1024, 256), (1024, 2), (2048, 4, 32), (4096, 2, 2)]
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -57,6 +60,11 @@ def test_nd_against_oracle(fftlib, shape, layout, precision):
         assert_parity(y.reshape(batch, -1), ref.reshape(batch, -1), what, tol)
         assert_parity(g.reshape(batch, -1), adj.reshape(batch, -1), what + " adjoint", tol)
         assert desc["rank"] == len(shape)
+        two_pass = [c for c in desc["column_passes"] if "passes" in c]
+        print(f"[case] {shape}: column passes {desc['column_passes']}", flush=True)
+        if shape in ((2048, 64), (4096, 512), (2048, 4, 32)) or (shape == (1024, 256) and
+                                                                  (layout == "split" or precision == "fp64")):
+            assert two_pass, desc
 
 
 def test_nd_in_place_and_tensor_functions(fftlib):
