@@ -13,10 +13,10 @@ namespace fftk {
 
 static const StridedKernel kStrided[] = {
     ND_S(float, 1), ND_S(float, 2), ND_S(float, 3), ND_S(float, 4),
-    ND_T(float, 5, 0), ND_T(float, 5, 2), ND_T(float, 5, 4),
-    ND_T(float, 6, 0), ND_T(float, 6, 2), ND_T(float, 6, 4),
-    ND_T(float, 7, 0), ND_T(float, 7, 2), ND_T(float, 7, 4),
-    ND_T(float, 8, 0), ND_T(float, 8, 2), ND_T(float, 8, 4),
+    ND_T(float, 5, 0), ND_T(float, 5, 2), ND_T(float, 5, 4), ND_T(float, 5, 5),
+    ND_T(float, 6, 0), ND_T(float, 6, 2), ND_T(float, 6, 4), ND_T(float, 6, 5),
+    ND_T(float, 7, 0), ND_T(float, 7, 2), ND_T(float, 7, 4), ND_T(float, 7, 5),
+    ND_T(float, 8, 0), ND_T(float, 8, 2), ND_T(float, 8, 4), ND_T(float, 8, 5),
     ND_T(float, 9, 0), ND_T(float, 9, 2), ND_T(float, 9, 4),
     ND_T(float, 10, 0), ND_T(float, 10, 2), ND_T(float, 10, 3),
     ND_T(float, 11, 0), ND_T(float, 11, 2),
