@@ -85,3 +85,24 @@ def test_nd_in_place_and_tensor_functions(fftlib):
 def test_nd_rejects_long_strided_axis(fftlib):
     with pytest.raises(fftlib.FFTError):
         fftlib.PlanND((8192, 4), 1)
+
+
+@pytest.mark.parametrize("layout", ["interleaved", "split"])
+def test_nd_two_pass_columns_with_caller_workspace(fftlib, layout):
+    """A plan whose long columns run as two passes needs a workspace of the
+    whole array (shared with its last-axis plan); a caller-owned one works the
+    same, and None returns the plan to its own."""
+    shape, batch = (4096, 128), 2
+    re, im = workloads.normal_complex((batch,) + shape, seed=9700)
+    ref = oracle.fftn(re.astype(np.float64) + 1j * im.astype(np.float64), 2, threads=8)
+    with fftlib.PlanND(shape, batch, layout) as p:
+        assert any("passes" in c for c in p.describe()["column_passes"])
+        nb = p.workspace_bytes
+        assert nb >= batch * 4096 * 128 * 8
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        p.set_workspace(ws)
+        y1 = from_dev(p.execute(to_dev(re, im, layout)), layout)
+        p.set_workspace(None)
+        y2 = from_dev(p.execute(to_dev(re, im, layout)), layout)
+    for y, what in ((y1, "caller workspace"), (y2, "own workspace")):
+        assert_parity(y.reshape(batch, -1), ref.reshape(batch, -1), f"2D two-pass columns {layout} {what}")
