@@ -117,27 +117,55 @@ __device__ __forceinline__ uint32_t run_single(const RaggedArgs& a, uint32_t ti,
     static_assert(SH::THREADS == kThreads, "single tiles use the whole workgroup");
     constexpr int E = SC::E, T = SC::T;
     // all stage twiddles in registers when they are few, else only the last
-    // stage's (the 128-register budget of two 512-thread workgroups per CU)
+    // stage's (the 128-register budget of two 512-thread workgroups per CU);
+    // in the split-layout kernel with 16 points per thread (2^13) none: the
+    // table is L1-resident, and registers for it would make that kernel spill
     constexpr bool ALLREG = (SC::NST - 1) * E <= 16;
+    constexpr bool MEMTW = SPLIT && !ALLREG && E == 16;
     using ENG = Engine<SC, SH::G, SH::GS, false, false, SH::WAVE>;
     const uint32_t code = static_cast<uint32_t>(LOG2N);
     const float2* tw = a.tw32 + a.tiles[ti].tw_eng;
     using TWT = typename std::conditional<ALLREG, TwReg<SC>, TwLast<SC>>::type;
     TWT twr(tw);
-    twr.init(tid % T);
+    if constexpr (!MEMTW) twr.init(tid % T);
     do {
         const RaggedTile d = a.tiles[ti];
         int tidl = tid;
         asm volatile("" : "+v"(tidl));
         const int t = tidl % T, g = tidl / T;
         const bool active = static_cast<uint32_t>(g) < d.count;
-        const int64_t base = (active ? a.toffs[d.first + g] : 0) + t;
         float2 v[E];
+        if constexpr (SPLIT && SH::G == 1) {
+            // split data, one transform per tile: pointers rebased on it
+            // (workgroup-uniform) and 32-bit offsets per lane, so the loads
+            // need no 64-bit address pair each (register budget)
+            const int64_t toff = a.toffs[d.first];
+            const float* ia = a.ia + (SPLIT ? toff : 2 * toff);
+            const float* ib = SPLIT ? a.ib + toff : nullptr;
 #pragma unroll
-        for (int m = 0; m < E; ++m)
-            v[m] = active ? swap_if<SWAP>(gload_nt<SPLIT>(a.ia, a.ib, base + T * m)) : make_float2(0.f, 0.f);
-        ENG::run(v, lds, twr, tidl);
-        if (active) {
+            for (int m = 0; m < E; ++m)
+                v[m] = swap_if<SWAP>(gload_nt<SPLIT>(ia, ib, static_cast<uint32_t>(t + T * m)));
+        } else {
+            const int64_t base = (active ? a.toffs[d.first + g] : 0) + t;
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                v[m] = active ? swap_if<SWAP>(gload_nt<SPLIT>(a.ia, a.ib, base + T * m)) : make_float2(0.f, 0.f);
+        }
+        if constexpr (MEMTW) {
+            const float2* twl = tw;
+            asm volatile("" : "+v"(twl));  // keep the table reads inside the loop
+            ENG::run(v, lds, TwMem<SC>(twl), tidl);
+        } else {
+            ENG::run(v, lds, twr, tidl);
+        }
+        if constexpr (SPLIT && SH::G == 1) {
+            const int64_t toff = a.toffs[d.first];
+            float* oa = a.oa + (SPLIT ? toff : 2 * toff);
+            float* ob = SPLIT ? a.ob + toff : nullptr;
+#pragma unroll
+            for (int m = 0; m < E; ++m) gstore_nt<SPLIT>(oa, ob, static_cast<uint32_t>(t + T * m), swap_if<SWAP>(v[m]));
+        } else if (active) {
+            const int64_t base = a.toffs[d.first + g] + t;
 #pragma unroll
             for (int m = 0; m < E; ++m) gstore_nt<SPLIT>(a.oa, a.ob, base + T * m, swap_if<SWAP>(v[m]));
         }
