@@ -8,6 +8,7 @@ scratch: this is also the "does it build" check.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import json
 import os
 import shutil
 import subprocess
@@ -49,27 +50,59 @@ COMMON = [
 ]
 
 
-def _compile(src: str) -> tuple[str, str]:
+# per-kernel register and scratch use, as reported by the compiler
+RESOURCES = os.path.join(BUILD, "kernel_resources.json")
+
+
+def _resources(remarks: list[str]) -> list[dict]:
+    """Kernel entries (name, VGPRs, spills, scratch bytes per lane) from the
+    compiler's kernel-resource-usage remarks."""
+    out, cur = [], None
+    for line in remarks:
+        msg = line.split("remark:", 1)[-1].strip()
+        if msg.startswith("Function Name:"):
+            cur = {"name": msg.split(":", 1)[1].split("[")[0].strip()}
+            out.append(cur)
+        elif cur is not None and ":" in msg:
+            key, val = msg.split(":", 1)
+            val = val.split("[")[0].strip()
+            if key in ("VGPRs", "AGPRs", "VGPRs Spill", "SGPRs Spill", "ScratchSize [bytes/lane]",
+                       "Occupancy [waves/SIMD]", "LDS Size [bytes/block]"):
+                try:
+                    cur[key] = int(val)
+                except ValueError:
+                    pass
+    return out
+
+
+def _compile(src: str) -> tuple[str, str, list[dict]]:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+    if src.endswith(".hip"):
+        cmd.append("-Rpass-analysis=kernel-resource-usage")
     r = subprocess.run(cmd, capture_output=True, text=True)
+    lines = r.stderr.splitlines()
+    remarks = [l for l in lines if "kernel-resource-usage" in l]
     # the host pass does not know the packed-fp32 feature; drop that notice
-    err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
+    err = "\n".join(l for l in lines if "packed-fp32-ops" not in l and "kernel-resource-usage" not in l)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{err}")
-    return obj, err
+    return obj, err, _resources(remarks)
 
 
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 1)
-    objs = []
+    objs, kernels = [], []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        for obj, err in ex.map(_compile, SOURCES):
+        for obj, err, res in ex.map(_compile, SOURCES):
             objs.append(obj)
+            kernels += res
             if verbose and err.strip():
                 print(err, file=sys.stderr)
+    with open(RESOURCES, "w") as f:
+        json.dump({"arch": ARCH, "kernels": kernels}, f, indent=0)
     tmp = LIB + ".tmp%d" % os.getpid()
     # -z defs: an unresolved symbol fails the build instead of the first load
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Wl,-z,defs", "-o", tmp, *objs]

@@ -223,3 +223,21 @@ def test_query_truncates(lib):
     buf = ctypes.create_string_buffer(8)
     assert lib.fft_query_decomposition(1 << 24, 0, 0, buf, 8) == 0
     assert len(buf.value) == 7
+
+
+def test_no_kernel_spills_or_uses_scratch():
+    """Every kernel of the last build keeps its state in registers: no VGPR or
+    SGPR spills and no per-lane scratch (the compiler's resource report, kept
+    by the build next to the library)."""
+    path = os.path.join(ROOT, "_build", "kernel_resources.json")
+    if not os.path.exists(path):
+        pytest.skip("no resource report: the library was built without one")
+    import json
+    report = json.load(open(path))
+    assert report["arch"] == "gfx950"
+    kernels = report["kernels"]
+    assert len(kernels) > 100
+    bad = [k["name"] for k in kernels
+           if k.get("VGPRs Spill", 0) or k.get("SGPRs Spill", 0) or k.get("ScratchSize [bytes/lane]", 0)]
+    assert not bad, f"{len(bad)} kernels spill or use scratch, e.g. {bad[:3]}"
+    assert all(k.get("VGPRs", 0) <= 512 for k in kernels)
