@@ -502,6 +502,13 @@ __device__ __forceinline__ void gstore_nt(R* a, R* b, int64_t i, cplx_t<R> v) {
     }
 }
 
+// Wave priority while a batch of global loads is issued: the wavefront's
+// loads leave ahead of the other wavefronts' arithmetic on its SIMD, so more
+// reads are in flight while the rest of the workgroup computes.  Stores keep
+// the normal priority (raising it there measured slower).
+__device__ __forceinline__ void loads_begin() { __builtin_amdgcn_s_setprio(3); }
+__device__ __forceinline__ void loads_end() { __builtin_amdgcn_s_setprio(0); }
+
 // real/imaginary swap S of the inverse (free: a register renaming)
 template <bool SWAP, class V>
 __device__ __forceinline__ V swap_if(V a) {

@@ -128,11 +128,13 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
             const int64_t grow0 = grp * G + r0;                  // ... and in the batch
             if constexpr (!C2R) {
                 // the wavefront's real rows as H complex pairs each: 64 E pairs in a row
+                loads_begin();
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int i = lane + 64 * m;
                     v[m] = grow0 + i / H < batch ? gload_nt<false>(ia, ia, grow0 * H + i) : c_zero<V>();
                 }
+                loads_end();
                 stage_sync<true>();  // this wavefront's reads of its previous rows are done
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
@@ -172,12 +174,14 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
             } else {
                 // the wavefront's complex rows: RPW (H + 1) values in a row
                 V in[E + 1];
+                loads_begin();
 #pragma unroll
                 for (int m = 0; m <= E; ++m) {
                     const int j = lane + 64 * m;
                     in[m] = j < RPW * SGS && grow0 + j / SGS < batch ? gload_nt<SPLIT>(ia, ib, grow0 * SGS + j)
                                                                       : c_zero<V>();
                 }
+                loads_end();
                 stage_sync<true>();
 #pragma unroll
                 for (int m = 0; m <= E; ++m) {
@@ -216,8 +220,10 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
         }
         if constexpr (!C2R) {
             const int64_t base = tr * H + tl;  // complex pair index in the real row
+            loads_begin();
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = active ? gload_nt<false>(ia, ia, base + T * m) : c_zero<V>();
+            loads_end();
             if constexpr (TWREG) ENG::run(v, lds, twr, tidl);
             else ENG::run(v, lds, TwMem<SC, V>(twl), tidl);
             if constexpr (!RS::SEP) stage_sync<SH::WAVE>();  // the engine's last reads of LDS are done
@@ -240,9 +246,11 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
         } else {
             const int64_t ib0 = tr * (H + 1);
             V xh = c_zero<V>();
+            loads_begin();
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = active ? gload_nt<SPLIT>(ia, ib, ib0 + tl + T * m) : c_zero<V>();
             if (active && tl == 0) xh = gload<SPLIT>(ia, ib, ib0 + H);
+            loads_end();
             if constexpr (!RS::SEP) stage_sync<SH::WAVE>();  // the previous transform's reads of LDS are done
 #pragma unroll
             for (int m = 0; m < E; ++m) xch[lds_at<SH::GS>(gl, tl + T * m)] = v[m];

@@ -50,6 +50,8 @@ struct SingleKernel {
 // sides of a pass that are the caller's buffers: read or written once, with
 // streaming (nontemporal) access
 constexpr int kStreamIn = 1, kStreamOut = 2;
+// pass tiles: raise the wave priority while the tile's loads are issued
+constexpr int kLoadPrio = 4;
 
 // grid = number of persistent workgroups (clamped to the number of tiles);
 // stream = kStreamIn | kStreamOut for the sides that are the caller's buffers
