@@ -422,6 +422,28 @@ def cpu_baseline(re, im, y_gpu, n, seconds):
     out = {"value": round(flops / el / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
            "sample": f"{len(rows)} of the 8192 N=4096 transforms (every 8th), FP64 forward, "
                      f"repeated {runs}x over {el:.1f} s on {threads} threads"}
+
+    def rate(fn, budget):
+        k, t1 = 0, time.perf_counter()
+        while True:
+            fn()
+            k += 1
+            e = time.perf_counter() - t1
+            if e >= budget:
+                return 5.0 * n * np.log2(n) * len(rows) * k / e / 1e9
+
+    # context beside it: the same oracle on one thread, and numpy's pocketfft (FP64, one thread)
+    out["single_thread_value"] = round(rate(
+        lambda: oracle.fft_split_inplace_arrays(xr, xim, yr, yim, oracle.FORWARD, 1), seconds / 4), 3)
+    xc = xr + 1j * xim
+    out["numpy_fft_fp64_value"] = round(rate(lambda: np.fft.fft(xc, axis=1), seconds / 6), 3)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    out["host"] = {"cpu_count": os.cpu_count(), "model": model}
     # accuracy gate: the GPU's interleaved forward output on the same rows
     g = y_gpu.view(re.shape[0], n)[rows].cpu().numpy().astype(np.complex128)
     ref = yr + 1j * yim
