@@ -195,8 +195,11 @@ __device__ __forceinline__ uint32_t run_copy(const RaggedArgs& a, uint32_t ti, i
 
 // Pass tiles of one (pass kind, sub-length) class; the sub-FFT's stage
 // twiddles stay in registers across tiles.  Interleaved workspace between
-// passes, the caller's layout at the ends.
-template <int LOG2L, uint32_t KIND, bool SPLIT, bool SWAP>
+// passes, the caller's layout at the ends.  REGALL: the later passes of 128
+// and 256 points keep their stage twiddles in registers too (the pass-only
+// kernel, whose register budget is not shared with the single-pass classes;
+// the 32- and 64-point passes would spill there).
+template <int LOG2L, uint32_t KIND, bool SPLIT, bool SWAP, bool REGALL>
 __device__ __forceinline__ uint32_t run_pass(const RaggedArgs& a, uint32_t ti, float2* lds, int tid) {
     constexpr int LOG2C = kTileLog2 - LOG2L;
     constexpr bool FIRST = KIND == CODE_PASS_FIRST, LAST = KIND == CODE_PASS_LAST;
@@ -205,11 +208,13 @@ __device__ __forceinline__ uint32_t run_pass(const RaggedArgs& a, uint32_t ti, f
     static_assert(SH::THREADS == kThreads, "pass tiles use the whole workgroup");
     using ENG = Engine<SC, SH::C, SH::GS, true, !FIRST, false>;
     const uint32_t code = KIND + static_cast<uint32_t>(LOG2L - kMinPassLog2);
-    // later passes also form FP64 pass twiddles; their stage twiddles come
-    // from the (L1-resident) table to stay inside the register budget
-    using TWT = typename std::conditional<FIRST, TwReg<SC>, TwMem<SC>>::type;
+    // later passes also form FP64 pass twiddles; in the kernel that serves
+    // every class their stage twiddles come from the (L1-resident) table to
+    // stay inside the register budget (registers measured 8 % faster)
+    constexpr bool REG = FIRST || (REGALL && LOG2L >= 7);
+    using TWT = typename std::conditional<REG, TwReg<SC>, TwMem<SC>>::type;
     TWT twr(a.tw32 + a.tiles[ti].tw_eng);
-    if constexpr (FIRST) twr.template init_engine<ENG>(tid);
+    if constexpr (REG) twr.template init_engine<ENG>(tid);
     do {
         const RaggedTile d = a.tiles[ti];
         int tidl = tid;
@@ -246,24 +251,35 @@ __device__ __forceinline__ uint32_t run_pass(const RaggedArgs& a, uint32_t ti, f
     return ti;
 }
 
-template <bool SPLIT, bool SWAP>
+// PASSONLY: an instance for the levels that hold pass tiles only (every level
+// after the first); it leaves out the single-pass and copy classes.
+template <bool SPLIT, bool SWAP, bool PASSONLY>
 __global__ void __launch_bounds__(kThreads, 4) k_ragged(RaggedArgs a) {
     __shared__ float2 lds[kLds];
     const int tid = threadIdx.x;
     uint32_t ti = blockIdx.x;
     while (ti < a.ntiles) {
-        switch (a.tiles[ti].code) {
-            case CODE_COPY: ti = run_copy<SPLIT>(a, ti, tid); break;
+        const uint32_t code = a.tiles[ti].code;
+        if constexpr (!PASSONLY) {
+            if (code < CODE_PASS_FIRST) {
+                switch (code) {
+                    case CODE_COPY: ti = run_copy<SPLIT>(a, ti, tid); break;
 #define FFT_RS(n) \
     case n: ti = run_single<n, SPLIT, SWAP>(a, ti, lds, tid); break;
-            FFT_RS(1) FFT_RS(2) FFT_RS(3) FFT_RS(4) FFT_RS(5) FFT_RS(6) FFT_RS(7)
-            FFT_RS(8) FFT_RS(9) FFT_RS(10) FFT_RS(11) FFT_RS(12) FFT_RS(13)
+                    FFT_RS(1) FFT_RS(2) FFT_RS(3) FFT_RS(4) FFT_RS(5) FFT_RS(6) FFT_RS(7)
+                    FFT_RS(8) FFT_RS(9) FFT_RS(10) FFT_RS(11) FFT_RS(12) FFT_RS(13)
 #undef FFT_RS
-#define FFT_RP(kind)                                                          \
-    case kind + 0: ti = run_pass<5, kind, SPLIT, SWAP>(a, ti, lds, tid); break; \
-    case kind + 1: ti = run_pass<6, kind, SPLIT, SWAP>(a, ti, lds, tid); break; \
-    case kind + 2: ti = run_pass<7, kind, SPLIT, SWAP>(a, ti, lds, tid); break; \
-    case kind + 3: ti = run_pass<8, kind, SPLIT, SWAP>(a, ti, lds, tid); break;
+                    default: ti += gridDim.x; break;
+                }
+                continue;
+            }
+        }
+        switch (code) {
+#define FFT_RP(kind)                                                                    \
+    case kind + 0: ti = run_pass<5, kind, SPLIT, SWAP, PASSONLY>(a, ti, lds, tid); break; \
+    case kind + 1: ti = run_pass<6, kind, SPLIT, SWAP, PASSONLY>(a, ti, lds, tid); break; \
+    case kind + 2: ti = run_pass<7, kind, SPLIT, SWAP, PASSONLY>(a, ti, lds, tid); break; \
+    case kind + 3: ti = run_pass<8, kind, SPLIT, SWAP, PASSONLY>(a, ti, lds, tid); break;
             FFT_RP(CODE_PASS_FIRST)
             FFT_RP(CODE_PASS_MID)
             FFT_RP(CODE_PASS_LAST)
@@ -302,6 +318,7 @@ struct RaggedPlan {
     int nlevels = 0;
     uint32_t level_begin[kMaxLevels + 1] = {};     // tile index ranges of the levels
     int level_grid[kMaxLevels] = {};
+    bool level_pass_only[kMaxLevels] = {};         // launched with the pass-only kernel
     hipGraphNode_t node[2][kMaxLevels] = {};
     RaggedArgs args[2][kMaxLevels];
     int nsingle_tiles = 0, npass_tiles = 0, ncopy_tiles = 0, nmulti = 0, ngroups = 0;
@@ -344,21 +361,27 @@ std::vector<int> even_parts(int log2n, int parts) {
     return v;
 }
 
-void* kernel_for(bool split, bool swap) {
-    if (split) return reinterpret_cast<void*>(&k_ragged<true, false>);
-    return swap ? reinterpret_cast<void*>(&k_ragged<false, true>) : reinterpret_cast<void*>(&k_ragged<false, false>);
+void* kernel_for(bool split, bool swap, bool pass_only) {
+    if (pass_only) {
+        if (split) return reinterpret_cast<void*>(&k_ragged<true, false, true>);
+        return swap ? reinterpret_cast<void*>(&k_ragged<false, true, true>)
+                    : reinterpret_cast<void*>(&k_ragged<false, false, true>);
+    }
+    if (split) return reinterpret_cast<void*>(&k_ragged<true, false, false>);
+    return swap ? reinterpret_cast<void*>(&k_ragged<false, true, false>)
+                : reinterpret_cast<void*>(&k_ragged<false, false, false>);
 }
 
 // Capture one persistent launch per level into a graph.
 fft_status build_graph(RaggedPlan* r, int variant, std::string* detail) {
     const bool split = r->layout == FFT_LAYOUT_SPLIT;
     const bool swap = variant == 1;
-    void* fn = kernel_for(split, swap);
     hipError_t e = hipStreamBeginCapture(r->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_err(e, "graph capture begin", detail);
     for (int l = 0; l < r->nlevels && e == hipSuccess; ++l) {
         RaggedArgs& a = r->args[variant][l];
         void* kparams[] = {&a};
+        void* fn = kernel_for(split, swap, r->level_pass_only[l]);
         e = hipLaunchKernel(fn, dim3(r->level_grid[l]), dim3(kThreads), kparams, 0, r->cap);
     }
     hipGraph_t g = nullptr;
@@ -379,10 +402,13 @@ fft_status build_graph(RaggedPlan* r, int variant, std::string* detail) {
         hipGraphNodeType ty;
         if (hipGraphNodeGetType(nd, &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
         hipKernelNodeParams kp;
-        if (hipGraphKernelNodeGetParams(nd, &kp) != hipSuccess || kp.func != fn || !kp.kernelParams) continue;
+        if (hipGraphKernelNodeGetParams(nd, &kp) != hipSuccess || !kp.kernelParams) continue;
+        const bool ours = kp.func == kernel_for(split, swap, false) || kp.func == kernel_for(split, swap, true);
+        if (!ours) continue;
         const RaggedArgs* ka = static_cast<const RaggedArgs*>(kp.kernelParams[0]);
         for (int l = 0; l < r->nlevels; ++l)
-            if (ka->tiles == r->args[variant][l].tiles) r->node[variant][l] = nd;
+            if (ka->tiles == r->args[variant][l].tiles && kp.func == kernel_for(split, swap, r->level_pass_only[l]))
+                r->node[variant][l] = nd;
     }
     for (int l = 0; l < r->nlevels; ++l)
         if (!r->node[variant][l]) {
@@ -644,6 +670,11 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
     // (every level then has tiles, and a distinct first descriptor)
     while (r->nlevels > 1 && r->level_begin[r->nlevels - 1] == tiles.size()) --r->nlevels;
     r->level_begin[r->nlevels] = static_cast<uint32_t>(tiles.size());
+    for (int l = 0; l < r->nlevels; ++l) {
+        bool only = true;
+        for (uint32_t i = r->level_begin[l]; i < r->level_begin[l + 1]; ++i) only = only && tiles[i].code >= CODE_PASS_FIRST;
+        r->level_pass_only[l] = only;
+    }
     for (int n = kTileLog2 + 1; n <= kMaxLog2N; ++n) {
         int64_t c = 0;
         for (int64_t i : multi) c += lg[i] == n;
@@ -689,7 +720,7 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
 
     // persistent grids: as many workgroups as can be resident, at most one per tile
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel_for(layout == FFT_LAYOUT_SPLIT, false)),
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel_for(layout == FFT_LAYOUT_SPLIT, false, false)),
                                                      kThreads, 0);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     const int64_t want = std::max<int64_t>(1, int64_t(per_cu) * cus * cfg.grid_eighths / 8);
@@ -829,7 +860,10 @@ std::string ragged_describe(const RaggedPlan* r) {
              (long long)r->count, (long long)r->total, r->htiles.size(), r->nsingle_tiles, r->npass_tiles,
              r->ncopy_tiles, r->nmulti, r->nlevels, r->ngroups, r->grid, kThreads, size_t(kLds) * sizeof(float2),
              r->ws_half * r->ws_regions);
-    return std::string(buf) + r->classes + "}, \"config\": \"" + r->cfg.str() + "\"";
+    int pass_only = 0;
+    for (int l = 0; l < r->nlevels; ++l) pass_only += r->level_pass_only[l];
+    return std::string(buf) + r->classes + "}, \"pass_only_levels\": " + std::to_string(pass_only) +
+           ", \"config\": \"" + r->cfg.str() + "\"";
 }
 
 }  // namespace fftk

@@ -209,6 +209,9 @@ def test_ragged_pipelined_groups(fftlib, cfg):
                 print(f"[case] {cfg} {layout} {direction}: groups {d['groups']} levels {d['levels']}", flush=True)
                 assert d["config"] == cfg and d["source"] == "explicit", d
                 assert d["groups"] > 1 and d["levels"] >= d["groups"] + 1, d
+                # level 0 mixes single-pass tiles with first passes; every later
+                # level holds pass tiles only and runs the pass-only kernel
+                assert d["pass_only_levels"] == d["levels"] - 1, d
                 for rep in range(2):
                     y = from_device(plan.execute(to_device(re, im, layout)), layout)
                     errs = per_item_errors(y, ref, sizes, offsets)
