@@ -92,11 +92,18 @@ def main() -> int:
     xs = (torch.from_numpy(re).to(dev), torch.from_numpy(im).to(dev))
     ys = (torch.empty_like(xs[0]), torch.empty_like(xs[1]))
 
+    # every launch of a step has buffers of its own (the inverse gets copies of
+    # the same inputs), so no launch reads or overwrites what the launch
+    # before it just touched
     variants = []
     for layout in ("interleaved", "split"):
         for direction in ("forward", "inverse"):
             plan = fftlib.Plan(n, batch, layout, direction)
-            x, y = (xi, yi) if layout == "interleaved" else (xs, ys)
+            if layout == "interleaved":
+                x, y = (xi, yi) if direction == "forward" else (xi.clone(), torch.empty_like(yi))
+            else:
+                x, y = (xs, ys) if direction == "forward" else (tuple(t.clone() for t in xs),
+                                                               tuple(torch.empty_like(t) for t in ys))
             variants.append({"name": f"{layout}-{direction}", "plan": plan, "x": x, "y": y,
                              "desc": plan.describe()})
     flops_per_launch = variants[0]["plan"].nominal_flops
