@@ -540,8 +540,13 @@ fft_status run_nd(fft_plan p, const void* ia, const void* ib, void* oa, void* ob
             const double2* ta = p->tw64 + stp.ta_off;
             const double2* tb = p->tw64 + stp.tb_off;
             const int log2n = stp.l + stp.log2s;
+            // the first column step reads what the last-axis plan has just
+            // streamed out (not cached): streaming loads there measured
+            // faster (4096 x 4096 interleaved: 307 -> 277 us); a later step
+            // reads what the step before it left in the cache
+            const int in_stream = &stp == &p->nd.front() ? fftk::kStreamIn : 0;
             hipError_t e = ka->fn(a, b, p->ws(), nullptr, twe + stp.twe_a * p->cbytes(), ta, tb, log2n, stp.log2s,
-                                  stp.hbits, stp.blocks, stp.grid_a, 0, stp.log2s, s);
+                                  stp.hbits, stp.blocks, stp.grid_a, in_stream, stp.log2s, s);
             if (e == hipSuccess)
                 e = kb->fn(p->ws(), nullptr, a, b, twe + stp.twe_b * p->cbytes(), ta, tb, log2n, stp.log2s + stp.l1,
                            stp.hbits, stp.blocks, stp.grid_b, fftk::kStreamOut, stp.log2s, s);
