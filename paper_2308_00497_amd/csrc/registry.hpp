@@ -47,10 +47,12 @@ struct SingleKernel {
     size_t lds_bytes;
 };
 
-// sides of a pass that are the caller's buffers: read or written once, with
-// streaming (nontemporal) access
+// Per-launch access flags of a pass tile (the `stream` argument).  kStreamIn /
+// kStreamOut: the side is the caller's buffer, read or written once, with
+// streaming (nontemporal) access.  kLoadPrio: raise the wave priority while
+// the tile's loads are issued (set inside the FP32 pass kernel itself, not by
+// callers).
 constexpr int kStreamIn = 1, kStreamOut = 2;
-// pass tiles: raise the wave priority while the tile's loads are issued
 constexpr int kLoadPrio = 4;
 
 // grid = number of persistent workgroups (clamped to the number of tiles);
