@@ -170,6 +170,10 @@ fft_status fft_plan_create_nd(fft_plan *out, int rank, const int64_t *dims,
                               fft_direction dir, fft_precision precision);
 
 /* Apply the plan's transform to `batch` transforms: in -> out.
+ * Defined by: the DFT_N of Eq. 1 (section 3), applied through the plan/execute
+ * call of the precompiled library with an FFTW-like API (section 4), whose
+ * arguments are plain pointers in place of the paper's memref structs; the
+ * two pointer pairs are the layout flag of section 3, step 3.
  * in_re_or_z / out_re_or_z: interleaved array, or the real array (split).
  * in_im / out_im: the imaginary arrays (split), ignored (may be NULL) when
  * interleaved.  For a ragged plan the transforms are packed back to back in
@@ -178,7 +182,10 @@ fft_status fft_execute(fft_plan p, const void *in_re_or_z, const void *in_im,
                        void *out_re_or_z, void *out_im, void *stream);
 
 /* Apply the adjoint of the plan's transform, unnormalised: F^H (the inverse
- * transform) for a forward plan, F for an inverse plan.  This is the vector-
+ * transform) for a forward plan, F for an inverse plan.
+ * Defined by: the conjugate transpose of DFT_N in Eq. 1 (section 3); the
+ * factorisation is unitary up to the scale N, so F^H = N F^-1 is the same
+ * stages with conjugated twiddles.  This is the vector-
  * Jacobian product of fft_execute, so fft_execute followed by
  * fft_execute_backward multiplies the input by N.  Same buffers and rules as
  * fft_execute (real-input plans: see fft_plan_create_real). */
@@ -188,7 +195,8 @@ fft_status fft_execute_backward(fft_plan p, const void *grad_out_re_or_z,
 
 /* Release the plan and everything it owns (tables, workspace it allocated,
  * graphs).  NULL is a no-op.  Waits for the device to finish work that may
- * still use the plan's memory. */
+ * still use the plan's memory.
+ * Defined by: the plan lifetime of the FFTW-like library API (section 4). */
 fft_status fft_plan_destroy(fft_plan p);
 
 /* Ragged plan (FP32): `count` transforms of sizes sizes[0..count) (each a
@@ -201,6 +209,11 @@ fft_status fft_plan_destroy(fft_plan p);
  * transforms, persistent grid size, tile order) come from the autotune cache
  * for this size histogram if present; FFT_AUTOTUNE=1 times every candidate
  * configuration at creation and records the fastest, as for fft_plan_create. */
+/* Defined by: not a call of the paper - the batched form grows the method
+ * toward serving systems; its per-size radix split and tile sizes are the
+ * tiling hyperparameters of section 3, step 4, chosen by measuring candidate
+ * plans, the runtime planner section 6 names as future work.  Every transform
+ * of the batch is the DFT of Eq. 1. */
 fft_status fft_plan_create_ragged(fft_plan *out, const int64_t *sizes,
                                   int64_t count, fft_layout layout,
                                   fft_direction dir);
@@ -220,10 +233,15 @@ fft_status fft_plan_create_ragged_ex(fft_plan *out, const int64_t *sizes,
                                      int64_t count, fft_layout layout,
                                      fft_direction dir, const char *config);
 
-/* Bytes of device workspace the plan uses (0 for single-pass plans). */
+/* Bytes of device workspace the plan uses (0 for single-pass plans).
+ * Defined by: the buffers between the passes of a multi-pass plan, Eq. 1
+ * applied with M and K both larger than one pass (section 3), exposed
+ * through the plan/execute API of section 4. */
 fft_status fft_plan_workspace_bytes(fft_plan p, size_t *bytes);
 
-/* Hand the plan a caller-owned device workspace of at least
+/* Defined by: as fft_plan_workspace_bytes; the caller owns the memory, as the
+ * caller owns every data pointer handed to the library (section 4).
+ * Hand the plan a caller-owned device workspace of at least
  * fft_plan_workspace_bytes bytes (16-byte aligned); the plan frees its own.
  * NULL returns the plan to a workspace it allocates itself.  Executions of one
  * plan that overlap in time (different streams) race on the workspace. */
@@ -250,7 +268,9 @@ fft_status fft_query_decomposition(int64_t n, fft_layout layout,
  * benchmark reports beside the FFT. */
 fft_status fft_copy_device(const void *src, void *dst, size_t bytes, void *stream);
 
-/* Static description of a status code. */
+/* Static description of a status code.  Not defined by the paper: the
+ * error reporting of this boundary (every entry point returns a status and
+ * none aborts). */
 const char *fft_status_string(fft_status s);
 
 /* Detail of the most recent FFT_ERR_HIP / FFT_ERR_ALLOC on this thread

@@ -259,6 +259,13 @@ __global__ void __launch_bounds__(kThreads, 4) k_ragged(RaggedArgs a) {
     const int tid = threadIdx.x;
     uint32_t ti = blockIdx.x;
     while (ti < a.ntiles) {
+        // Each pass of this loop starts a run of another class.  The engines
+        // of classes whose transforms fit in one wavefront order LDS with
+        // wavefront fences only, and their LDS regions differ from those of
+        // the class before, so a wavefront could write the new class's first
+        // exchange while another is still reading the previous class's last
+        // one: one workgroup barrier per class change rules that out.
+        stage_sync<false>();
         const uint32_t code = a.tiles[ti].code;
         if constexpr (!PASSONLY) {
             if (code < CODE_PASS_FIRST) {

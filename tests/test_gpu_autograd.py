@@ -33,17 +33,17 @@ def c5_grad(fftlib, batch=1024, n=4096):
 
 
 def test_c5_gradient_against_oracle(fftlib):
-    """batch 1024 x N=4096 split, loss = sum(w |FFT(x)|^2): 64 seeded transforms
-    against the oracle's analytic gradient 2 F^H (w F x), per transform."""
+    """batch 1024 x N=4096 split, loss = sum(w |FFT(x)|^2): every transform's
+    gradient against the oracle's analytic gradient 2 F^H (w F x), element by
+    element, per transform."""
     re, im, w, g, _ = c5_grad(fftlib)
-    rows = np.sort(np.random.default_rng(55).choice(re.shape[0], size=64, replace=False))
-    worst = 0.0
-    for r in rows:
+    errs = np.empty(re.shape[0])
+    for r in range(re.shape[0]):
         x = re[r].astype(np.float64) + 1j * im[r].astype(np.float64)
         ref = oracle.wpower_grad(x, w[r].astype(np.float64))
-        worst = max(worst, oracle.rel_l2(g[r], ref))
-    print(f"[parity] C5 gradient: max per-transform rel-L2 {worst:.3e}")
-    assert worst <= TOL
+        errs[r] = oracle.rel_l2(g[r], ref)
+    print(f"[parity] C5 gradient, all {len(errs)} transforms: max per-transform rel-L2 {errs.max():.3e}")
+    assert errs.max() <= TOL
 
 
 def test_c5_gradient_against_finite_differences(fftlib):

@@ -232,3 +232,38 @@ def test_ragged_pipelined_matches_plain_levels(fftlib):
         assert per_item_errors(y, ref, sizes, offsets).max() <= TOL
     a, b = ys.values()
     assert per_item_errors(a, b, sizes, offsets).max() <= TOL
+
+
+def _resident_grid(fftlib, cfg):
+    """Persistent workgroups of a full level: a plan with more tiles than can be
+    resident reports the grid in its description (no data is transformed)."""
+    with fftlib.RaggedPlan(np.full(64 * 4096, 64, dtype=np.int64), "interleaved", "forward", config=cfg) as p:
+        return int(p.describe()["workgroups"])
+
+
+@pytest.mark.parametrize("layout", ["interleaved", "split"])
+def test_class_changes_inside_a_workgroup(fftlib, layout):
+    """Size mixes dealt so that every persistent workgroup of level 0 runs one
+    tile of a class whose transforms span several wavefronts (first-pass tiles
+    of 2^15, or 2^10 transforms) and then one tile of a class whose transforms
+    fit in one wavefront (2^6, or 2^9): the second class's first LDS exchange
+    must not overwrite what the first class's last stage is still reading."""
+    cfg = "ragged:p8:g8:o1"
+    w = _resident_grid(fftlib, cfg)
+    mixes = {
+        "pass->2^6": [1 << 15] * (w // 4) + [1 << 6] * (64 * w),   # 4 first-pass tiles per 2^15, 64 per 2^6 tile
+        "2^10->2^9": [1 << 10] * (4 * w) + [1 << 9] * (8 * w),     # 4 per 2^10 tile, 8 per 2^9 tile
+    }
+    for name, sz in mixes.items():
+        rng = np.random.default_rng(51)
+        sizes, offsets, re, im = make(list(rng.permutation(sz)), 52)
+        for direction in ("forward", "inverse"):
+            print(f"[case] {name} {layout} {direction} grid {w}", flush=True)
+            with fftlib.RaggedPlan(sizes, layout, direction, config=cfg) as plan:
+                d = plan.describe()
+                assert d["workgroups"] == w, d
+                y = from_device(plan.execute(to_device(re, im, layout)), layout)
+            ref = ragged_oracle(sizes, offsets, re, im, direction)
+            errs = per_item_errors(y, ref, sizes, offsets)
+            print(f"[parity] class change {name} {layout} {direction}: max rel-L2 {errs.max():.3e}", flush=True)
+            assert errs.max() <= TOL, (name, layout, direction)
