@@ -59,6 +59,7 @@ struct PassStep {
     int src;  // 0 = caller input, 1 = workspace A, 2 = workspace B
     int dst;  // 3 = caller output, 1, 2 as above
     int grid; // persistent workgroups: resident per CU x CUs
+    int ain = -1, aout = -1;  // address maps of the pass tile (-1: Stockham's own)
 };
 
 // One strided axis of a multi-dimensional plan: DFT down the columns of
@@ -238,20 +239,35 @@ fft_status resolve(fft_plan p, const Decomp& dec) {
             break;
         case Decomp::MULTI: {
             const size_t P = dec.log2l.size();
-            int log2ns = 0;
+            int log2ns = 0, halves = 0;
             for (size_t i = 0; i < P; ++i) {
                 PassStep st;
                 const bool first = i == 0, last = i == P - 1;
                 const fft_status rs = make_pass_step(p, dec, i, log2ns, split, false, &st);
                 if (rs != FFT_OK) return rs;
-                // ping-pong between two workspace halves; the last pass writes the output
-                st.src = first ? 0 : ((i - 1) % 2 == 0 ? 1 : 2);
-                st.dst = last ? 3 : (i % 2 == 0 ? 1 : 2);
+                // ping-pong between two workspace halves; the last pass writes
+                // the output.  An in-place penultimate pass (P >= 3) writes
+                // over its own input, and the last pass reads it with the
+                // address map of that layout (ain = log2 of the penultimate
+                // pass's Ns), so a three-pass chain needs one half only.
+                const int prev_dst = i == 0 ? 0 : p->steps.back().dst;
+                st.src = prev_dst;
+                if (dec.in_place(i)) {
+                    if (P < 3 || i + 2 != P) return FFT_ERR_NOT_SUPPORTED;
+                    st.dst = st.src;
+                    st.ain = p->log2n - dec.log2l[i];
+                    st.aout = st.ain;
+                } else {
+                    st.dst = last ? 3 : (prev_dst == 1 ? 2 : 1);
+                }
+                if (i > 0 && dec.in_place(i - 1)) st.ain = p->steps.back().log2ns;
+                if (st.dst == 2 || st.src == 2) halves = 2;
+                else if (halves == 0 && (st.dst == 1 || st.src == 1)) halves = 1;
                 p->steps.push_back(st);
                 log2ns += dec.log2l[i];
             }
             const size_t half = size_t(p->n) * size_t(p->batch) * p->cbytes();
-            p->ws_bytes = (P >= 3 ? 2 : 1) * half;
+            p->ws_bytes = size_t(halves) * half;
             break;
         }
     }
@@ -430,7 +446,7 @@ fft_status check_real_buffers(fft_plan p, const void* ia, const void* ib, const 
 // One real transform in direction c2r (the plan's own, or the other one for
 // the backward); iscale scales the interior bins of the complex side (1, or
 // 1/2 and 2 for the adjoints of R2C and C2R).
-fft_status run_real(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, bool c2r, double iscale,
+fft_status run_real(fft_plan p, void* wsp, const void* ia, const void* ib, void* oa, void* ob, bool c2r, double iscale,
                     hipStream_t s) {
     const bool split = p->layout == FFT_LAYOUT_SPLIT;
     hipError_t e = hipSuccess;
@@ -453,12 +469,12 @@ fft_status run_real(fft_plan p, const void* ia, const void* ib, void* oa, void* 
             return e == hipSuccess ? FFT_OK : fail_hip(e, "real single-pass launch");
         }
         case Decomp::MULTI: {
-            if (!p->ws()) {
+            if (!wsp) {
                 g_detail = "no workspace";
                 return FFT_ERR_INVALID_ARG;
             }
             const size_t half = (size_t(1) << p->log2h) * size_t(p->batch) * p->cbytes();
-            void* ws[3] = {nullptr, p->ws(), static_cast<char*>(p->ws()) + half};
+            void* ws[3] = {nullptr, wsp, static_cast<char*>(wsp) + half};
             // buffers: 0 the caller's input, 1/2 the workspace halves, 3 the
             // caller's output; C2R starts from the pre pass's output in half 1
             int prev = 0;
@@ -476,7 +492,7 @@ fft_status run_real(fft_plan p, const void* ia, const void* ib, void* oa, void* 
                 const fftk::PassKernel* k = c2r ? st.k_inv : st.k;
                 e = k->fn(src, nullptr, out, nullptr, static_cast<const char*>(p->twe) + st.twe_off * p->cbytes(),
                           p->tw64 + st.ta_off, p->tw64 + st.tb_off, p->log2h, st.log2ns, st.hbits, p->batch,
-                          st.grid, stream, 0, s);
+                          st.grid, stream, 0, -1, -1, s);
                 if (e != hipSuccess) return fail_hip(e, "pass launch");
                 prev = dst;
             }
@@ -514,12 +530,16 @@ fft_status check_buffers(fft_plan p, const void* ia, const void* ib, const void*
     return FFT_OK;
 }
 
-fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, void* stream, bool adjoint);
+// `wsp`: the workspace the passes use (the plan's own, or one the caller
+// supplies for this call only: the scratch-buffer entry point)
+fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, void* stream, bool adjoint,
+               void* wsp = nullptr);
 
 // Multi-dimensional: the last axis (inner 1D plan, in -> out), then the
 // column passes in place on the output, last-but-one axis first.
-fft_status run_nd(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, void* stream, bool adjoint) {
-    fft_status st = run(p->inner, ia, ib, oa, ob, stream, adjoint);
+fft_status run_nd(fft_plan p, void* wsp, const void* ia, const void* ib, void* oa, void* ob, void* stream,
+                  bool adjoint, bool ws_given) {
+    fft_status st = run(p->inner, ia, ib, oa, ob, stream, adjoint, ws_given ? wsp : nullptr);
     if (st != FFT_OK) return st;
     const bool inverse = (p->dir == FFT_INVERSE) != adjoint;
     const bool split = p->layout == FFT_LAYOUT_SPLIT;
@@ -530,7 +550,7 @@ fft_status run_nd(fft_plan p, const void* ia, const void* ib, void* oa, void* ob
     for (const NdStep& stp : p->nd) {
         if (stp.l) {
             // out -> workspace -> out; the pass twiddles see the column's own index only
-            if (!p->ws()) {
+            if (!wsp) {
                 g_detail = "no workspace";
                 return FFT_ERR_INVALID_ARG;
             }
@@ -545,11 +565,11 @@ fft_status run_nd(fft_plan p, const void* ia, const void* ib, void* oa, void* ob
             // faster (4096 x 4096 interleaved: 307 -> 277 us); a later step
             // reads what the step before it left in the cache
             const int in_stream = &stp == &p->nd.front() ? fftk::kStreamIn : 0;
-            hipError_t e = ka->fn(a, b, p->ws(), nullptr, twe + stp.twe_a * p->cbytes(), ta, tb, log2n, stp.log2s,
-                                  stp.hbits, stp.blocks, stp.grid_a, in_stream, stp.log2s, s);
+            hipError_t e = ka->fn(a, b, wsp, nullptr, twe + stp.twe_a * p->cbytes(), ta, tb, log2n, stp.log2s,
+                                  stp.hbits, stp.blocks, stp.grid_a, in_stream, stp.log2s, -1, -1, s);
             if (e == hipSuccess)
-                e = kb->fn(p->ws(), nullptr, a, b, twe + stp.twe_b * p->cbytes(), ta, tb, log2n, stp.log2s + stp.l1,
-                           stp.hbits, stp.blocks, stp.grid_b, fftk::kStreamOut, stp.log2s, s);
+                e = kb->fn(wsp, nullptr, a, b, twe + stp.twe_b * p->cbytes(), ta, tb, log2n, stp.log2s + stp.l1,
+                           stp.hbits, stp.blocks, stp.grid_b, fftk::kStreamOut, stp.log2s, -1, -1, s);
             if (e != hipSuccess) return fail_hip(e, "column pass launch");
             continue;
         }
@@ -561,17 +581,20 @@ fft_status run_nd(fft_plan p, const void* ia, const void* ib, void* oa, void* ob
     return FFT_OK;
 }
 
-fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, void* stream, bool adjoint) {
+fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, void* stream, bool adjoint,
+               void* wsp) {
     fft_status st = check_buffers(p, ia, ib, oa, ob, adjoint);
     if (st != FFT_OK) return st;
     DeviceGuard guard(p->device);
-    if (p->rank > 1) return run_nd(p, ia, ib, oa, ob, stream, adjoint);
+    const bool ws_given = wsp != nullptr;
+    if (!ws_given) wsp = p->ws();
+    if (p->rank > 1) return run_nd(p, wsp, ia, ib, oa, ob, stream, adjoint, ws_given);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (p->real) {
         // the backward of R2C is C2R with the interior bins halved, of C2R
         // R2C with them doubled (the adjoints under the real inner product)
         const bool c2r = (p->dir == FFT_INVERSE) != adjoint;
-        return run_real(p, ia, ib, oa, ob, c2r, adjoint ? (c2r ? 0.5 : 2.0) : 1.0, s);
+        return run_real(p, wsp, ia, ib, oa, ob, c2r, adjoint ? (c2r ? 0.5 : 2.0) : 1.0, s);
     }
     // forward kernels everywhere; the inverse swaps re and im on the way in and
     // out: split arrays by exchanging the pointers, interleaved data in-kernel
@@ -604,12 +627,12 @@ fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, v
         case Decomp::OPS: {
             // Permute for l = 0 .. L-2, innermost DFT blocks, then Mul and
             // FusedMKIV for l = L-2 .. 0; ping-pong through the workspace
-            if (!p->ws()) {
+            if (!wsp) {
                 g_detail = "no workspace";
                 return FFT_ERR_INVALID_ARG;
             }
             const size_t full = size_t(p->n) * size_t(p->batch) * p->cbytes();
-            void* buf[2] = {p->ws(), static_cast<char*>(p->ws()) + full};
+            void* buf[2] = {wsp, static_cast<char*>(wsp) + full};
             const int L = static_cast<int>(p->ops_r.size());
             const int nops = 3 * L - 2;
             int done = 0, cur = -1;  // cur = -1: the caller's input
@@ -651,13 +674,13 @@ fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, v
             return FFT_OK;
         }
         case Decomp::MULTI: {
-            if (!p->ws()) {
+            if (!wsp) {
                 g_detail = "no workspace";
                 return FFT_ERR_INVALID_ARG;
             }
             const size_t half = size_t(p->n) * size_t(p->batch) * p->cbytes();
-            void* wsa = p->ws();
-            void* wsb = static_cast<char*>(p->ws()) + half;
+            void* wsa = wsp;
+            void* wsb = static_cast<char*>(wsp) + half;
             const size_t P = p->steps.size();
             for (size_t i = 0; i < P; ++i) {
                 const PassStep& stp = p->steps[i];
@@ -682,7 +705,7 @@ fft_status run(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, v
                 e = k->fn(sa, sb, da, db, static_cast<const char*>(p->twe) + stp.twe_off * p->cbytes(),
                           p->tw64 ? p->tw64 + stp.ta_off : nullptr,
                           p->tw64 ? p->tw64 + stp.tb_off : nullptr, p->log2n, stp.log2ns, stp.hbits, p->batch,
-                          stp.grid, stream, 0, s);
+                          stp.grid, stream, 0, stp.ain, stp.aout, s);
                 if (e != hipSuccess) return fail_hip(e, "pass launch");
             }
             (void)split;

@@ -275,6 +275,16 @@ struct PassShape {
 // twiddles must not see: w_M'^(r (k >> s)), M' = (Ns >> s) L (the column
 // passes of a multi-dimensional plan, columns at stride 2^s, run as passes of
 // a chain whose Ns starts at 2^s; the tables are then those of M').
+// Addresses: input r of column j sits at
+//   tbase + (j mod 2^ain) + ((j div 2^ain) 2^(ain + LOG2L)) + r 2^ain,
+// and output q of a later pass at the same expression in aout.  The Stockham
+// pass has ain = log2 N - LOG2L (j < 2^ain: x[j + r N/L]) and aout = log2 Ns
+// (y[(j div Ns) Ns L + k + q Ns]); a negative argument selects these.  A pass
+// with aout = ain writes its results over its own inputs (an in-place pass: a
+// tile reads every address it writes, and all its loads are consumed before
+// the engine's first barrier, so no tile overwrites data another still needs);
+// the pass after an in-place penultimate pass finds its inputs with
+// ain = log2 of that pass's Ns.
 // A thread holds r = tp + T m (m < E), so w_M^(r k) = w_M^(tp k) (w_M^(T k))^m:
 // two table lookups per thread and an FP64 running product, rounded once per
 // element to the working precision (PASSTW = false leaves the factors out: a
@@ -291,13 +301,15 @@ __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R
                                           const TW& tw, const double2* __restrict__ ta,
                                           const double2* __restrict__ tb, int log2N, int log2Ns, int hbits,
                                           int64_t tbase, int64_t j0, cplx_t<R>* lds, int tid, int stream,
-                                          int twshift = 0) {
+                                          int twshift = 0, int ain = -1, int aout = -1) {
     using V = cplx_t<R>;
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     using SC = typename SH::SC;
     constexpr int E = SC::E, T = SC::T, C = SH::C;
     static_assert(SC::NST >= 2, "a pass needs at least two stages to change the thread mapping");
-    const int64_t stride = int64_t(1) << (log2N - LOG2L);  // distance between the L inputs of a column
+    if (ain < 0) ain = log2N - LOG2L;
+    if (aout < 0) aout = log2Ns;
+    const int64_t stride = int64_t(1) << ain;  // distance between the L inputs of a column
     const int64_t NsMask = (int64_t(1) << log2Ns) - 1;
 
     // load: column-fast mapping, C consecutive columns form one contiguous run
@@ -306,7 +318,7 @@ __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R
         const int c = tid & (C - 1), tp = tid >> LOG2C;
         const int64_t j = j0 + c;
         const int64_t k = j & NsMask;
-        const int64_t i0 = tbase + j + tp * stride;
+        const int64_t i0 = tbase + (j & (stride - 1)) + ((j >> ain) << (ain + LOG2L)) + tp * stride;
         if (stream & kLoadPrio) loads_begin();
         if (stream & kStreamIn) {
 #pragma unroll
@@ -346,16 +358,15 @@ __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R
     } else {
         const int c = tid & (C - 1), tp = tid >> LOG2C;
         const int64_t j = j0 + c;
-        const int64_t k = j & NsMask;
-        const int64_t obase = tbase + ((j >> log2Ns) << (log2Ns + LOG2L)) + k;
+        const int64_t obase = tbase + ((j >> aout) << (aout + LOG2L)) + (j & ((int64_t(1) << aout) - 1));
         if (stream & kStreamOut) {
 #pragma unroll
             for (int m = 0; m < E; ++m)
-                gstore_nt<SPLIT_OUT>(oa, ob, obase + (int64_t(tp + T * m) << log2Ns), swap_if<SWAP_OUT>(v[m]));
+                gstore_nt<SPLIT_OUT>(oa, ob, obase + (int64_t(tp + T * m) << aout), swap_if<SWAP_OUT>(v[m]));
         } else {
 #pragma unroll
             for (int m = 0; m < E; ++m)
-                gstore<SPLIT_OUT>(oa, ob, obase + (int64_t(tp + T * m) << log2Ns), swap_if<SWAP_OUT>(v[m]));
+                gstore<SPLIT_OUT>(oa, ob, obase + (int64_t(tp + T * m) << aout), swap_if<SWAP_OUT>(v[m]));
         }
     }
 }
@@ -368,7 +379,8 @@ template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, b
           bool SWAP_OUT>
 __global__ void __launch_bounds__((PassShape<LOG2L, LOG2E, LOG2C>::THREADS))
 k_pass(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw, const double2* __restrict__ ta,
-       const double2* __restrict__ tb, int log2N, int log2Ns, int hbits, int64_t tiles, int stream, int twshift) {
+       const double2* __restrict__ tb, int log2N, int log2Ns, int hbits, int64_t tiles, int stream, int twshift,
+       int ain, int aout) {
     using V = cplx_t<R>;
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     using SC = typename SH::SC;
@@ -394,11 +406,12 @@ k_pass(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw,
         const int64_t j0 = (tile & ((int64_t(1) << log2TilesPerT) - 1)) << LOG2C;
         if constexpr (REGTW)
             pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>(
-                ia, ib, oa, ob, twr, ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl, stream, twshift);
+                ia, ib, oa, ob, twr, ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl, stream, twshift, ain,
+                aout);
         else
             pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>(
                 ia, ib, oa, ob, TwMem<SC, V>(tw), ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl, stream,
-                twshift);
+                twshift, ain, aout);
     }
 }
 
@@ -406,16 +419,21 @@ template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, b
           bool SWAP_OUT>
 hipError_t launch_pass(const void* ia, const void* ib, void* oa, void* ob, const void* tw, const double2* ta,
                        const double2* tb, int log2N, int log2Ns, int hbits, int64_t batch, int grid, int stream,
-                       int twshift, hipStream_t s) {
+                       int twshift, int ain, int aout, hipStream_t s) {
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     if (log2N < LOG2L + LOG2C) return hipErrorInvalidConfiguration;
+    // runs of C columns must stay contiguous on both sides: ain, aout >= log2 C
+    // (a first pass stores whole columns and takes no aout)
+    if (ain >= 0 && (ain < LOG2C || ain > log2N - LOG2L)) return hipErrorInvalidConfiguration;
+    if (aout >= 0 && (FIRST || aout < LOG2C || aout > log2N - LOG2L)) return hipErrorInvalidConfiguration;
     const int64_t tiles = (int64_t(1) << (log2N - LOG2L - LOG2C)) * batch;
     const int64_t blocks = tiles < grid ? tiles : grid;
     if (blocks < 1) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((k_pass<R, LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>),
                        dim3(static_cast<unsigned>(blocks)), dim3(SH::THREADS), 0, s, static_cast<const R*>(ia),
                        static_cast<const R*>(ib), static_cast<R*>(oa), static_cast<R*>(ob),
-                       static_cast<const cplx_t<R>*>(tw), ta, tb, log2N, log2Ns, hbits, tiles, stream, twshift);
+                       static_cast<const cplx_t<R>*>(tw), ta, tb, log2N, log2Ns, hbits, tiles, stream, twshift, ain,
+                       aout);
     return hipGetLastError();
 }
 

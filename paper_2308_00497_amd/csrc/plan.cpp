@@ -36,7 +36,7 @@ std::string Decomp::str() const {
         case MULTI: {
             std::string s = "multi:";
             for (size_t p = 0; p < log2l.size(); ++p) {
-                snprintf(buf, sizeof buf, "%s%dc%d", p ? "," : "", log2l[p], log2c[p]);
+                snprintf(buf, sizeof buf, "%s%dc%d%s", p ? "," : "", log2l[p], log2c[p], in_place(p) ? "i" : "");
                 s += buf;
             }
             return s;
@@ -86,6 +86,8 @@ bool Decomp::parse(const std::string& s, Decomp* out) {
             d.log2l.push_back(l);
             d.log2c.push_back(c);
             p += used;
+            d.inplace.push_back(*p == 'i' ? 1 : 0);
+            if (*p == 'i') ++p;
             if (*p == ',') ++p;
             else if (*p) return false;
         }
@@ -179,8 +181,19 @@ bool decomposition_available(const Decomp& d, int log2n, fft_layout layout, int 
             for (int l : d.log2l) sum += l;
             if (sum != log2n || d.log2l.size() != d.log2c.size()) return false;
             // every pass needs at least 2^log2c columns
-            for (size_t p = 0; p < d.log2l.size(); ++p)
+            const size_t P = d.log2l.size();
+            for (size_t p = 0; p < P; ++p)
                 if (log2n - d.log2l[p] < d.log2c[p]) return false;
+            // only the penultimate pass of a chain of three or more may run in
+            // place, and the last pass then reads runs of 2^(l_1 + .. + l_(P-2))
+            // elements, which must hold its 2^log2c columns
+            for (size_t p = 0; p < P; ++p)
+                if (d.in_place(p) && (P < 3 || p + 2 != P)) return false;
+            if (P >= 3 && d.in_place(P - 2)) {
+                int ns = 0;
+                for (size_t p = 0; p + 2 < P; ++p) ns += d.log2l[p];
+                if (ns < d.log2c[P - 1]) return false;
+            }
             return pass_chain_available(d.log2l, d.log2c, layout, rb);
         }
     }
@@ -348,6 +361,8 @@ bool real_decomposition_available(const Decomp& d, int log2n, fft_layout layout,
             int sum = 0;
             for (int l : d.log2l) sum += l;
             if (sum != log2h || d.log2l.size() != d.log2c.size() || d.log2l.size() < 2) return false;
+            for (int f : d.inplace)
+                if (f) return false;  // real chains keep the Stockham addressing
             const size_t P = d.log2l.size();
             for (size_t q = 0; q < P; ++q) {
                 if (log2h - d.log2l[q] < d.log2c[q]) return false;
@@ -468,6 +483,12 @@ std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int r
                 bool sorted = true;
                 for (int p = 1; p < parts; ++p) sorted &= d.log2l[p] <= d.log2l[p - 1];
                 if (sorted && decomposition_available(d, log2n, layout, rb)) out.push_back(d);
+                if (sorted && parts >= 3) {
+                    // the same chain with an in-place penultimate pass
+                    d.inplace.assign(parts, 0);
+                    d.inplace[parts - 2] = 1;
+                    if (decomposition_available(d, log2n, layout, rb)) out.push_back(d);
+                }
             }
             int p = parts - 1;
             while (p >= 0 && ++idx[p] == lc.size()) idx[p--] = 0;

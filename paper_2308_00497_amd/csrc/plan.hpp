@@ -32,8 +32,10 @@ struct Decomp {
     bool stg = false; // single: contiguous loads/stores staged through LDS (small transforms)
     std::vector<int> log2l;
     std::vector<int> log2c;
+    std::vector<int> inplace;  // per pass: 1 = writes over its own input ("i" suffix)
+    bool in_place(size_t p) const { return p < inplace.size() && inplace[p] != 0; }
 
-    std::string str() const;  // "copy" | "single:e4:w256:g2:r1[:p1|:s1]" | "multi:8c4,8c4,8c4" | "ops:r4"
+    std::string str() const;  // "copy" | "single:e4:w256:g2:r1[:p1|:s1]" | "multi:8c4,8c4i,8c4" | "ops:r4"
     static bool parse(const std::string& s, Decomp* out);
     bool operator==(const Decomp& o) const { return str() == o.str(); }
 };

@@ -58,10 +58,12 @@ constexpr int kLoadPrio = 4;
 // grid = number of persistent workgroups (clamped to the number of tiles);
 // stream = kStreamIn | kStreamOut for the sides that are the caller's buffers
 // (streaming access), 0 for workspace on both sides; twshift = low bits of
-// the column index hidden from the pass twiddles (0 for 1D chains)
+// the column index hidden from the pass twiddles (0 for 1D chains); ain/aout
+// = the address maps of the pass tile (-1: the Stockham pass's own; equal
+// values: an in-place pass)
 using pass_fn = hipError_t (*)(const void* ia, const void* ib, void* oa, void* ob, const void* tw, const double2* ta,
                                const double2* tb, int log2N, int log2Ns, int hbits, int64_t batch, int grid,
-                               int stream, int twshift, hipStream_t s);
+                               int stream, int twshift, int ain, int aout, hipStream_t s);
 
 struct PassKernel {
     int real_bytes; // 4 (FP32) or 8 (FP64)
