@@ -252,6 +252,24 @@ fft_status fft_plan_set_workspace(fft_plan p, void *dev_ptr);
 fft_status fft_plan_sizes(fft_plan p, int64_t *transforms, int64_t *elements,
                           double *nominal_flops);
 
+/* For callers that cannot allocate device memory during execution (code under
+ * HIP stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * fft_execute with the workspace of the multi-pass kernels taken from a static
+ * device array of the library (fft_no_alloc_scratch_bytes() = 64 MiB per GPU,
+ * held by every GPU the library is loaded on until the process ends) instead
+ * of the plan's own.  The call allocates and frees nothing.  Arguments, layout,
+ * ownership and results are those of fft_execute (bitwise the same output).
+ * Plans whose workspace exceeds the scratch size return FFT_ERR_INVALID_SIZE,
+ * ragged plans FFT_ERR_NOT_SUPPORTED, both before any launch.  All calls on one
+ * GPU share its array: calls that overlap in time on one GPU (other streams,
+ * other threads) race on it and must be ordered by the caller. */
+fft_status fft_execute_no_alloc(fft_plan p, const void *in_re_or_z,
+                                const void *in_im, void *out_re_or_z,
+                                void *out_im, void *stream);
+
+/* Size in bytes of the static scratch array behind fft_execute_no_alloc. */
+size_t fft_no_alloc_scratch_bytes(void);
+
 /* Human-readable JSON description of the chosen decomposition (kernel kind,
  * radices, passes, tiles) into buf (NUL-terminated, truncated to len). */
 fft_status fft_plan_describe(fft_plan p, char *buf, size_t len);

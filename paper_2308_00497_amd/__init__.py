@@ -135,6 +135,16 @@ class _PlanBase:
         check(lib.fft_execute(self._handle, ia, ib, oa, ob, _stream_handle(stream)), "fft_execute")
         return out
 
+    def execute_no_alloc(self, x, out, stream=None):
+        """execute() on the library's static scratch buffer (fft_execute_no_alloc):
+        the call allocates nothing; `out` must be supplied."""
+        if out is None:
+            raise ValueError("execute_no_alloc needs a caller-supplied output")
+        ia, ib, oa, ob, out = self._io(x, out)
+        check(lib.fft_execute_no_alloc(self._handle, ia, ib, oa, ob, _stream_handle(stream)),
+              "fft_execute_no_alloc")
+        return out
+
     def backward(self, g, out=None, stream=None):
         """Adjoint of execute (unnormalised): F^H g for a forward plan, F g for an inverse plan."""
         ia, ib, oa, ob, out = self._io(g, out)

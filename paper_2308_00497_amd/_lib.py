@@ -39,6 +39,8 @@ EXPORTS = [
     "fft_plan_create_nd",
     "fft_execute",
     "fft_execute_backward",
+    "fft_execute_no_alloc",
+    "fft_no_alloc_scratch_bytes",
     "fft_plan_destroy",
     "fft_plan_create_ragged",
     "fft_plan_create_ragged_ex",
@@ -74,6 +76,8 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.fft_plan_create_nd.argtypes = [ctypes.POINTER(vp), ci, ctypes.POINTER(i64), i64, ci, ci, ci]
     lib.fft_execute.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.fft_execute_backward.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.fft_execute_no_alloc.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.fft_no_alloc_scratch_bytes.argtypes = []
     lib.fft_plan_destroy.argtypes = [vp]
     lib.fft_plan_create_ragged.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), i64, ci, ci]
     lib.fft_plan_create_ragged_ex.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), i64, ci, ci, ctypes.c_char_p]
@@ -88,8 +92,9 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.fft_last_error_detail.argtypes = []
     lib.fft_last_error_detail.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("fft_status_string", "fft_last_error_detail"):
+        if name not in ("fft_status_string", "fft_last_error_detail", "fft_no_alloc_scratch_bytes"):
             getattr(lib, name).restype = ci
+    lib.fft_no_alloc_scratch_bytes.restype = ctypes.c_size_t
     return lib
 
 

@@ -36,6 +36,7 @@ SOURCES = [
     "k_nd.hip",
     "k_misc.hip",
     "ragged.hip",
+    "noalloc.hip",
     "plan.cpp",
     "autotune.cpp",
     "capi.cpp",

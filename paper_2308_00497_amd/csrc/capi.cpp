@@ -1369,3 +1369,30 @@ int plan_log2n(fft_plan p) { return p->log2n; }
 int plan_real_bytes(fft_plan p) { return p->rb; }
 
 }  // namespace fftk
+
+// ---------------------------------------------------------------------------
+// hooks for the entry point that runs on the library's static scratch buffer
+// ---------------------------------------------------------------------------
+namespace fftk {
+
+fft_status plan_scratch_need(fft_plan p, size_t* bytes, int* device) {
+    if (!plan_ok(p)) return FFT_ERR_INVALID_ARG;
+    if (p->ragged) {
+        g_detail = "ragged plans keep their own workspace ring; use fft_execute";
+        return FFT_ERR_NOT_SUPPORTED;
+    }
+    size_t need = p->ws_bytes;
+    if (p->inner && p->inner->ws_bytes > need) need = p->inner->ws_bytes;
+    *bytes = need;
+    *device = p->device;
+    return FFT_OK;
+}
+
+fft_status execute_with_workspace(fft_plan p, const void* ia, const void* ib, void* oa, void* ob, void* stream,
+                                  void* ws) {
+    return run(p, ia, ib, oa, ob, stream, false, ws);
+}
+
+void set_error_detail(const char* what) { g_detail = what; }
+
+}  // namespace fftk

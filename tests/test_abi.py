@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def header_functions():
     text = open(os.path.join(ROOT, "include", "fft.h")).read()
-    return sorted(set(re.findall(r"^(?:fft_status|const char \*)\s*(fft_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^(?:fft_status|const char \*|size_t)\s*(fft_\w+)\s*\(", text, re.M)))
 
 
 @pytest.fixture(scope="module")
