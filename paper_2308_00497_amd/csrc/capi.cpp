@@ -318,6 +318,10 @@ fft_status resolve_real(fft_plan p, const Decomp& dec) {
                 // the buffers of each pass are chosen at execution (run_real)
                 const fft_status rs = make_pass_step(p, dec, i, log2ns, false, false, &st);
                 if (rs != FFT_OK) return rs;
+                // an in-place penultimate pass (src = dst at execution) and the
+                // address map of the pass after it, as in complex chains
+                if (dec.in_place(i)) st.ain = st.aout = p->log2h - dec.log2l[i];
+                if (i > 0 && dec.in_place(i - 1)) st.ain = p->steps.back().log2ns;
                 p->steps.push_back(st);
                 log2ns += dec.log2l[i];
             }
@@ -485,14 +489,15 @@ fft_status run_real(fft_plan p, void* wsp, const void* ia, const void* ib, void*
             }
             for (size_t i = 0; i < p->steps.size(); ++i) {
                 const PassStep& st = p->steps[i];
-                const int dst = (c2r && i + 1 == p->steps.size()) ? 3 : (prev == 1 ? 2 : 1);
+                const bool in_place = st.aout >= 0 && st.aout == st.ain;  // the penultimate pass only, prev is a half
+                const int dst = (c2r && i + 1 == p->steps.size()) ? 3 : in_place ? prev : (prev == 1 ? 2 : 1);
                 const void* src = prev == 0 ? ia : ws[prev];
                 void* out = dst == 3 ? oa : ws[dst];
                 const int stream = (prev == 0 ? fftk::kStreamIn : 0) | (dst == 3 ? fftk::kStreamOut : 0);
                 const fftk::PassKernel* k = c2r ? st.k_inv : st.k;
                 e = k->fn(src, nullptr, out, nullptr, static_cast<const char*>(p->twe) + st.twe_off * p->cbytes(),
                           p->tw64 + st.ta_off, p->tw64 + st.tb_off, p->log2h, st.log2ns, st.hbits, p->batch,
-                          st.grid, stream, 0, -1, -1, s);
+                          st.grid, stream, 0, st.ain, st.aout, s);
                 if (e != hipSuccess) return fail_hip(e, "pass launch");
                 prev = dst;
             }

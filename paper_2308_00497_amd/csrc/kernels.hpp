@@ -294,8 +294,15 @@ struct PassShape {
 // units of FP64 rounding for the FP64 instances).
 template <class T> struct nodeduce { using type = T; };
 
+// The stream bits in KMASK are fixed at compile time to KVAL (the others come
+// from `stream` at run time).  A run-time choice between a streaming and an
+// ordinary access of the same address lets the compiler merge the two into one
+// ordinary access when it simplifies this function before inlining it (it
+// hoists identical scalar loads or stores out of both branches and drops the
+// nontemporal hint), so callers fix the bits of the split-array sides, whose
+// accesses are plain floats.
 template <int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN, bool SWAP_OUT,
-          class TW, class R, bool PASSTW = true>
+          class TW, class R, bool PASSTW = true, int KMASK = 0, int KVAL = 0>
 __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R>::type* ib,
                                           typename nodeduce<R>::type* oa, typename nodeduce<R>::type* ob,
                                           const TW& tw, const double2* __restrict__ ta,
@@ -320,12 +327,20 @@ __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R
         const int64_t k = j & NsMask;
         const int64_t i0 = tbase + (j & (stride - 1)) + ((j >> ain) << (ain + LOG2L)) + tp * stride;
         if (stream & kLoadPrio) loads_begin();
-        if (stream & kStreamIn) {
+        auto load_nt = [&] {
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = swap_if<SWAP_IN>(gload_nt<SPLIT_IN>(ia, ib, i0 + T * m * stride));
-        } else {
+        };
+        auto load = [&] {
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = swap_if<SWAP_IN>(gload<SPLIT_IN>(ia, ib, i0 + T * m * stride));
+        };
+        if constexpr ((KMASK & kStreamIn) != 0) {
+            if constexpr ((KVAL & kStreamIn) != 0) load_nt();
+            else load();
+        } else {
+            if (stream & kStreamIn) load_nt();
+            else load();
         }
         if (stream & kLoadPrio) loads_end();
         if constexpr (!FIRST && PASSTW) {
@@ -348,25 +363,41 @@ __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R
         const int t = tid % T, c = tid / T;
         const int64_t j = j0 + c;
         const int64_t obase = tbase + (j << LOG2L) + t;
-        if (stream & kStreamOut) {
+        auto store_nt = [&] {
 #pragma unroll
             for (int m = 0; m < E; ++m) gstore_nt<SPLIT_OUT>(oa, ob, obase + T * m, swap_if<SWAP_OUT>(v[m]));
-        } else {
+        };
+        auto store = [&] {
 #pragma unroll
             for (int m = 0; m < E; ++m) gstore<SPLIT_OUT>(oa, ob, obase + T * m, swap_if<SWAP_OUT>(v[m]));
+        };
+        if constexpr ((KMASK & kStreamOut) != 0) {
+            if constexpr ((KVAL & kStreamOut) != 0) store_nt();
+            else store();
+        } else {
+            if (stream & kStreamOut) store_nt();
+            else store();
         }
     } else {
         const int c = tid & (C - 1), tp = tid >> LOG2C;
         const int64_t j = j0 + c;
         const int64_t obase = tbase + ((j >> aout) << (aout + LOG2L)) + (j & ((int64_t(1) << aout) - 1));
-        if (stream & kStreamOut) {
+        auto store_nt = [&] {
 #pragma unroll
             for (int m = 0; m < E; ++m)
                 gstore_nt<SPLIT_OUT>(oa, ob, obase + (int64_t(tp + T * m) << aout), swap_if<SWAP_OUT>(v[m]));
-        } else {
+        };
+        auto store = [&] {
 #pragma unroll
             for (int m = 0; m < E; ++m)
                 gstore<SPLIT_OUT>(oa, ob, obase + (int64_t(tp + T * m) << aout), swap_if<SWAP_OUT>(v[m]));
+        };
+        if constexpr ((KMASK & kStreamOut) != 0) {
+            if constexpr ((KVAL & kStreamOut) != 0) store_nt();
+            else store();
+        } else {
+            if (stream & kStreamOut) store_nt();
+            else store();
         }
     }
 }
@@ -375,12 +406,15 @@ __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R
 // so that the tiles one XCD works on are consecutive), with the sub-FFT's stage
 // twiddles held in registers across tiles.  `stream` says which side is the
 // caller's data (streaming access); the workspace between passes is not.
+//
+// The tile loop, with the stream bits in KMASK fixed at compile time to KVAL
+// (pass_tile): the split-array sides take their stream bit as a constant.
 template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN,
-          bool SWAP_OUT>
-__global__ void __launch_bounds__((PassShape<LOG2L, LOG2E, LOG2C>::THREADS))
-k_pass(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw, const double2* __restrict__ ta,
-       const double2* __restrict__ tb, int log2N, int log2Ns, int hbits, int64_t tiles, int stream, int twshift,
-       int ain, int aout) {
+          bool SWAP_OUT, int KMASK, int KVAL>
+__device__ __forceinline__ void pass_loop(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw,
+                                          const double2* __restrict__ ta, const double2* __restrict__ tb, int log2N,
+                                          int log2Ns, int hbits, int64_t tiles, int stream, int twshift, int ain,
+                                          int aout, cplx_t<R>* lds) {
     using V = cplx_t<R>;
     using SH = PassShape<LOG2L, LOG2E, LOG2C>;
     using SC = typename SH::SC;
@@ -389,7 +423,6 @@ k_pass(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw,
     // threads: at most 128 registers per lane) that they would spill, or the
     // elements are FP64 (twice the registers per entry)
     constexpr bool REGTW = SH::THREADS <= 512 && sizeof(R) == 4;
-    __shared__ V lds[SH::LDS];
     const int tid = threadIdx.x;
     TwReg<SC, V> twr(tw);
     if constexpr (REGTW) twr.template init_engine<ENG>(tid);
@@ -405,14 +438,37 @@ k_pass(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw,
         const int64_t b = tile >> log2TilesPerT;
         const int64_t j0 = (tile & ((int64_t(1) << log2TilesPerT) - 1)) << LOG2C;
         if constexpr (REGTW)
-            pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>(
-                ia, ib, oa, ob, twr, ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl, stream, twshift, ain,
-                aout);
+            pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT, TwReg<SC, V>, R, true,
+                      KMASK, KVAL>(ia, ib, oa, ob, twr, ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl,
+                                   stream, twshift, ain, aout);
         else
-            pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>(
-                ia, ib, oa, ob, TwMem<SC, V>(tw), ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl, stream,
-                twshift, ain, aout);
+            pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT, TwMem<SC, V>, R, true,
+                      KMASK, KVAL>(ia, ib, oa, ob, TwMem<SC, V>(tw), ta, tb, log2N, log2Ns, hbits, b << log2N, j0,
+                                   lds, tidl, stream, twshift, ain, aout);
     }
+}
+
+template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN,
+          bool SWAP_OUT>
+__global__ void __launch_bounds__((PassShape<LOG2L, LOG2E, LOG2C>::THREADS))
+k_pass(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw, const double2* __restrict__ ta,
+       const double2* __restrict__ tb, int log2N, int log2Ns, int hbits, int64_t tiles, int stream, int twshift,
+       int ain, int aout) {
+    using SH = PassShape<LOG2L, LOG2E, LOG2C>;
+    __shared__ cplx_t<R> lds[SH::LDS];
+#define FFTK_PASS_LOOP(KM, KV)                                                                                   \
+    pass_loop<R, LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT, KM, KV>(                    \
+        ia, ib, oa, ob, tw, ta, tb, log2N, log2Ns, hbits, tiles, stream, twshift, ain, aout, lds)
+    if constexpr (SPLIT_IN) {
+        if (stream & kStreamIn) FFTK_PASS_LOOP(kStreamIn, kStreamIn);
+        else FFTK_PASS_LOOP(kStreamIn, 0);
+    } else if constexpr (SPLIT_OUT) {
+        // split output is always the caller's buffer (launch_pass checks)
+        FFTK_PASS_LOOP(kStreamOut, kStreamOut);
+    } else {
+        FFTK_PASS_LOOP(0, 0);
+    }
+#undef FFTK_PASS_LOOP
 }
 
 template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN,
@@ -426,6 +482,7 @@ hipError_t launch_pass(const void* ia, const void* ib, void* oa, void* ob, const
     // (a first pass stores whole columns and takes no aout)
     if (ain >= 0 && (ain < LOG2C || ain > log2N - LOG2L)) return hipErrorInvalidConfiguration;
     if (aout >= 0 && (FIRST || aout < LOG2C || aout > log2N - LOG2L)) return hipErrorInvalidConfiguration;
+    if (SPLIT_OUT && !(stream & kStreamOut)) return hipErrorInvalidValue;  // compiled for streaming stores only
     const int64_t tiles = (int64_t(1) << (log2N - LOG2L - LOG2C)) * batch;
     const int64_t blocks = tiles < grid ? tiles : grid;
     if (blocks < 1) return hipErrorInvalidConfiguration;

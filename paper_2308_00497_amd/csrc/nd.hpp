@@ -35,10 +35,10 @@ k_strided(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ 
         const int64_t j0 = (lin & ((int64_t(1) << log2tpb) - 1)) << LOG2C;
         const int64_t tbase = b << (log2s + LOG2L);
         if constexpr (REGTW)
-            pass_tile<LOG2L, 4, LOG2C, false, SPLIT, SPLIT, SWAP, SWAP, TwReg<SC, V>, R, false>(
+            pass_tile<LOG2L, 4, LOG2C, false, SPLIT, SPLIT, SWAP, SWAP, TwReg<SC, V>, R, false, 3, 0>(
                 ia, ib, oa, ob, twr, nullptr, nullptr, log2s + LOG2L, log2s, 0, tbase, j0, lds, tidl, 0);
         else
-            pass_tile<LOG2L, 4, LOG2C, false, SPLIT, SPLIT, SWAP, SWAP, TwMem<SC, V>, R, false>(
+            pass_tile<LOG2L, 4, LOG2C, false, SPLIT, SPLIT, SWAP, SWAP, TwMem<SC, V>, R, false, 3, 0>(
                 ia, ib, oa, ob, TwMem<SC, V>(tw), nullptr, nullptr, log2s + LOG2L, log2s, 0, tbase, j0, lds, tidl, 0);
     }
 }

@@ -69,3 +69,18 @@ def c2r_vjp_bruteforce(g: np.ndarray, n: int) -> np.ndarray:
     cols = oracle.irfft(units, n, threads=8)  # (2h, n)
     dots = g.astype(np.float64) @ cols.T      # (b, 2h)
     return dots[:, :h] + 1j * dots[:, h:]
+
+
+def multi_candidates(cands: list[str], default: str, limit: int) -> list[str]:
+    """The multi-pass decompositions among `cands`: all of them when there are
+    at most `limit`, else an evenly spaced subset of `limit` plus the default
+    (the sizes below the largest run every candidate, so every compiled pass
+    kernel is still exercised)."""
+    multi = [d for d in cands if d.startswith("multi")]
+    if len(multi) <= limit:
+        return multi
+    step = len(multi) / limit
+    pick = [multi[int(i * step)] for i in range(limit)]
+    if default.startswith("multi") and default not in pick:
+        pick.append(default)
+    return pick

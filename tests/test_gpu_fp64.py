@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import workloads
-from fftcheck import SIGN, TOL64, assert_parity, from_device, oracle_ref, to_device, widen
+from fftcheck import SIGN, TOL64, assert_parity, from_device, multi_candidates, oracle_ref, to_device, widen
 
 pytestmark = pytest.mark.gpu
 
@@ -72,9 +72,9 @@ def test_every_multi_pass_variant_fp64(fftlib, log2n, layout):
     re, im = workloads.uniform_complex((batch, n), seed=7200 + log2n, dtype=F64)
     ref = oracle_ref(re, im, direction)
     seen = 0
-    for dec in candidates(fftlib, log2n, layout):
-        if not dec.startswith("multi"):
-            continue
+    q = fftlib.query_decomposition(n, layout, "fp64")
+    # 2^24: a spread of the ~400 chains (every pass kernel runs at the smaller sizes)
+    for dec in multi_candidates(q["candidates"], q["default"], 48 if log2n >= 24 else 10**6):
         with fftlib.Plan(n, batch, layout, direction, decomposition=dec, precision="fp64") as plan:
             y = from_device(plan.execute(to_device(re, im, layout)), layout)
         assert_parity(y, ref, f"FP64 N=2^{log2n} {layout} {direction} {dec}", tol=TOL64)
