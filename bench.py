@@ -12,6 +12,11 @@ bounded sample of the same workload.  The oracle leg also states the error
 of every result this benchmark measures against the FP64 oracle.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
+
+For profiling, `--only c2|c3|c4|c5` runs just one workload's launches (K of
+them after W warm-up launches, inputs in rotation where the workload has
+several) after a streaming copy of 512 MiB that calibrates byte counters, and
+prints its timing as one JSON line.
 """
 from __future__ import annotations
 
@@ -74,6 +79,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (baseline and error figures)")
     ap.add_argument("--no-extras", action="store_true", help="skip the supplementary workloads")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--only", choices=["c2", "c3", "c4", "c5"],
+                    help="profiling: run one workload's launches only (no extras, no CPU leg)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -89,6 +96,8 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.only:
+        return only(args.only, args.steps, args.warmup, fftlib, torch, workloads, dev)
     n, batch = 4096, 8192
     log(f"[bench] generating C2 inputs N={n} batch={batch}")
     re, im = workloads.c2()
@@ -249,6 +258,85 @@ def main() -> int:
         result["cpu_baseline"] = cpu_baseline(re, im, n, args.cpu_seconds, checks)
 
     print(json.dumps(result), flush=True)
+    return 0
+
+
+def only(name, steps, warmup, fftlib, torch, workloads, dev) -> int:
+    """One workload's launches alone, for a kernel trace or counters: first a
+    streaming copy of 2^26 complex64 values (512 MiB read and written, the
+    calibration of byte counters), then `warmup` + `steps` launches."""
+    cal = torch.empty(1 << 26, dtype=torch.complex64, device=dev)
+    cal_out = torch.empty_like(cal)
+    torch.cuda.synchronize()
+    fftlib.copy_device(cal, cal_out)
+    torch.cuda.synchronize()
+    del cal, cal_out
+    runs = []   # (label, callable)
+    keep = []
+    if name == "c2":
+        re, im = workloads.c2()
+        for layout in ("interleaved", "split"):
+            x = (torch.from_numpy(re).to(dev), torch.from_numpy(im).to(dev)) if layout == "split" \
+                else torch.from_numpy(workloads.interleave(re, im)).to(dev)
+            y = tuple(torch.empty_like(t) for t in x) if layout == "split" else torch.empty_like(x)
+            for direction in ("forward", "inverse"):
+                p = fftlib.Plan(4096, 8192, layout, direction)
+                keep.append(p)
+                runs.append((f"{layout}-{direction}", lambda p=p, x=x, y=y: p.execute(x, out=y)))
+    elif name == "c3":
+        n = 1 << 24
+        re, im, _, _, _ = workloads.c3(n)
+        xs = [(torch.from_numpy(re).to(dev), torch.from_numpy(im).to(dev))]
+        for k in range(2):
+            a, b = workloads.normal_complex((n,), seed=workloads.SEEDS["c3"] + 10 + k)
+            xs.append((torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)))
+        y = (torch.empty_like(xs[0][0]), torch.empty_like(xs[0][1]))
+        p = fftlib.Plan(n, 1, "split", "forward")
+        keep.append(p)
+        rot = iter(range(1 << 30))
+        runs.append(("split-forward-2^24", lambda: p.execute(xs[next(rot) % 3], out=y)))
+    elif name == "c4":
+        sizes, offsets, re, im = workloads.c4()
+        z = torch.from_numpy(workloads.interleave(re, im)).to(dev)
+        zo = torch.empty_like(z)
+        rp = fftlib.RaggedPlan(sizes, "interleaved", "forward")
+        keep.append(rp)
+        runs.append(("ragged-graph", lambda: rp.execute(z, out=zo)))
+        groups = []
+        for sz in np.unique(sizes):
+            idx = np.nonzero(sizes == sz)[0]
+            gz = torch.stack([z[int(offsets[i]):int(offsets[i] + sz)] for i in idx]).contiguous()
+            groups.append((fftlib.Plan(int(sz), len(idx), "interleaved", "forward"), gz, torch.empty_like(gz)))
+        keep.extend(g[0] for g in groups)
+
+        def per_size():
+            for q, gi, go in groups:
+                q.execute(gi, out=go)
+        runs.append(("per-size-launches", per_size))
+    else:  # c5
+        re, im, w = workloads.c5()
+        x = (torch.from_numpy(re).to(dev), torch.from_numpy(im).to(dev))
+        wt = torch.from_numpy(w).to(dev)
+        p = fftlib.Plan(re.shape[1], re.shape[0], "split", "forward")
+        keep.append(p)
+        y = p.execute(x)
+        g = (2 * wt * y[0], 2 * wt * y[1])
+        gx = (torch.empty_like(x[0]), torch.empty_like(x[1]))
+
+        def fwd_bwd():
+            p.execute(x, out=y)
+            p.backward(g, out=gx)
+        runs.append(("forward+backward", fwd_bwd))
+    out = {"only": name, "steps": steps, "warmup": warmup}
+    for label, fn in runs:
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        out[label + "_ms"] = round(_time(torch, fn, steps, warm=0), 5)
+        log(f"[bench --only {name}] {label}: {out[label + '_ms']} ms")
+    for p in keep:
+        p.close()
+    print(json.dumps(out), flush=True)
     return 0
 
 
@@ -446,6 +534,20 @@ def extras(fftlib, torch, workloads, dev, checks):
         "single_fft_hbm_frac": round(c5_bytes / (ms_k * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
     checks.append((out["autograd_1024x4096_split"], {"kind": "grad", "re": re, "im": im, "w": w, "y": grad_host}))
     del xr, xim, wt, gr, gi, y0r, y0i
+    # the same pair at batch 8192, where the two kernels take longer than the
+    # host-side work of torch's autograd engine: what the wrapper adds on the GPU
+    re8, im8 = workloads.normal_complex((8192, 4096), seed=workloads.SEEDS["c5"])
+    xr = torch.from_numpy(re8).to(dev)
+    xim = torch.from_numpy(im8).to(dev)
+    gr, gi = torch.randn_like(xr), torch.randn_like(xim)
+    plan = fftlib.Plan(4096, 8192, "split", "forward")
+    ms_a8 = _time(torch, autograd_fixed_grad, 30)
+    ms_d8 = _time(torch, direct_fixed_grad, 30)
+    plan.close()
+    out["autograd_1024x4096_split"].update({
+        "batch8192_autograd_fwd_bwd_ms": round(ms_a8, 4), "batch8192_direct_fwd_bwd_ms": round(ms_d8, 4),
+        "batch8192_wrapper_overhead_ms": round(ms_a8 - ms_d8, 4)})
+    del xr, xim, gr, gi
     # --- FP64: the same batched shape and the 2^24 transform in double -------
     for n, batch in ((4096, 8192), (1 << 24, 1)):
         re, im = workloads.normal_complex((batch, n), seed=workloads.SEEDS["c2"], dtype=np.float64)

@@ -383,8 +383,10 @@ bool real_decomposition_available(const Decomp& d, int log2n, fft_layout layout,
 
 // Real plans: single-pass shapes measured on MI355X (2^25 FP32 or 2^24 FP64
 // reals, the faster of R2C + C2R; up to 2^8 on inputs that are not cached,
-// both layouts, where the staged kernel wins), indexed by log2 N; above the
-// single-pass limit, the half length's complex pass chain.
+// both layouts, where the staged kernel wins; N = 4096 re-measured on rows
+// not in any cache: e3 g3 49.6 us against e4 g2 52-54 us for 8192 rows),
+// indexed by log2 N; above the single-pass limit, the half length's complex
+// pass chain.
 struct RealShapeChoice {
     int log2e, gmul, twreg, stg;
 };
@@ -392,7 +394,7 @@ struct RealShapeChoice {
 Decomp default_real_decomposition(int log2n, int rb) {
     static const RealShapeChoice r32[16] = {
         {4, 1, 1, 0}, {4, 1, 1, 0}, {3, 4, 1, 1}, {4, 4, 1, 1}, {3, 3, 1, 1}, {3, 3, 1, 1}, {3, 3, 1, 1},  // 2^0 .. 2^6
-        {3, 3, 1, 1}, {3, 3, 1, 1}, {3, 2, 1, 0}, {3, 2, 1, 0}, {4, 2, 1, 0}, {4, 2, 1, 0}, {3, 2, 1, 0},  // 2^7 .. 2^13
+        {3, 3, 1, 1}, {3, 3, 1, 1}, {3, 2, 1, 0}, {3, 2, 1, 0}, {4, 2, 1, 0}, {3, 3, 1, 0}, {3, 2, 1, 0},  // 2^7 .. 2^13
         {3, 8, 0, 0}, {4, 1, 0, 0},                                                                        // 2^14 .. 2^15
     };
     static const RealShapeChoice r64[15] = {
