@@ -293,9 +293,10 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout) {
     // multi-pass chains measured fastest on MI355X per layout (batches of 2^25
     // elements from inputs not in any cache; the workspace between passes is
     // read back through the memory-side cache, which favours two passes for
-    // interleaved 2^18 .. 2^20, wider tiles where split arrays halve the
-    // contiguous runs, and an in-place middle pass for three-pass chains: one
-    // workspace half instead of two, 15-25 % faster at every size)
+    // interleaved 2^18 .. 2^20, and an in-place middle pass for three-pass
+    // chains: one workspace half instead of two, 15-25 % faster at every size;
+    // split chains re-measured once their first and last passes stream the
+    // caller's arrays: the interleaved shapes win there too, 2^18 by 22 %)
     static const char* measured_il[kMaxLog2N + 1] = {
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
         nullptr, nullptr, nullptr, nullptr, nullptr,
@@ -313,11 +314,11 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout) {
     static const char* measured_sp[kMaxLog2N + 1] = {
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
         nullptr, nullptr, nullptr, nullptr, nullptr,
-        "multi:8c6,7c7",          // 2^15
-        "multi:8c6,8c6",          // 2^16
-        "multi:9c4,8c6",          // 2^17
-        "multi:10c3,8c6",         // 2^18
-        "multi:7c7,6c7i,6c7",     // 2^19
+        "multi:8c5,7c5",          // 2^15
+        "multi:8c5,8c5",          // 2^16
+        "multi:9c4,8c5",          // 2^17
+        "multi:9c4,9c4",          // 2^18
+        "multi:7c6,6c6i,6c6",     // 2^19
         "multi:7c6,7c6i,6c6",     // 2^20
         "multi:7c6,7c6i,7c6",     // 2^21
         "multi:8c6,8c5i,6c7",     // 2^22
