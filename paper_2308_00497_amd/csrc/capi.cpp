@@ -846,7 +846,7 @@ static fft_status create_impl(fft_plan* out, int64_t n, int64_t batch, fft_layou
         return fail_hip(e, "hipGetDevice");
     }
 
-    Decomp dec = fftk::default_decomposition(log2n, rb, layout);
+    Decomp dec = fftk::default_decomposition(log2n, rb, layout, batch);
     p->source = "default";
     fftk::TuneKey key = fftk::make_key(p->device, log2n, batch, layout, rb);
     Decomp cached;

@@ -235,8 +235,8 @@ static Decomp default_decomposition64(int log2n, fft_layout layout) {
     static const char* multi_sp[kMaxLog2N + 1] = {
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
         nullptr, nullptr, nullptr, nullptr,
-        "multi:7c6,7c6",          // 2^14
-        "multi:8c4,7c5",          // 2^15
+        "multi:7c4,7c4",          // 2^14
+        "multi:8c4,7c4",          // 2^15
         "multi:8c5,8c5",          // 2^16
         "multi:9c4,8c5",          // 2^17
         "multi:9c4,9c4",          // 2^18
@@ -264,7 +264,7 @@ static Decomp default_decomposition64(int log2n, fft_layout layout) {
     return d;
 }
 
-Decomp default_decomposition(int log2n, int rb, fft_layout layout) {
+Decomp default_decomposition(int log2n, int rb, fft_layout layout, int64_t batch) {
     if (rb == 8) return default_decomposition64(log2n, layout);
     Decomp d;
     if (log2n <= 0) {
@@ -288,6 +288,10 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout) {
         d.twreg = table[log2n].twreg == 1;
         d.pf = table[log2n].pf == 1;
         d.stg = table[log2n].stg == 1;
+        // N = 4096 at most 1024 transforms (every group resident at once):
+        // radix-8 stages measured faster (1024 split rows not cached:
+        // e3 15.2-15.7 us against e4 16.4-16.7 us; e4 leads from 8192 rows)
+        if (log2n == 12 && batch > 0 && batch <= 1024) d.log2e = 3;
         return d;
     }
     // multi-pass chains measured fastest on MI355X per layout (batches of 2^25

@@ -44,7 +44,9 @@ struct Decomp {
 // real number: 4 (FP32) or 8 (FP64); the multi-pass choice depends on the
 // layout of the caller's arrays.
 constexpr int kMaxLog2N = 24;
-Decomp default_decomposition(int log2n, int rb, fft_layout layout = FFT_LAYOUT_INTERLEAVED);
+// `batch` (0: unknown) refines the choice where a small batch measured
+// faster with another shape.
+Decomp default_decomposition(int log2n, int rb, fft_layout layout = FFT_LAYOUT_INTERLEAVED, int64_t batch = 0);
 
 // every decomposition the library can run for log2n (autotuner candidates)
 std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int rb);
