@@ -82,6 +82,46 @@ def test_explicit_decomposition_validation(lib):
     assert lib.fft_plan_create_explicit(ctypes.byref(h), 4096, 1, 0, -1, None) == 3
 
 
+@pytest.mark.parametrize("dec,status", [
+    (b"multi:8c5,8c5i,8c5x", 2),    # trailing garbage after the in-place flag
+    (b"multi:8c5,8c5ii,8c5", 2),    # one flag per pass
+    (b"multi:8c5i,8c5,8c5", 7),     # the first pass reads the caller's input: never in place
+    (b"multi:8c5,8c5,8c5i", 7),     # the last pass writes the caller's output: never in place
+    (b"multi:12c2i,12c2", 7),       # a two-pass chain has no middle pass
+    (b"multi:6c6,11c2i,7c7", 7),    # the last pass would read runs of 2^6 < 2^7 columns
+    (b"multi:6c4,6c4i,6c4,6c4", 7), # only the penultimate pass may run in place
+])
+def test_in_place_pass_validation(lib, dec, status):
+    """The in-place flag ("i" after a pass) parses only as one letter per pass
+    and is accepted only on the penultimate pass of three or more, with the
+    last pass's runs long enough for its tile; all checked before any device
+    call."""
+    h = ctypes.c_void_p()
+    assert lib.fft_plan_create_explicit(ctypes.byref(h), 1 << 24, 1, 0, -1, dec) == status, dec
+    if status == 7:
+        # the same chain without the flag passes validation (it then fails, or
+        # succeeds, only at the first device call): the flag is what is refused
+        plain = dec.replace(b"i,", b",").replace(b"i", b"")
+        assert lib.fft_plan_create_explicit(ctypes.byref(h), 1 << 24, 1, 0, -1, plain) not in (2, 7), plain
+        if h.value:
+            lib.fft_plan_destroy(h)
+
+
+def test_in_place_chains_round_trip_as_text(fftlib):
+    """Every candidate, the in-place chains included, prints back as it
+    parses, and the three-pass defaults carry the flag on the middle pass."""
+    for log2n in (19, 21, 24):
+        for layout in ("interleaved", "split"):
+            q = fftlib.query_decomposition(1 << log2n, layout, "fp32")
+            ip = [d for d in q["candidates"] if "i," in d]
+            assert ip, (log2n, layout)
+            for d in ip:
+                parts = d.split(":")[1].split(",")
+                assert len(parts) >= 3 and parts[-2].endswith("i") and not parts[-1].endswith("i")
+            if q["default"].count(",") == 2:
+                assert q["default"].split(",")[1].endswith("i"), q["default"]
+
+
 def test_prefetch_decomposition_strings(lib, fftlib):
     """":p1" selects the prefetching single-pass kernel; it exists only where
     compiled (FP32 2^13, 2^14; FP64 2^12, 2^13) and ":p0" is not a spelling."""
