@@ -57,13 +57,15 @@ hipError_t launch_gen_pow64(double2* dst, int log2M, int64_t step, int64_t count
 }
 
 // Streaming copy: each thread moves four 16-byte vectors spaced one
-// workgroup-width apart (a 4 KiB block per workgroup) with nontemporal loads
-// and stores - the same access style as the FFT kernels; a grid-stride loop
-// finishes the remainder.
+// workgroup-width apart (a 4 KiB block per workgroup step) with nontemporal
+// loads and stores - the same access style as the FFT kernels; a grid-stride
+// loop finishes the remainder.
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) k_copy16(const f32x4_t* __restrict__ src, f32x4_t* __restrict__ dst,
                                                 int64_t n16) {
+    // persistent: workgroup w copies 4 KiB blocks w, w + grid, ... (four
+    // 16-byte streaming loads per thread, then four streaming stores)
     const int64_t full = n16 / 1024;  // complete 4 KiB blocks
     const int64_t tid = threadIdx.x;
     for (int64_t blk = blockIdx.x; blk < full; blk += gridDim.x) {
@@ -81,8 +83,17 @@ __global__ void __launch_bounds__(256) k_copy16(const f32x4_t* __restrict__ src,
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
     const int64_t n16 = static_cast<int64_t>(bytes / 16);
     if (n16 == 0) return hipSuccess;
+    // one workgroup per compute unit measured fastest (256 MiB: 6.34 TB/s,
+    // against 6.08 TB/s with one workgroup per 4 KiB block and 6.23-6.29 TB/s
+    // with 4-16 per CU)
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();  // only the failed query's own error
+        cus = 256;
+    }
     int64_t blocks = (n16 + 1023) / 1024;
-    if (blocks > 0x7fffffff) blocks = 0x7fffffff;
+    if (blocks > cus) blocks = cus;
     hipLaunchKernelGGL(k_copy16, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
                        static_cast<const f32x4_t*>(src), static_cast<f32x4_t*>(dst), n16);
     return hipGetLastError();

@@ -258,7 +258,7 @@ def test_alloc_failure_is_reported():
     assert lines[1] == "0 True", r.stdout + r.stderr
 
 
-@pytest.mark.parametrize("nbytes", [16, 4096, 4096 * 3 + 48, 1 << 24])
+@pytest.mark.parametrize("nbytes", [16, 4096, 4096 * 3 + 48, 1 << 24, (1 << 24) + 4096 * 5 + 32])
 def test_copy_device(fftlib, nbytes):
     """The streaming copy entry point (the benchmark's HBM ceiling) copies exactly."""
     src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
