@@ -82,6 +82,35 @@ def test_every_multi_pass_variant(fftlib, log2n, layout):
 
 
 @pytest.mark.parametrize("layout", ["interleaved", "split"])
+@pytest.mark.parametrize("chain,batch", [("multi:6c6,6c6,6c6", 5), ("multi:8c5,6c6,5c8", 3),
+                                         ("multi:8c5,7c5,6c6", 2), ("multi:8c5,8c5,8c5", 1),
+                                         ("multi:6c4,6c4,6c4,6c4", 1)])
+def test_in_place_middle_pass_is_bitwise_stockham(fftlib, chain, batch, layout):
+    """A chain whose penultimate pass writes over its own input differs from
+    the Stockham chain of the same lengths only in addresses (the last pass
+    reads the permuted layout): both directions must give bit-identical
+    results, and the oracle's within the tolerance."""
+    parts = chain.split(":")[1].split(",")
+    parts[-2] += "i"
+    twin = "multi:" + ",".join(parts)
+    log2n = sum(int(p.split("c")[0]) for p in parts)
+    n = 1 << log2n
+    re, im = workloads.normal_complex((batch, n), seed=4100 + log2n)
+    for direction in ("forward", "inverse"):
+        ys = []
+        for dec in (chain, twin):
+            with fftlib.Plan(n, batch, layout, direction, decomposition=dec) as plan:
+                y = plan.execute(to_device(re, im, layout))
+                torch.cuda.synchronize()
+                ys.append(torch.cat(y) if layout == "split" else y)
+                if dec == twin:
+                    assert plan.workspace_bytes == n * batch * 8 * (1 if len(parts) == 3 else 2)
+        assert torch.equal(ys[0], ys[1]), f"{twin} {layout} {direction} differs from {chain}"
+        assert_parity(from_device(ys[1].chunk(2) if layout == "split" else ys[1], layout),
+                      oracle_ref(re, im, direction), f"{twin} {layout} {direction}")
+
+
+@pytest.mark.parametrize("layout", ["interleaved", "split"])
 @pytest.mark.parametrize("log2n", [0, 4, 10, 12, 14, 16, 20])
 def test_in_place(fftlib, log2n, layout):
     n = 1 << log2n
