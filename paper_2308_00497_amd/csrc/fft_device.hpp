@@ -336,8 +336,11 @@ struct TwLast {
 // ones between t-fast.  On entry v[m] holds input element t + T*m of sub-FFT
 // g under the first mapping; on exit v[m] holds output element t + T*m of
 // sub-FFT g under the last mapping.  GS is the LDS stride between groups.
+// HALF: each exchange passes the real parts and then the imaginary parts
+// through a buffer of G*GS reals (half the LDS of a complex exchange, two
+// more barriers per exchange), so more workgroups fit on a compute unit.
 // ---------------------------------------------------------------------------
-template <class SC, int G, int GS, bool FIRST_GFAST, bool LAST_GFAST, bool WAVE>
+template <class SC, int G, int GS, bool FIRST_GFAST, bool LAST_GFAST, bool WAVE, bool HALF = false>
 struct Engine {
     static constexpr int E = SC::E;
     static constexpr int T = SC::T;
@@ -426,12 +429,37 @@ struct Engine {
     __device__ __forceinline__ static void stage(V (&v)[E], V* lds, const TW& tw, int tid) {
         int g, t;
         map<S>(tid, g, t);
-        if constexpr (S > 0) read(v, g, t, lds);
         compute<S>(v, t, tw);
         if constexpr (S < NST - 1) {
-            stage_sync<WAVE>();  // every thread has finished reading the previous exchange
-            write<S>(v, g, t, lds);
-            stage_sync<WAVE>();  // this exchange is complete
+            int g1, t1;
+            map<S + 1>(tid, g1, t1);
+            if constexpr (HALF) {
+                using RV = typename RealOf<V>::type;
+                RV* h = reinterpret_cast<RV*>(lds);
+                RV part[E];
+#pragma unroll
+                for (int m = 0; m < E; ++m) part[m] = v[m].x;
+                stage_sync<WAVE>();  // every thread has finished reading the previous exchange
+                write<S>(part, g, t, h);
+                stage_sync<WAVE>();  // the real parts are exchanged
+                read(part, g1, t1, h);
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    v[m].x = part[m];  // next stage's layout
+                    part[m] = v[m].y;  // still this stage's layout
+                }
+                stage_sync<WAVE>();  // every thread has read its real parts
+                write<S>(part, g, t, h);
+                stage_sync<WAVE>();  // the imaginary parts are exchanged
+                read(part, g1, t1, h);
+#pragma unroll
+                for (int m = 0; m < E; ++m) v[m].y = part[m];
+            } else {
+                stage_sync<WAVE>();  // every thread has finished reading the previous exchange
+                write<S>(v, g, t, lds);
+                stage_sync<WAVE>();  // this exchange is complete
+                read(v, g1, t1, lds);
+            }
             stage<S + 1>(v, lds, tw, tid);
         }
     }

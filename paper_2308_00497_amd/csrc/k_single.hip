@@ -35,6 +35,14 @@ static const SingleKernel kSingle[] = {
     single_entry<float, 14, 4, 256, true, false, false, true>(),
     single_entry<float, 13, 4, 256, false, false, true, true>(), single_entry<float, 13, 4, 256, false, true, true, true>(),
     single_entry<float, 13, 4, 256, true, false, true, true>(),
+    // exchanges one real part at a time: half the LDS, so more workgroups per
+    // CU at the sizes LDS limits (2^12: 4 -> 8, 2^13: 2 -> 4 by LDS)
+#define FFT_SH(n, e, r)                                                                                     \
+    single_entry<float, n, e, 256, false, false, r, false, false, true>(),                                  \
+        single_entry<float, n, e, 256, false, true, r, false, false, true>(),                               \
+        single_entry<float, n, e, 256, true, false, r, false, false, true>()
+    FFT_SH(12, 4, true), FFT_SH(13, 4, true), FFT_SH(13, 4, false), FFT_SH(14, 4, false),
+#undef FFT_SH
     // small transforms (each inside one wavefront): contiguous loads and
     // stores staged through LDS
 #define FFT_ST(n, e)                                                                                        \

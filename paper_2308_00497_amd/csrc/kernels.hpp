@@ -51,11 +51,13 @@ struct SingleShape {
     static constexpr bool WAVE = SC::T <= 64;
 };
 
-// LDS elements of a single-pass workgroup: the engine's exchange, or with
-// staging the whole group (every group padded as in the engine)
-template <int LOG2N, int LOG2E, int WGT, bool STG>
+// LDS elements (complex) of a single-pass workgroup: the engine's exchange,
+// with staging the whole group (every group padded as in the engine), or with
+// HALF exchanges (one real part at a time) half the engine's
+template <int LOG2N, int LOG2E, int WGT, bool STG, bool HALF = false>
 constexpr int single_lds() {
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
+    if constexpr (HALF) return (SH::LDS + 1) / 2;
     return STG && SH::G * SH::GS > SH::LDS ? SH::G * SH::GS : SH::LDS;
 }
 
@@ -71,9 +73,11 @@ constexpr int single_lds() {
 // inside one wavefront) a wavefront's transforms, which are contiguous in
 // memory, are read and written as one contiguous run (lane l takes elements
 // l, l + 64, ...) and staged through LDS into the engine's layout, instead of
-// each lane reading its own points at stride T.
+// each lane reading its own points at stride T.  With HALF the stages exchange
+// real and imaginary parts one after the other through half the LDS, so more
+// workgroups fit on a compute unit where LDS limits them.
 template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false,
-          bool STG = false>
+          bool STG = false, bool HALF = false>
 __global__ void __launch_bounds__((SingleShape<LOG2N, LOG2E, WGT>::THREADS))
 k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw, int64_t batch) {
     using V = cplx_t<R>;
@@ -81,9 +85,10 @@ k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ t
     using SC = typename SH::SC;
     constexpr int E = SC::E, T = SC::T, L = SC::L, G = SH::G;
     static_assert(!(STG && PF), "staging and prefetching are separate variants");
+    static_assert(!(STG && HALF), "staged transforms use the complex exchange");
     static_assert(!STG || (SH::WAVE && (64 % T) == 0 && SH::THREADS % 64 == 0),
                   "staging needs every transform inside one wavefront");
-    __shared__ V lds[single_lds<LOG2N, LOG2E, WGT, STG>()];
+    __shared__ V lds[single_lds<LOG2N, LOG2E, WGT, STG, HALF>()];
 
     const int tid = threadIdx.x;
     TwReg<SC, V> twr(tw);
@@ -186,8 +191,8 @@ k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ t
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = c_zero<V>();
         }
-        if constexpr (TWREG) Engine<SC, G, SH::GS, false, false, SH::WAVE>::run(v, lds, twr, tidl);
-        else Engine<SC, G, SH::GS, false, false, SH::WAVE>::run(v, lds, TwMem<SC, V>(twl), tidl);
+        if constexpr (TWREG) Engine<SC, G, SH::GS, false, false, SH::WAVE, HALF>::run(v, lds, twr, tidl);
+        else Engine<SC, G, SH::GS, false, false, SH::WAVE, HALF>::run(v, lds, TwMem<SC, V>(twl), tidl);
         if (active) {
 #pragma unroll
             for (int m = 0; m < E; ++m) gstore_nt<SPLIT>(oa, ob, base + T * m, swap_if<SWAP>(v[m]));
@@ -195,14 +200,15 @@ k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ t
     }
 }
 
-template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false, bool STG = false>
+template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false, bool STG = false,
+          bool HALF = false>
 hipError_t launch_single(const void* ia, const void* ib, void* oa, void* ob, const void* tw, int64_t batch, int grid,
                          hipStream_t s) {
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
     const int64_t groups = (batch + SH::G - 1) / SH::G;
     const int64_t blocks = groups < grid ? groups : grid;
     if (blocks < 1) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG>), dim3(static_cast<unsigned>(blocks)),
+    hipLaunchKernelGGL((k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG, HALF>), dim3(static_cast<unsigned>(blocks)),
                        dim3(SH::THREADS), 0, s, static_cast<const R*>(ia), static_cast<const R*>(ib),
                        static_cast<R*>(oa), static_cast<R*>(ob), static_cast<const cplx_t<R>*>(tw), batch);
     return hipGetLastError();
@@ -224,7 +230,8 @@ EngineInfo engine_info() {
     return e;
 }
 
-template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false, bool STG = false>
+template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false, bool STG = false,
+          bool HALF = false>
 SingleKernel single_entry() {
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
     SingleKernel k{};
@@ -237,12 +244,13 @@ SingleKernel single_entry() {
     k.twreg = TWREG;
     k.pf = PF;
     k.stg = STG;
-    k.fn = &launch_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG>;
-    k.kernel = reinterpret_cast<const void*>(&k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG>);
+    k.half = HALF;
+    k.fn = &launch_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG, HALF>;
+    k.kernel = reinterpret_cast<const void*>(&k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG, HALF>);
     k.eng = engine_info<typename SH::SC>();
     k.threads = SH::THREADS;
     k.per_wg = SH::G;
-    k.lds_bytes = single_lds<LOG2N, LOG2E, WGT, STG>() * sizeof(cplx_t<R>);
+    k.lds_bytes = single_lds<LOG2N, LOG2E, WGT, STG, HALF>() * sizeof(cplx_t<R>);
     return k;
 }
 

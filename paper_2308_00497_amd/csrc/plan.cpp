@@ -28,7 +28,7 @@ std::string Decomp::str() const {
             return "copy";
         case SINGLE:
             snprintf(buf, sizeof buf, "single:e%d:w%d:g%d:r%d%s", log2e, wgt, gmul, twreg ? 1 : 0,
-                     pf ? ":p1" : (stg ? ":s1" : ""));
+                     pf ? ":p1" : (stg ? ":s1" : (half ? ":h1" : "")));
             return buf;
         case OPS:
             snprintf(buf, sizeof buf, "ops:r%d", log2r);
@@ -54,10 +54,10 @@ bool Decomp::parse(const std::string& s, Decomp* out) {
     }
     int e = 0, w = 0, g = 0, r = 0, used = 0;
     if (sscanf(s.c_str(), "single:e%d:w%d:g%d:r%d%n", &e, &w, &g, &r, &used) == 4) {
-        // optional variant: ":p1" prefetching, ":s1" staged (":p0"/":s0" are
-        // spelled by leaving the field out)
+        // optional variant: ":p1" prefetching, ":s1" staged, ":h1" half-width
+        // exchanges (":p0"/":s0"/":h0" are spelled by leaving the field out)
         const std::string rest = s.substr(used);
-        if (!rest.empty() && rest != ":p1" && rest != ":s1") return false;
+        if (!rest.empty() && rest != ":p1" && rest != ":s1" && rest != ":h1") return false;
         if (g < 1 || g > 64 || (r != 0 && r != 1)) return false;
         d.kind = SINGLE;
         d.log2e = e;
@@ -66,6 +66,7 @@ bool Decomp::parse(const std::string& s, Decomp* out) {
         d.twreg = r == 1;
         d.pf = rest == ":p1";
         d.stg = rest == ":s1";
+        d.half = rest == ":h1";
         *out = d;
         return true;
     }
@@ -99,13 +100,13 @@ bool Decomp::parse(const std::string& s, Decomp* out) {
 }
 
 const SingleKernel* find_single(int rb, int log2n, int log2e, int wgt, bool split, bool swap, bool twreg, bool pf,
-                                bool stg) {
+                                bool stg, bool half) {
     int cnt = 0;
     const SingleKernel* t = rb == 8 ? single_kernels64(&cnt) : single_kernels(&cnt);
     const int le = log2e < log2n ? log2e : log2n;
     for (int i = 0; i < cnt; ++i)
         if (t[i].log2n == log2n && t[i].log2e == le && t[i].wgt == wgt && t[i].split == split && t[i].swap == swap &&
-            t[i].twreg == twreg && t[i].pf == pf && t[i].stg == stg)
+            t[i].twreg == twreg && t[i].pf == pf && t[i].stg == stg && t[i].half == half)
             return &t[i];
     return nullptr;
 }
@@ -128,7 +129,7 @@ const PassKernel* pass_kernel_for(int rb, int log2l, int log2c, size_t p, size_t
 }
 
 const SingleKernel* single_kernel_for(int rb, int log2n, const Decomp& d, bool split, bool inverse) {
-    return find_single(rb, log2n, d.log2e, d.wgt, split, inverse && !split, d.twreg, d.pf, d.stg);
+    return find_single(rb, log2n, d.log2e, d.wgt, split, inverse && !split, d.twreg, d.pf, d.stg, d.half);
 }
 
 // column tile for a sub-FFT length: the widest compiled one up to 128-byte
@@ -275,11 +276,13 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout, int64_t batch
         // single-pass shapes measured fastest on MI355X (batches of 2^25
         // elements from inputs that are not cached, the mean over both
         // layouts); up to 2^7 the staged kernel, whose loads and stores are
-        // contiguous runs; the autotuner refines them per device
-        static const struct { int log2e, gmul, twreg, pf, stg; } table[15] = {
-            {4, 1, 1, 0, 0}, {4, 4, 1, 0, 1}, {4, 3, 1, 0, 1}, {4, 2, 1, 0, 1}, {4, 8, 1, 0, 1},  // 2^0 .. 2^4
-            {4, 8, 1, 0, 1}, {4, 8, 1, 0, 1}, {4, 8, 1, 0, 1}, {3, 2, 1, 0, 0}, {3, 2, 1, 0, 0},  // 2^5 .. 2^9
-            {3, 2, 1, 0, 0}, {3, 2, 1, 0, 0}, {4, 2, 1, 0, 0}, {4, 4, 1, 0, 0}, {4, 4, 0, 1, 0},  // 2^10 .. 2^14
+        // contiguous runs; at 2^14 half-width exchanges (two workgroups per
+        // CU instead of one: 151.5 -> 136.3 us interleaved, 149.5 -> 142.2 us
+        // split); the autotuner refines them per device
+        static const struct { int log2e, gmul, twreg, pf, stg, half; } table[15] = {
+            {4, 1, 1, 0, 0, 0}, {4, 4, 1, 0, 1, 0}, {4, 3, 1, 0, 1, 0}, {4, 2, 1, 0, 1, 0}, {4, 8, 1, 0, 1, 0},  // 2^0 .. 2^4
+            {4, 8, 1, 0, 1, 0}, {4, 8, 1, 0, 1, 0}, {4, 8, 1, 0, 1, 0}, {3, 2, 1, 0, 0, 0}, {3, 2, 1, 0, 0, 0},  // 2^5 .. 2^9
+            {3, 2, 1, 0, 0, 0}, {3, 2, 1, 0, 0, 0}, {4, 2, 1, 0, 0, 0}, {4, 4, 1, 0, 0, 0}, {4, 8, 0, 0, 0, 1},  // 2^10 .. 2^14
         };
         d.kind = Decomp::SINGLE;
         d.log2e = table[log2n].log2e;
@@ -288,6 +291,7 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout, int64_t batch
         d.twreg = table[log2n].twreg == 1;
         d.pf = table[log2n].pf == 1;
         d.stg = table[log2n].stg == 1;
+        d.half = table[log2n].half == 1;
         // N = 4096 at most 1024 transforms (every group resident at once):
         // radix-8 stages measured faster (1024 split rows not cached:
         // e3 15.2-15.7 us against e4 16.4-16.7 us; e4 leads from 8192 rows)
@@ -362,7 +366,8 @@ bool real_decomposition_available(const Decomp& d, int log2n, fft_layout layout,
         case Decomp::COPY:
             return log2h == 0;
         case Decomp::SINGLE:
-            return log2h >= 1 && !d.pf && find_real(rb, log2h, d.log2e, d.wgt, c2r, split, d.twreg, d.stg) != nullptr;
+            return log2h >= 1 && !d.pf && !d.half &&
+                   find_real(rb, log2h, d.log2e, d.wgt, c2r, split, d.twreg, d.stg) != nullptr;
         case Decomp::MULTI: {
             // the half-length chain runs on interleaved data in both directions
             int sum = 0;
@@ -450,9 +455,9 @@ std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int r
     for (int e : {4, 3})
         for (int w : {256, 64})
             for (int r : {1, 0})
-                for (int var : {0, 1, 2}) {  // plain, prefetching, staged
-                    const bool pf = var == 1, stg = var == 2;
-                    const SingleKernel* k = find_single(rb, log2n, e, w, false, false, r == 1, pf, stg);
+                for (int var : {0, 1, 2, 3}) {  // plain, prefetching, staged, half-width exchanges
+                    const bool pf = var == 1, stg = var == 2, half = var == 3;
+                    const SingleKernel* k = find_single(rb, log2n, e, w, false, false, r == 1, pf, stg, half);
                     if (!k) continue;
                     bool dup = false;
                     for (auto* o : shapes) dup |= (o == k);
@@ -467,6 +472,7 @@ std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int r
                         d.twreg = r == 1;
                         d.pf = pf;
                         d.stg = stg;
+                        d.half = half;
                         if (decomposition_available(d, log2n, layout, rb)) out.push_back(d);
                     }
                 }

@@ -30,12 +30,13 @@ struct Decomp {
     bool twreg = true;
     bool pf = false;  // single: the next transform's loads issued before the current one's stages
     bool stg = false; // single: contiguous loads/stores staged through LDS (small transforms)
+    bool half = false; // single: stage exchanges one real part at a time (half the LDS)
     std::vector<int> log2l;
     std::vector<int> log2c;
     std::vector<int> inplace;  // per pass: 1 = writes over its own input ("i" suffix)
     bool in_place(size_t p) const { return p < inplace.size() && inplace[p] != 0; }
 
-    std::string str() const;  // "copy" | "single:e4:w256:g2:r1[:p1|:s1]" | "multi:8c4,8c4i,8c4" | "ops:r4"
+    std::string str() const;  // "copy" | "single:e4:w256:g2:r1[:p1|:s1|:h1]" | "multi:8c4,8c4i,8c4" | "ops:r4"
     static bool parse(const std::string& s, Decomp* out);
     bool operator==(const Decomp& o) const { return str() == o.str(); }
 };
@@ -53,7 +54,7 @@ std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int r
 
 // kernel lookup; nullptr when no such instance was compiled
 const SingleKernel* find_single(int rb, int log2n, int log2e, int wgt, bool split, bool swap, bool twreg,
-                                bool pf = false, bool stg = false);
+                                bool pf = false, bool stg = false, bool half = false);
 const PassKernel* find_pass(int rb, int log2l, int log2c, bool first, bool split_in, bool split_out, bool swap_in,
                             bool swap_out);
 

@@ -39,6 +39,7 @@ struct SingleKernel {
     bool twreg;     // stage twiddles held in registers
     bool pf;        // next transform's loads issued before the current one's stages
     bool stg;       // small transforms: contiguous loads/stores staged through LDS
+    bool half;      // stage exchanges one real part at a time (half the LDS)
     single_fn fn;
     const void* kernel;  // the __global__ function (occupancy queries)
     EngineInfo eng;

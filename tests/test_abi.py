@@ -132,9 +132,26 @@ def test_prefetch_decomposition_strings(lib, fftlib):
     assert ex(ctypes.byref(h), 4096, 1, 0, -1, 0, b"single:e4:w256:g2:r1:p1") == 7
     assert ex(ctypes.byref(h), 1 << 14, 1, 0, -1, 1, b"single:e4:w256:g1:r0:p1") == 7   # FP64 has no 2^14
     q32 = fftlib.query_decomposition(1 << 14, "split", "fp32")
-    assert q32["default"].endswith(":p1") and any(c.endswith(":p1") for c in q32["candidates"])
+    assert any(c.endswith(":p1") for c in q32["candidates"])
     q64 = fftlib.query_decomposition(1 << 12, "interleaved", "fp64")
     assert q64["default"] == "single:e3:w256:g1:r1:p1"
+
+
+def test_half_exchange_decomposition_strings(lib, fftlib):
+    """":h1" selects the single-pass kernel whose stages exchange one real part
+    at a time; it exists only where compiled (FP32 2^12 .. 2^14), is not
+    combined with another variant, and is the 2^14 default."""
+    h = ctypes.c_void_p()
+    ex = lib.fft_plan_create_ex
+    assert ex(ctypes.byref(h), 4096, 1, 0, -1, 0, b"single:e4:w256:g2:r1:h2") == 2
+    assert ex(ctypes.byref(h), 4096, 1, 0, -1, 0, b"single:e4:w256:g2:r1:h1:p1") == 2
+    assert ex(ctypes.byref(h), 1024, 1, 0, -1, 0, b"single:e4:w256:g2:r1:h1") == 7      # not compiled at 2^10
+    assert ex(ctypes.byref(h), 1 << 13, 1, 0, -1, 1, b"single:e4:w256:g2:r0:h1") == 7   # nor in FP64
+    for layout in ("interleaved", "split"):
+        q = fftlib.query_decomposition(1 << 14, layout, "fp32")
+        assert q["default"] == "single:e4:w256:g8:r0:h1", q["default"]
+        hs = [c for c in q["candidates"] if c.endswith(":h1")]
+        assert hs and all(c.startswith("single:e4:w256:") for c in hs)
 
 
 def test_staged_decomposition_strings(lib, fftlib):
