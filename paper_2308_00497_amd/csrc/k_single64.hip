@@ -33,6 +33,14 @@ static const SingleKernel kSingle64[] = {
     single_entry<double, 13, 4, 256, true, false, false, true>(),
     single_entry<double, 12, 3, 256, false, false, true, true>(), single_entry<double, 12, 3, 256, false, true, true, true>(),
     single_entry<double, 12, 3, 256, true, false, true, true>(),
+    // exchanges one real part at a time: half the LDS, twice the workgroups
+    // per CU where LDS limits them
+#define FFT_DH(n, e, r)                                                                                     \
+    single_entry<double, n, e, 256, false, false, r, false, false, true>(),                                 \
+        single_entry<double, n, e, 256, false, true, r, false, false, true>(),                              \
+        single_entry<double, n, e, 256, true, false, r, false, false, true>()
+    FFT_DH(12, 3, true), FFT_DH(12, 3, false), FFT_DH(12, 4, false), FFT_DH(13, 4, false), FFT_DH(13, 3, false),
+#undef FFT_DH
 };
 
 #undef FFT_D

@@ -213,10 +213,12 @@ static std::vector<int> even_split(int log2n, int parts) {
 // layout, timed on inputs that are not in any cache; three-pass chains run
 // their middle pass in place (2^24 split: 351 -> 287 us)
 static Decomp default_decomposition64(int log2n, fft_layout layout) {
-    static const struct { int log2e, wgt, gmul, twreg, pf; } single[14] = {
-        {4, 256, 1, 1, 0}, {4, 256, 2, 0, 0}, {4, 64, 3, 0, 0}, {4, 64, 1, 0, 0}, {3, 256, 8, 1, 0},  // 2^0 .. 2^4
-        {3, 256, 8, 1, 0}, {3, 256, 1, 1, 0}, {3, 64, 3, 1, 0}, {3, 64, 3, 1, 0}, {3, 64, 4, 1, 0},   // 2^5 .. 2^9
-        {3, 256, 2, 1, 0}, {3, 256, 2, 1, 0}, {3, 256, 1, 1, 1}, {4, 256, 1, 0, 1},                   // 2^10 .. 2^13
+    // 2^13: half-width exchanges (two workgroups per CU instead of one;
+    // 2^25 elements: interleaved 269 -> 256 us, split 279 -> 280 us)
+    static const struct { int log2e, wgt, gmul, twreg, pf, half; } single[14] = {
+        {4, 256, 1, 1, 0, 0}, {4, 256, 2, 0, 0, 0}, {4, 64, 3, 0, 0, 0}, {4, 64, 1, 0, 0, 0}, {3, 256, 8, 1, 0, 0},
+        {3, 256, 8, 1, 0, 0}, {3, 256, 1, 1, 0, 0}, {3, 64, 3, 1, 0, 0}, {3, 64, 3, 1, 0, 0}, {3, 64, 4, 1, 0, 0},
+        {3, 256, 2, 1, 0, 0}, {3, 256, 2, 1, 0, 0}, {3, 256, 1, 1, 1, 0}, {4, 256, 3, 0, 0, 1},  // 2^10 .. 2^13
     };
     static const char* multi_il[kMaxLog2N + 1] = {
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
@@ -259,6 +261,7 @@ static Decomp default_decomposition64(int log2n, fft_layout layout) {
         d.gmul = single[log2n].gmul;
         d.twreg = single[log2n].twreg == 1;
         d.pf = single[log2n].pf == 1;
+        d.half = single[log2n].half == 1;
     } else {
         Decomp::parse(multi[log2n], &d);
     }

@@ -139,14 +139,14 @@ def test_prefetch_decomposition_strings(lib, fftlib):
 
 def test_half_exchange_decomposition_strings(lib, fftlib):
     """":h1" selects the single-pass kernel whose stages exchange one real part
-    at a time; it exists only where compiled (FP32 2^12 .. 2^14), is not
-    combined with another variant, and is the 2^14 default."""
+    at a time; it exists only where compiled (FP32 2^12 .. 2^14, FP64 2^12 and
+    2^13), is not combined with another variant, and is the FP32 2^14 default."""
     h = ctypes.c_void_p()
     ex = lib.fft_plan_create_ex
     assert ex(ctypes.byref(h), 4096, 1, 0, -1, 0, b"single:e4:w256:g2:r1:h2") == 2
     assert ex(ctypes.byref(h), 4096, 1, 0, -1, 0, b"single:e4:w256:g2:r1:h1:p1") == 2
     assert ex(ctypes.byref(h), 1024, 1, 0, -1, 0, b"single:e4:w256:g2:r1:h1") == 7      # not compiled at 2^10
-    assert ex(ctypes.byref(h), 1 << 13, 1, 0, -1, 1, b"single:e4:w256:g2:r0:h1") == 7   # nor in FP64
+    assert ex(ctypes.byref(h), 1 << 11, 1, 0, -1, 1, b"single:e3:w256:g2:r0:h1") == 7   # nor FP64 2^11
     for layout in ("interleaved", "split"):
         q = fftlib.query_decomposition(1 << 14, layout, "fp32")
         assert q["default"] == "single:e4:w256:g8:r0:h1", q["default"]
