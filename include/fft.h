@@ -219,7 +219,7 @@ fft_status fft_plan_create_ragged(fft_plan *out, const int64_t *sizes,
                                   fft_direction dir);
 
 /* fft_plan_create_ragged with an explicit configuration (the autotuner's
- * choices, bypassing cache and tuning): "ragged:p<P>:g<G>:o<O>[:w<W>]" with
+ * choices, bypassing cache and tuning): "ragged:p<P>:g<G>:o<O>[:w<W>][:s<S>]" with
  *   P  longest pass sub-FFT of the multi-pass transforms, 2^6 .. 2^8 (6..8)
  *   G  persistent workgroups per level, in eighths of the resident maximum (1..8)
  *   O  1: smallest multi-pass transforms first within a level, 0: largest
@@ -227,6 +227,9 @@ fft_status fft_plan_create_ragged(fft_plan *out, const int64_t *sizes,
  *      pass p runs in level g + p, so each level reads what the previous one
  *      wrote while it can still be cached; the workspace is a ring of two
  *      group-sized slots.  Absent: every pass p in level p.
+ *   S  largest size computed as one single-pass tile: 14 (2^14 on one
+ *      workgroup, 32 points per thread) or 13 (2^14 then takes two passes).
+ *      Absent: 14.
  * config NULL behaves as fft_plan_create_ragged.  A string that does not
  * parse is FFT_ERR_INVALID_ARG. */
 fft_status fft_plan_create_ragged_ex(fft_plan *out, const int64_t *sizes,

@@ -209,7 +209,7 @@ class PlanND(_PlanBase):
 class RaggedPlan(_PlanBase):
     """Transforms of the given power-of-two sizes packed back to back, one graph launch.
 
-    `config` ("ragged:p8:g8:o0[:w64]") fixes the plan's configuration instead
+    `config` ("ragged:p8:g8:o0[:w64][:s13]") fixes the plan's configuration instead
     of the cached, default or autotuned one."""
 
     def __init__(self, sizes, layout: str = "interleaved", direction: str = "forward", config: str | None = None):

@@ -162,6 +162,80 @@ template <> struct Dft<16> {
     }
 };
 
+// cos(k pi / 16), k = 0 .. 8, correctly rounded in each precision
+template <class R> struct K32;
+#define FFTK_COS_PI16(T, s)                                                                                       \
+    template <> struct K32<T> {                                                                                   \
+        __host__ __device__ static constexpr T c(int k) {                                                         \
+            return k == 0 ? T(1) : k == 1 ? 0.980785280403230449126##s : k == 2 ? 0.923879532511286756128##s      \
+                 : k == 3 ? 0.831469612302545237079##s : k == 4 ? 0.707106781186547524401##s                         \
+                 : k == 5 ? 0.555570233019602224743##s : k == 6 ? 0.382683432365089771728##s                         \
+                 : k == 7 ? 0.195090322016128267848##s : T(0);                                                       \
+        }                                                                                                         \
+    };
+FFTK_COS_PI16(float, f)
+FFTK_COS_PI16(double, )
+#undef FFTK_COS_PI16
+
+// cos(m pi / 16) for any integer m, from the first octant by symmetry
+template <class R>
+__host__ __device__ constexpr R cos_pi16(int m) {
+    m = ((m % 32) + 32) % 32;
+    if (m > 16) m = 32 - m;
+    return m > 8 ? -K32<R>::c(16 - m) : K32<R>::c(m);
+}
+
+// a * w_32^M, w_32 = exp(-2 pi i / 32) = (cos(pi/16), -sin(pi/16)); the
+// multiples of w_8 take the cheaper forms
+template <int M, class V>
+__device__ __forceinline__ V c_mul_w32(V a) {
+    using R = typename RealOf<V>::type;
+    constexpr int m = M % 32;
+    if constexpr (m == 0) return a;
+    else if constexpr (m == 4) return c_mul_w8_1(a);
+    else if constexpr (m == 8) return c_mul_mi(a);
+    else if constexpr (m == 12) return c_mul_w8_3(a);
+    else if constexpr (m == 16) return cmk(-a.x, -a.y);
+    else {
+        constexpr R c = cos_pi16<R>(m), s = cos_pi16<R>(8 - m);  // sin(m pi/16) = cos((8 - m) pi/16)
+        return c_mul(a, cmk(c, -s));
+    }
+}
+
+template <> struct Dft<32> {
+    template <int N2, int K1, class V>
+    __device__ __forceinline__ static void tw(V* v) {
+        v[N2 + 4 * K1] = c_mul_w32<N2 * K1>(v[N2 + 4 * K1]);
+        if constexpr (K1 + 1 < 8) tw<N2, K1 + 1>(v);
+    }
+    template <class V> __device__ __forceinline__ static void run(V* v) {
+        // K = 4 sub-sequences x[4 n1 + n2], DFT_8 over n1 -> v[n2 + 4 k1] = A[n2][k1]
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+            V u[8];
+#pragma unroll
+            for (int n1 = 0; n1 < 8; ++n1) u[n1] = v[n2 + 4 * n1];
+            Dft<8>::run(u);
+#pragma unroll
+            for (int k1 = 0; k1 < 8; ++k1) v[n2 + 4 * k1] = u[k1];
+        }
+        // twiddle w_32^(n2 k1)
+        tw<1, 1>(v);
+        tw<2, 1>(v);
+        tw<3, 1>(v);
+        // DFT_4 across n2 for each k1 -> X[k1 + 8 k2] sits in v[4 k1 + k2]
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+        V o[32];
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1)
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) o[k1 + 8 * k2] = v[4 * k1 + k2];
+#pragma unroll
+        for (int i = 0; i < 32; ++i) v[i] = o[i];
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Stage schedule of an L-point sub-FFT with E elements per thread.
 // Stages of radix E, plus one stage of the remaining smaller radix (last, or
@@ -385,9 +459,10 @@ struct Engine {
 
     // store stage S's outputs into LDS at their self-sorting positions.  The
     // padded index i + (i >> 4) of base + r*Ns splits into a per-butterfly part
-    // plus a constant whenever r*Ns is a multiple of 16 (Ns >= 16) or r < 16
-    // stays below the next multiple of 16 (Ns = 1, base a multiple of 16), so
-    // each butterfly costs one address computation instead of R.
+    // plus a constant whenever r*Ns is a multiple of 16 (Ns >= 16) or base is
+    // a multiple of 16 (Ns = 1, R >= 16: then the padding of base + r is that
+    // of base plus r >> 4), so each butterfly costs one address computation
+    // instead of R.
     template <int S, class V>
     __device__ __forceinline__ static void write(const V (&v)[E], int g, int t, V* lds) {
         constexpr int LR = SC::log2R(S);
@@ -395,7 +470,7 @@ struct Engine {
         constexpr int B = E / R;
         constexpr int LNS = SC::log2NS(S);
         constexpr int NS = 1 << LNS;
-        constexpr bool SPLITS = NS >= 16 || (NS == 1 && R == 16);
+        constexpr bool SPLITS = NS >= 16 || (NS == 1 && R >= 16);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int j = t + b * T;
@@ -404,7 +479,7 @@ struct Engine {
             if constexpr (SPLITS) {
                 V* p = lds + lds_at<GS>(g, base);
 #pragma unroll
-                for (int r = 0; r < R; ++r) p[NS >= 16 ? r * NS + ((r * NS) >> 4) : r] = v[b + r * B];
+                for (int r = 0; r < R; ++r) p[NS >= 16 ? r * NS + ((r * NS) >> 4) : r + (r >> 4)] = v[b + r * B];
             } else {
 #pragma unroll
                 for (int r = 0; r < R; ++r) lds[lds_at<GS>(g, base + r * NS)] = v[b + r * B];

@@ -1,6 +1,6 @@
 // Instances of the single-pass kernel: every N = 2^1 .. 2^14, both layouts,
-// both directions, stage twiddles in registers or read from the table, 8 or 16
-// elements per thread, 64- or 256-thread workgroups for the sizes where
+// both directions, stage twiddles in registers or read from the table, 8, 16
+// or 32 elements per thread, 64- or 256-thread workgroups for the sizes where
 // several transforms share a workgroup.
 #include "kernels.hpp"
 
@@ -42,6 +42,10 @@ static const SingleKernel kSingle[] = {
         single_entry<float, n, e, 256, false, true, r, false, false, true>(),                               \
         single_entry<float, n, e, 256, true, false, r, false, false, true>()
     FFT_SH(12, 4, true), FFT_SH(13, 4, true), FFT_SH(13, 4, false), FFT_SH(14, 4, false),
+    // 32 points per thread (radix-32 stages): three stages and two exchanges
+    // at 2^13 and 2^14 instead of four and three, half the threads per
+    // transform; stage twiddles from the table (registers for them would spill)
+    FFT_SH(13, 5, false), FFT_SH(14, 5, false),
 #undef FFT_SH
     // small transforms (each inside one wavefront): contiguous loads and
     // stores staged through LDS

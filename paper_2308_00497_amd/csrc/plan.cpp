@@ -455,7 +455,7 @@ std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int r
     }
     // single-pass variants: kernel shape x grid size x twiddle source
     std::vector<const SingleKernel*> shapes;
-    for (int e : {4, 3})
+    for (int e : {4, 3, 5})  // 5 last: below 2^5 it names the same kernels as 4
         for (int w : {256, 64})
             for (int r : {1, 0})
                 for (int var : {0, 1, 2, 3}) {  // plain, prefetching, staged, half-width exchanges

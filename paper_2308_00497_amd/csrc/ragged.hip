@@ -6,11 +6,16 @@
 // visit of a 512-thread workgroup:
 //   copy tile     up to 512 transforms of size 1
 //   single tile   G = 512/T whole transforms of size N <= 8192 (T = N/E
-//                 threads each, E = 8 points per thread up to 2^12, 16 above),
-//                 the single-pass Stockham engine
-//   pass tile     C = 8192/L columns of one pass of a transform with N > 8192,
-//                 split into P = ceil(log2 N / 8) passes of L <= 256 points
-//                 (the multi-pass scheme of Eq. 1 with M, K the pass lengths)
+//                 threads each, E = 8 points per thread up to 2^12, 16 at
+//                 2^13), the single-pass Stockham engine; one transform of
+//                 2^14 points at 32 points per thread (radix-32 stages, the
+//                 exchanges one real part at a time so the LDS stays that of
+//                 8192 complex elements), unless the configuration sets the
+//                 single-pass limit to 2^13
+//   pass tile     C = 8192/L columns of one pass of a transform above the
+//                 single-pass limit, split into P = ceil(log2 N / 8) passes of
+//                 L <= 256 points (the multi-pass scheme of Eq. 1 with M, K
+//                 the pass lengths)
 // Tiles are grouped in levels: level 0 holds every first-pass tile and then
 // every single/copy tile, level p > 0 the p-th pass tiles.  With pipelined
 // groups (RaggedConfig::group_mib) the multi-pass transforms are cut into
@@ -43,6 +48,7 @@ namespace {
 
 constexpr int kThreads = 512;
 constexpr int kTileLog2 = 13;  // 8192 elements per tile
+constexpr int kSingleMaxLog2 = 14;  // largest single-pass class
 constexpr int kMinPassLog2 = 5, kMaxPassLog2 = 8;
 constexpr int kMaxPasses = 3;  // passes of one multi-pass transform
 
@@ -77,8 +83,11 @@ struct RaggedArgs {
 };
 
 // points per thread of the single-pass classes: 8 up to 2^12, 16 for 2^13
-// (the shapes measured fastest for the plain kernels)
-constexpr int single_log2e(int log2n) { return log2n <= 12 ? 3 : 4; }
+// (the shapes measured fastest for the plain kernels), 32 for 2^14 (the
+// whole transform on the 512 threads)
+constexpr int single_log2e(int log2n) { return log2n <= 12 ? 3 : (log2n == 13 ? 4 : 5); }
+// the 2^14 class exchanges real and imaginary parts in turn (half the LDS)
+constexpr bool single_half(int log2n) { return log2n == 14; }
 
 template <int LOG2N>
 using RSingle = SingleShape<LOG2N, single_log2e(LOG2N), kThreads>;
@@ -88,6 +97,7 @@ using RPass = PassShape<LOG2L, 4, kTileLog2 - LOG2L>;
 
 constexpr int lds_max() {
     int m = 1;
+    m = std::max(m, (RSingle<14>::LDS + 1) / 2);
     m = std::max(m, RSingle<13>::LDS);
     m = std::max(m, RSingle<12>::LDS);
     m = std::max(m, RSingle<11>::LDS);
@@ -119,10 +129,11 @@ __device__ __forceinline__ uint32_t run_single(const RaggedArgs& a, uint32_t ti,
     // all stage twiddles in registers when they are few, else only the last
     // stage's (the 128-register budget of two 512-thread workgroups per CU);
     // in the split-layout kernel with 16 points per thread (2^13) none: the
-    // table is L1-resident, and registers for it would make that kernel spill
+    // table is L1-resident, and registers for it would make that kernel spill;
+    // none with 32 points per thread either (the data alone takes 64)
     constexpr bool ALLREG = (SC::NST - 1) * E <= 16;
-    constexpr bool MEMTW = SPLIT && !ALLREG && E == 16;
-    using ENG = Engine<SC, SH::G, SH::GS, false, false, SH::WAVE>;
+    constexpr bool MEMTW = (SPLIT && !ALLREG && E == 16) || E == 32;
+    using ENG = Engine<SC, SH::G, SH::GS, false, false, SH::WAVE, single_half(LOG2N)>;
     const uint32_t code = static_cast<uint32_t>(LOG2N);
     const float2* tw = a.tw32 + a.tiles[ti].tw_eng;
     using TWT = typename std::conditional<ALLREG, TwReg<SC>, TwLast<SC>>::type;
@@ -162,8 +173,14 @@ __device__ __forceinline__ uint32_t run_single(const RaggedArgs& a, uint32_t ti,
             const int64_t toff = a.toffs[d.first];
             float* oa = a.oa + (SPLIT ? toff : 2 * toff);
             float* ob = SPLIT ? a.ob + toff : nullptr;
+            // the lane offsets are formed again here rather than kept from the
+            // loads across the stages (32 points per thread leave no registers
+            // for them)
+            int tids = tid;
+            asm volatile("" : "+v"(tids));
+            const int ts = tids % T;
 #pragma unroll
-            for (int m = 0; m < E; ++m) gstore_nt<SPLIT>(oa, ob, static_cast<uint32_t>(t + T * m), swap_if<SWAP>(v[m]));
+            for (int m = 0; m < E; ++m) gstore_nt<SPLIT>(oa, ob, static_cast<uint32_t>(ts + T * m), swap_if<SWAP>(v[m]));
         } else if (active) {
             const int64_t base = a.toffs[d.first + g] + t;
 #pragma unroll
@@ -273,7 +290,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_ragged(RaggedArgs a) {
 #define FFT_RS(n) \
     case n: ti = run_single<n, SPLIT, SWAP>(a, ti, lds, tid); break;
                     FFT_RS(1) FFT_RS(2) FFT_RS(3) FFT_RS(4) FFT_RS(5) FFT_RS(6) FFT_RS(7)
-                    FFT_RS(8) FFT_RS(9) FFT_RS(10) FFT_RS(11) FFT_RS(12) FFT_RS(13)
+                    FFT_RS(8) FFT_RS(9) FFT_RS(10) FFT_RS(11) FFT_RS(12) FFT_RS(13) FFT_RS(14)
 #undef FFT_RS
                     default: ti += gridDim.x; break;
                 }
@@ -430,24 +447,36 @@ fft_status build_graph(RaggedPlan* r, int variant, std::string* detail) {
 
 std::string RaggedConfig::str() const {
     char buf[64];
-    if (group_mib > 0)
-        snprintf(buf, sizeof buf, "ragged:p%d:g%d:o%d:w%d", max_pass_log2, grid_eighths, smallest_first ? 1 : 0,
-                 group_mib);
-    else
-        snprintf(buf, sizeof buf, "ragged:p%d:g%d:o%d", max_pass_log2, grid_eighths, smallest_first ? 1 : 0);
+    int k = snprintf(buf, sizeof buf, "ragged:p%d:g%d:o%d", max_pass_log2, grid_eighths, smallest_first ? 1 : 0);
+    if (group_mib > 0) k += snprintf(buf + k, sizeof buf - k, ":w%d", group_mib);
+    if (single_max_log2 != kSingleMaxLog2) snprintf(buf + k, sizeof buf - k, ":s%d", single_max_log2);
     return buf;
 }
 
 bool RaggedConfig::parse(const std::string& s, RaggedConfig* out) {
-    int p = 0, g = 0, o = 0, w = 0, used = 0;
-    const int n = sscanf(s.c_str(), "ragged:p%d:g%d:o%d%n:w%d%n", &p, &g, &o, &used, &w, &used);
-    if ((n != 3 && n != 4) || used != static_cast<int>(s.size())) return false;
+    int p = 0, g = 0, o = 0, w = 0, sm = kSingleMaxLog2, used = 0;
+    if (sscanf(s.c_str(), "ragged:p%d:g%d:o%d%n", &p, &g, &o, &used) != 3) return false;
+    size_t at = static_cast<size_t>(used);
+    // optional ":w<W>", then optional ":s<S>"
+    if (s.compare(at, 2, ":w") == 0) {
+        used = 0;
+        if (sscanf(s.c_str() + at, ":w%d%n", &w, &used) != 1 || used == 0) return false;
+        at += static_cast<size_t>(used);
+        if (w < 8 || w > 65536) return false;
+    }
+    if (s.compare(at, 2, ":s") == 0) {
+        used = 0;
+        if (sscanf(s.c_str() + at, ":s%d%n", &sm, &used) != 1 || used == 0) return false;
+        at += static_cast<size_t>(used);
+        if (sm != kTileLog2 && sm != kSingleMaxLog2) return false;
+    }
+    if (at != s.size()) return false;
     if (p < 6 || p > kMaxPassLog2 || g < 1 || g > 8 || (o != 0 && o != 1)) return false;
-    if (n == 4 && (w < 8 || w > 65536)) return false;
     out->max_pass_log2 = p;
     out->grid_eighths = g;
     out->smallest_first = o == 1;
-    out->group_mib = n == 4 ? w : 0;
+    out->group_mib = w;
+    out->single_max_log2 = sm;
     return true;
 }
 
@@ -456,14 +485,17 @@ std::vector<RaggedConfig> ragged_candidates() {
     for (int w : {128, 0, 64, 192, 256})
         for (int p : {8, 7, 6})
             for (int g : {8, 6, 4})
-                for (int o : {0, 1}) {
-                    RaggedConfig c;
-                    c.max_pass_log2 = p;
-                    c.grid_eighths = g;
-                    c.smallest_first = o == 1;
-                    c.group_mib = w;
-                    v.push_back(c);
-                }
+                for (int o : {0, 1})
+                    for (int sm : {kSingleMaxLog2, kTileLog2}) {
+                        if (sm != kSingleMaxLog2 && w != 128) continue;  // the 2^13 limit at one group size
+                        RaggedConfig c;
+                        c.max_pass_log2 = p;
+                        c.grid_eighths = g;
+                        c.smallest_first = o == 1;
+                        c.group_mib = w;
+                        c.single_max_log2 = sm;
+                        v.push_back(c);
+                    }
     return v;
 }
 
@@ -496,8 +528,9 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
     }
     r->total = total;
 
-    // engine tables: single classes 1..12 and pass lengths 5..8
-    EngineInfo eng_single[kTileLog2 + 1] = {};
+    // engine tables: single classes 1..14 and pass lengths 5..8
+    const int smax = cfg.single_max_log2;
+    EngineInfo eng_single[kSingleMaxLog2 + 1] = {};
     eng_single[1] = engine_info<RSingle<1>::SC>();
     eng_single[2] = engine_info<RSingle<2>::SC>();
     eng_single[3] = engine_info<RSingle<3>::SC>();
@@ -511,14 +544,15 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
     eng_single[11] = engine_info<RSingle<11>::SC>();
     eng_single[12] = engine_info<RSingle<12>::SC>();
     eng_single[13] = engine_info<RSingle<13>::SC>();
+    eng_single[14] = engine_info<RSingle<14>::SC>();
     EngineInfo eng_pass[kMaxPassLog2 + 1] = {};
     eng_pass[5] = engine_info<RPass<5>::SC>();
     eng_pass[6] = engine_info<RPass<6>::SC>();
     eng_pass[7] = engine_info<RPass<7>::SC>();
     eng_pass[8] = engine_info<RPass<8>::SC>();
-    uint32_t off_single[kTileLog2 + 1] = {}, off_pass[kMaxPassLog2 + 1] = {};
+    uint32_t off_single[kSingleMaxLog2 + 1] = {}, off_pass[kMaxPassLog2 + 1] = {};
     size_t tw32_n = 0;
-    for (int n = 1; n <= kTileLog2; ++n) {
+    for (int n = 1; n <= smax; ++n) {
         off_single[n] = static_cast<uint32_t>(tw32_n);
         tw32_n += (eng_single[n].tw_size + 1) & ~1;
     }
@@ -539,7 +573,7 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
     int max_passes = 0;
     std::vector<int64_t> multi;
     for (int64_t i = 0; i < count; ++i) {
-        if (lg[i] <= kTileLog2) continue;
+        if (lg[i] <= smax) continue;
         multi.push_back(i);
         const int n = lg[i];
         if (parts[n].empty()) {
@@ -639,7 +673,7 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
     // level 0: first passes (of group 0), then the whole small transforms
     r->level_begin[0] = 0;
     if (ngroups > 0) pass_tiles(0, 0);
-    for (int n = kTileLog2; n >= 0; --n) {
+    for (int n = smax; n >= 0; --n) {
         std::vector<uint32_t> cls;
         for (int64_t i = 0; i < count; ++i)
             if (lg[i] == n) cls.push_back(static_cast<uint32_t>(i));
@@ -681,7 +715,7 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
         for (uint32_t i = r->level_begin[l]; i < r->level_begin[l + 1]; ++i) only = only && tiles[i].code >= CODE_PASS_FIRST;
         r->level_pass_only[l] = only;
     }
-    for (int n = kTileLog2 + 1; n <= kMaxLog2N; ++n) {
+    for (int n = smax + 1; n <= kMaxLog2N; ++n) {
         int64_t c = 0;
         for (int64_t i : multi) c += lg[i] == n;
         if (!c) continue;
@@ -706,10 +740,10 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
         delete r;
         return FFT_ERR_ALLOC;
     }
-    for (int n = 1; n <= kTileLog2 && e == hipSuccess; ++n) e = launch_gen_engine_tw(eng_single[n], r->tw32 + off_single[n], 4, nullptr);
+    for (int n = 1; n <= smax && e == hipSuccess; ++n) e = launch_gen_engine_tw(eng_single[n], r->tw32 + off_single[n], 4, nullptr);
     for (int l = kMinPassLog2; l <= kMaxPassLog2 && e == hipSuccess; ++l)
         e = launch_gen_engine_tw(eng_pass[l], r->tw32 + off_pass[l], 4, nullptr);
-    for (int n = kTileLog2 + 1; n <= kMaxLog2N && e == hipSuccess; ++n)
+    for (int n = smax + 1; n <= kMaxLog2N && e == hipSuccess; ++n)
         for (size_t p = 1; p < ptab[n].size() && e == hipSuccess; ++p) {
             const PassTab& t = ptab[n][p];
             e = launch_gen_pow64(r->tw64 + t.ta, t.log2m, int64_t(1) << t.hbits, int64_t(1) << (t.log2m - t.hbits),

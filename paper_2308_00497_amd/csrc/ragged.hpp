@@ -27,12 +27,15 @@ struct RaggedPlan;
 //                   level writes to the workspace is read by the next while it
 //                   can still be in the memory-side cache, and the workspace
 //                   is a ring of two group-sized slots
+//   single_max_log2 largest size run as one single-pass tile, 2^14 (radix-32
+//                   stages) or 2^13 (2^14 then takes two passes)
 struct RaggedConfig {
     int max_pass_log2 = 8;
     int grid_eighths = 8;
     bool smallest_first = true;  // measured equal or faster than largest first on the 2^6..2^16 mix
     int group_mib = 128;  // measured best on the 2^6..2^16 mix (two 128 MiB slots)
-    std::string str() const;  // "ragged:p8:g8:o0" or "ragged:p8:g8:o0:w128"
+    int single_max_log2 = 14;
+    std::string str() const;  // "ragged:p8:g8:o0", "ragged:p8:g8:o0:w128", "ragged:p8:g8:o0:w128:s13"
     static bool parse(const std::string& s, RaggedConfig* out);
 };
 

@@ -151,7 +151,10 @@ def test_half_exchange_decomposition_strings(lib, fftlib):
         q = fftlib.query_decomposition(1 << 14, layout, "fp32")
         assert q["default"] == "single:e4:w256:g8:r0:h1", q["default"]
         hs = [c for c in q["candidates"] if c.endswith(":h1")]
-        assert hs and all(c.startswith("single:e4:w256:") for c in hs)
+        assert hs and all(c.startswith(("single:e4:w256:", "single:e5:w256:")) for c in hs)
+        # 32 points per thread (radix-32 stages) exists with half-width exchanges only
+        e5 = [c for c in q["candidates"] if c.startswith("single:e5:")]
+        assert e5 and all(c.endswith(":r0:h1") for c in e5), e5
 
 
 def test_staged_decomposition_strings(lib, fftlib):
@@ -232,7 +235,9 @@ def test_ragged_validation(lib):
     assert lib.fft_plan_create_ragged(ctypes.byref(h), arr, 2, 7, -1) == 2
     # explicit configurations that do not parse are rejected before any device call
     for bad in (b"bogus", b"ragged:p9:g8:o0", b"ragged:p5:g8:o0", b"ragged:p8:g0:o0", b"ragged:p8:g8:o2",
-                b"ragged:p8:g8:o0:w4", b"ragged:p8:g8:o0:w", b"ragged:p8:g8:o0:w64x", b"ragged:p8:g8"):
+                b"ragged:p8:g8:o0:w4", b"ragged:p8:g8:o0:w", b"ragged:p8:g8:o0:w64x", b"ragged:p8:g8",
+                b"ragged:p8:g8:o0:s12", b"ragged:p8:g8:o0:s15", b"ragged:p8:g8:o0:s", b"ragged:p8:g8:o0:s13:w8",
+                b"ragged:p8:g8:o0:w8:s13x", b"ragged:p8:g8:o0:w8:s13:s14"):
         assert lib.fft_plan_create_ragged_ex(ctypes.byref(h), arr, 2, 0, -1, bad) == 2, bad
 
 

@@ -63,6 +63,25 @@ def test_every_single_pass_variant(fftlib, log2n, layout):
 
 
 @pytest.mark.parametrize("layout", ["interleaved", "split"])
+@pytest.mark.parametrize("log2n", [13, 14])
+def test_radix32_single_pass(fftlib, log2n, layout):
+    """32 points per thread: radix-32 register DFTs (Eq. 1 with K = 4, M = 8
+    inside each thread), every grid size, both directions, a batch that
+    leaves the persistent grid a ragged last round."""
+    n = 1 << log2n
+    batch = 1029 if log2n == 13 else 515
+    re, im = workloads.normal_complex((batch, n), seed=2100 + log2n)
+    decs = [c for c in candidates(fftlib, log2n, layout) if c.startswith("single:e5:")]
+    assert decs
+    for direction in ("forward", "inverse"):
+        ref = oracle_ref(re, im, direction)
+        for dec in decs:
+            with fftlib.Plan(n, batch, layout, direction, decomposition=dec) as plan:
+                y = from_device(plan.execute(to_device(re, im, layout)), layout)
+            assert_parity(y, ref, f"N=2^{log2n} b={batch} {layout} {direction} {dec}")
+
+
+@pytest.mark.parametrize("layout", ["interleaved", "split"])
 @pytest.mark.parametrize("log2n", [12, 13, 14, 15, 16, 17, 18, 20, 24])
 def test_every_multi_pass_variant(fftlib, log2n, layout):
     n = 1 << log2n

@@ -193,12 +193,14 @@ def test_ragged_autotune_and_every_config(fftlib, tmp_path, monkeypatch):
                 assert per_item_errors(y, ref, sizes, offsets).max() <= TOL, cfg
 
 
-@pytest.mark.parametrize("cfg", ["ragged:p8:g8:o0:w8", "ragged:p7:g6:o1:w8", "ragged:p6:g4:o0:w16"])
+@pytest.mark.parametrize("cfg", ["ragged:p8:g8:o0:w8", "ragged:p7:g6:o1:w8", "ragged:p6:g4:o0:w16:s13"])
 def test_ragged_pipelined_groups(fftlib, cfg):
     """Multi-pass transforms cut into groups of at most w MiB of workspace,
     group g's pass p in level g + p, the workspace a ring of two slots: three-
     and two-pass chains in different groups, single tiles in level 0, both
-    layouts and directions; new buffers on the second run reuse the graph."""
+    layouts and directions; new buffers on the second run reuse the graph.
+    (With 16 MiB groups the batch needs its 2^14 transforms among the
+    multi-pass ones, the single-pass limit at 2^13, to form two groups.)"""
     sizes, offsets, re, im = make([1 << 20, 1 << 18, 1 << 6, 1 << 18, 1 << 16, 1 << 14, 1 << 18, 1 << 12,
                                    1 << 16, 1 << 16, 1 << 14, 1 << 16, 1 << 9], 49)
     for direction in ("forward", "inverse"):
@@ -234,6 +236,31 @@ def test_ragged_pipelined_matches_plain_levels(fftlib):
     assert per_item_errors(a, b, sizes, offsets).max() <= TOL
 
 
+@pytest.mark.parametrize("layout", ["interleaved", "split"])
+def test_single_pass_limit(fftlib, layout):
+    """2^14 transforms as one single-pass tile each (32 points per thread,
+    radix-32 stages, half-width exchanges) by default, or as two passes with
+    the limit at 2^13: both to the oracle's tolerance, among single-pass and
+    multi-pass neighbours, both directions."""
+    rng = np.random.default_rng(53)
+    sz = [1 << 14] * 40 + [1 << 13] * 9 + [1 << 15] * 5 + [1 << 6] * 100 + [1 << 12] * 7
+    sizes, offsets, re, im = make(list(rng.permutation(sz)), 54)
+    for direction in ("forward", "inverse"):
+        ref = ragged_oracle(sizes, offsets, re, im, direction)
+        ys = []
+        for cfg, multi in (("ragged:p8:g8:o1:w128", 5), ("ragged:p8:g8:o1:w128:s13", 45)):
+            print(f"[case] single-pass limit {cfg} {layout} {direction}", flush=True)
+            with fftlib.RaggedPlan(sizes, layout, direction, config=cfg) as plan:
+                d = plan.describe()
+                assert d["config"] == cfg and d["multi_pass_transforms"] == multi, d
+                y = from_device(plan.execute(to_device(re, im, layout)), layout)
+            errs = per_item_errors(y, ref, sizes, offsets)
+            print(f"[parity] {cfg} {layout} {direction}: max rel-L2 {errs.max():.3e}", flush=True)
+            assert errs.max() <= TOL, (cfg, layout, direction)
+            ys.append(y)
+        assert per_item_errors(ys[0], ys[1], sizes, offsets).max() <= TOL
+
+
 def _resident_grid(fftlib, cfg):
     """Persistent workgroups of a full level: a plan with more tiles than can be
     resident reports the grid in its description (no data is transformed)."""
@@ -245,7 +272,7 @@ def _resident_grid(fftlib, cfg):
 def test_class_changes_inside_a_workgroup(fftlib, layout):
     """Size mixes dealt so that every persistent workgroup of level 0 runs one
     tile of a class whose transforms span several wavefronts (first-pass tiles
-    of 2^15, or 2^10 transforms) and then one tile of a class whose transforms
+    of 2^15, 2^10 or 2^14 transforms) and then one tile of a class whose transforms
     fit in one wavefront (2^6, or 2^9): the second class's first LDS exchange
     must not overwrite what the first class's last stage is still reading."""
     cfg = "ragged:p8:g8:o1"
@@ -253,6 +280,7 @@ def test_class_changes_inside_a_workgroup(fftlib, layout):
     mixes = {
         "pass->2^6": [1 << 15] * (w // 4) + [1 << 6] * (64 * w),   # 4 first-pass tiles per 2^15, 64 per 2^6 tile
         "2^10->2^9": [1 << 10] * (4 * w) + [1 << 9] * (8 * w),     # 4 per 2^10 tile, 8 per 2^9 tile
+        "2^14->2^6": [1 << 14] * w + [1 << 6] * (64 * w),          # one per 2^14 tile (half-width exchanges)
     }
     for name, sz in mixes.items():
         rng = np.random.default_rng(51)
