@@ -299,6 +299,10 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout, int64_t batch
         // radix-8 stages measured faster (1024 split rows not cached:
         // e3 15.2-15.7 us against e4 16.4-16.7 us; e4 leads from 8192 rows)
         if (log2n == 12 && batch > 0 && batch <= 1024) d.log2e = 3;
+        // split data at 2^14: 32 points per thread (radix-32, 32, 16 stages)
+        // measured 128-135 us against 143-154 us for 16 points per thread;
+        // interleaved the 16-point shape leads (135-139 against 140-151 us)
+        if (log2n == 14 && layout == FFT_LAYOUT_SPLIT) d.log2e = 5;
         return d;
     }
     // multi-pass chains measured fastest on MI355X per layout (batches of 2^25

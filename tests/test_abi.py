@@ -140,7 +140,8 @@ def test_prefetch_decomposition_strings(lib, fftlib):
 def test_half_exchange_decomposition_strings(lib, fftlib):
     """":h1" selects the single-pass kernel whose stages exchange one real part
     at a time; it exists only where compiled (FP32 2^12 .. 2^14, FP64 2^12 and
-    2^13), is not combined with another variant, and is the FP32 2^14 default."""
+    2^13), is not combined with another variant, and is the FP32 2^14 default
+    (16 points per thread interleaved, 32 split)."""
     h = ctypes.c_void_p()
     ex = lib.fft_plan_create_ex
     assert ex(ctypes.byref(h), 4096, 1, 0, -1, 0, b"single:e4:w256:g2:r1:h2") == 2
@@ -149,7 +150,8 @@ def test_half_exchange_decomposition_strings(lib, fftlib):
     assert ex(ctypes.byref(h), 1 << 11, 1, 0, -1, 1, b"single:e3:w256:g2:r0:h1") == 7   # nor FP64 2^11
     for layout in ("interleaved", "split"):
         q = fftlib.query_decomposition(1 << 14, layout, "fp32")
-        assert q["default"] == "single:e4:w256:g8:r0:h1", q["default"]
+        e = 5 if layout == "split" else 4
+        assert q["default"] == f"single:e{e}:w256:g8:r0:h1", q["default"]
         hs = [c for c in q["candidates"] if c.endswith(":h1")]
         assert hs and all(c.startswith(("single:e4:w256:", "single:e5:w256:")) for c in hs)
         # 32 points per thread (radix-32 stages) exists with half-width exchanges only
