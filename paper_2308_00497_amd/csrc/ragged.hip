@@ -128,10 +128,12 @@ __device__ __forceinline__ uint32_t run_single(const RaggedArgs& a, uint32_t ti,
     constexpr int E = SC::E, T = SC::T;
     // all stage twiddles in registers when they are few, else only the last
     // stage's (the 128-register budget of two 512-thread workgroups per CU);
-    // in the split-layout kernel with 16 points per thread (2^13) none: the
-    // table is L1-resident, and registers for it would make that kernel spill;
-    // none with 32 points per thread either (the data alone takes 64)
-    constexpr bool ALLREG = (SC::NST - 1) * E <= 16;
+    // also all of them for 2^12 (24 pairs: a batch of 2^12 transforms 121 ->
+    // 102 us for 2^25 elements; two such classes made the kernel spill); in
+    // the split-layout kernel with 16 points per thread (2^13) none: the table
+    // is L1-resident, and registers for it would make that kernel spill; none
+    // with 32 points per thread either (the data alone takes 64)
+    constexpr bool ALLREG = (SC::NST - 1) * E <= (E == 8 && LOG2N == 12 ? 32 : 16);
     constexpr bool MEMTW = (SPLIT && !ALLREG && E == 16) || E == 32;
     using ENG = Engine<SC, SH::G, SH::GS, false, false, SH::WAVE, single_half(LOG2N)>;
     const uint32_t code = static_cast<uint32_t>(LOG2N);
@@ -158,9 +160,12 @@ __device__ __forceinline__ uint32_t run_single(const RaggedArgs& a, uint32_t ti,
                 v[m] = swap_if<SWAP>(gload_nt<SPLIT>(ia, ib, static_cast<uint32_t>(t + T * m)));
         } else {
             const int64_t base = (active ? a.toffs[d.first + g] : 0) + t;
+            // raised load priority for interleaved data, as in the plain kernel
+            if constexpr (!SPLIT) loads_begin();
 #pragma unroll
             for (int m = 0; m < E; ++m)
                 v[m] = active ? swap_if<SWAP>(gload_nt<SPLIT>(a.ia, a.ib, base + T * m)) : make_float2(0.f, 0.f);
+            if constexpr (!SPLIT) loads_end();
         }
         if constexpr (MEMTW) {
             const float2* twl = tw;
