@@ -416,8 +416,9 @@ def extras(fftlib, torch, workloads, dev, checks):
     autograd forward+backward against the same two kernels called directly, the
     FP64 path on the batched shape and on 2^24, the real-input transforms, the
     per-operator baseline (the paper's one-kernel-per-operator mapping) against
-    the fused kernel, and batched 2D/3D transforms.  Each result is copied to
-    the host for the oracle leg's error figures."""
+    the fused kernel, the vendor FFT library through torch.fft on the same
+    shapes (labelled context), and batched 2D/3D transforms.  Each result is
+    copied to the host for the oracle leg's error figures."""
     out = {}
     # --- single large transform, split, noise + 8 cosines ---------------------
     n = 1 << 24
@@ -640,6 +641,31 @@ def extras(fftlib, torch, workloads, dev, checks):
                    {"kind": "c2c", "re": re[rows], "im": im[rows], "sign": -1, "y": ops_host,
                     "sample": f"ops:r4 output, {len(rows)} of {batch} rows"}))
     del z, zo
+    # --- context: the vendor FFT library through torch.fft (hipFFT / rocFFT on
+    # ROCm) on the same device tensors, interleaved complex64 forward; labelled
+    # context only (not the path, not a parity reference), its output checked
+    # against the oracle like every other result
+    for n, batch, label in ((4096, 8192, "n4096_b8192"), (1 << 24, 1, "n2^24_b1"), (4096, 1024, "n4096_b1024")):
+        re, im = workloads.normal_complex((batch, n), seed=workloads.SEEDS["c2"] + 40)
+        x = torch.from_numpy(workloads.interleave(re, im)).to(dev).view(batch, n)
+        y = torch.empty_like(x)
+        with fftlib.Plan(n, batch, "interleaved", "forward") as p:
+            ms_ours = _time(torch, lambda: p.execute(x, out=y), 20)
+        ms_vendor = _time(torch, lambda: torch.fft.fft(x, dim=-1), 20)
+        yv = torch.fft.fft(x, dim=-1)
+        torch.cuda.synchronize()
+        key = f"vendor_fft_context_{label}"
+        out[key] = {"torch_fft_ms": round(ms_vendor, 4), "this_library_ms": round(ms_ours, 4),
+                    "this_library_speedup": round(ms_vendor / ms_ours, 2),
+                    "vendor": f"torch.fft.fft, torch {torch.__version__} (ROCm: hipFFT / rocFFT)",
+                    "note": "labelled context, not the path and not a parity reference; the torch call allocates its "
+                            "output through torch's caching allocator"}
+        rows = np.arange(0, batch, 8) if batch > 1 else np.arange(1)
+        yh = yv.cpu().numpy().reshape(batch, n)[rows]
+        checks.append((out[key], {"kind": "c2c", "re": re[rows], "im": im[rows], "sign": -1, "y": yh,
+                                  "threads": 1 if batch == 1 else 16,
+                                  "sample": f"torch.fft output, {len(rows)} of {batch} rows"}))
+        del x, y, yv
     # --- batched 2D / 3D: the last axis by the 1D plan, the others by column passes
     for dims, batch in (((4096, 4096), 2), ((256, 256, 256), 2)):
         numel = batch * int(np.prod(dims))
