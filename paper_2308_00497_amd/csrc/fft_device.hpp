@@ -269,6 +269,13 @@ struct Sched {
         return a;
     }
     static constexpr int TW_SIZE = NST > 1 ? twOff(NST) : 0;
+    // the recurrence form (TwRec): stage s keeps only w_(Ns*R)^k, k < Ns, in FP64
+    __host__ __device__ static constexpr int recOff(int s) {
+        int a = 0;
+        for (int q = 1; q < s; ++q) a += 1 << log2NS(q);
+        return a;
+    }
+    static constexpr int REC_SIZE = NST > 1 ? recOff(NST) : 0;
 };
 
 // LDS index of element i of group g: one element of padding every 16 elements
@@ -653,5 +660,31 @@ __device__ __forceinline__ V twiddle_2level(const double2* __restrict__ ta, cons
                                            int64_t e, int hbits) {
     return cvt_tw<V>(twiddle_2level64(ta, tb, e, hbits));
 }
+
+// Stage twiddles by recurrence: butterfly j of stage S reads one FP64 value,
+// w = w_(Ns*R)^k (k = j mod Ns, from a table of Ns entries at recOff(S)), and
+// forms w^2 .. w^(R-1) by FP64 products (an error of a few FP64 ulps), each
+// rounded once to the working precision: one load per butterfly instead of
+// R - 1, for the sizes whose stage tables do not fit in registers.
+template <class SC, class V = float2>
+struct TwRec {
+    const double2* __restrict__ p;
+    __device__ __forceinline__ explicit TwRec(const double2* q) : p(q) {}
+    __device__ __forceinline__ void init(int) {}
+
+    template <int S, int R>
+    __device__ __forceinline__ void apply(V (&u)[R], int /*b*/, int j) const {
+        constexpr int LNS = SC::log2NS(S);
+        const int k = j & ((1 << LNS) - 1);
+        const double2 w = p[SC::recOff(S) + k];
+        double2 x = w;
+        u[1] = c_mul(u[1], cvt_tw<V>(x));
+#pragma unroll
+        for (int r = 2; r < R; ++r) {
+            x = z_mul(x, w);
+            u[r] = c_mul(u[r], cvt_tw<V>(x));
+        }
+    }
+};
 
 }  // namespace fftk

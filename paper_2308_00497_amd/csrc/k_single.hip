@@ -47,6 +47,14 @@ static const SingleKernel kSingle[] = {
     // transform; stage twiddles from the table (registers for them would spill)
     FFT_SH(13, 5, false), FFT_SH(14, 5, false),
 #undef FFT_SH
+    // stage twiddles from one FP64 value per butterfly (the sizes whose tables
+    // do not fit in registers): half-width exchanges at 2^14, and 2^13
+#define FFT_SR(n, e, h)                                                                                      \
+    single_entry<float, n, e, 256, false, false, false, false, false, h, true>(),                            \
+        single_entry<float, n, e, 256, false, true, false, false, false, h, true>(),                         \
+        single_entry<float, n, e, 256, true, false, false, false, false, h, true>()
+    FFT_SR(14, 4, true), FFT_SR(14, 5, true), FFT_SR(13, 4, false), FFT_SR(13, 5, true),
+#undef FFT_SR
     // small transforms (each inside one wavefront): contiguous loads and
     // stores staged through LDS
 #define FFT_ST(n, e)                                                                                        \

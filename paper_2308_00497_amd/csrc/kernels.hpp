@@ -77,7 +77,7 @@ constexpr int single_lds() {
 // real and imaginary parts one after the other through half the LDS, so more
 // workgroups fit on a compute unit where LDS limits them.
 template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false,
-          bool STG = false, bool HALF = false>
+          bool STG = false, bool HALF = false, bool TWREC = false>
 __global__ void __launch_bounds__((SingleShape<LOG2N, LOG2E, WGT>::THREADS))
 k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw, int64_t batch) {
     using V = cplx_t<R>;
@@ -86,6 +86,7 @@ k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ t
     constexpr int E = SC::E, T = SC::T, L = SC::L, G = SH::G;
     static_assert(!(STG && PF), "staging and prefetching are separate variants");
     static_assert(!(STG && HALF), "staged transforms use the complex exchange");
+    static_assert(!TWREC || (!TWREG && !STG && sizeof(R) == 4), "the recurrence twiddles serve FP32 plain kernels");
     static_assert(!STG || (SH::WAVE && (64 % T) == 0 && SH::THREADS % 64 == 0),
                   "staging needs every transform inside one wavefront");
     __shared__ V lds[single_lds<LOG2N, LOG2E, WGT, STG, HALF>()];
@@ -192,6 +193,9 @@ k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ t
             for (int m = 0; m < E; ++m) v[m] = c_zero<V>();
         }
         if constexpr (TWREG) Engine<SC, G, SH::GS, false, false, SH::WAVE, HALF>::run(v, lds, twr, tidl);
+        else if constexpr (TWREC)
+            Engine<SC, G, SH::GS, false, false, SH::WAVE, HALF>::run(
+                v, lds, TwRec<SC, V>(reinterpret_cast<const double2*>(twl)), tidl);
         else Engine<SC, G, SH::GS, false, false, SH::WAVE, HALF>::run(v, lds, TwMem<SC, V>(twl), tidl);
         if (active) {
 #pragma unroll
@@ -201,37 +205,40 @@ k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ t
 }
 
 template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false, bool STG = false,
-          bool HALF = false>
+          bool HALF = false, bool TWREC = false>
 hipError_t launch_single(const void* ia, const void* ib, void* oa, void* ob, const void* tw, int64_t batch, int grid,
                          hipStream_t s) {
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
     const int64_t groups = (batch + SH::G - 1) / SH::G;
     const int64_t blocks = groups < grid ? groups : grid;
     if (blocks < 1) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG, HALF>), dim3(static_cast<unsigned>(blocks)),
+    hipLaunchKernelGGL((k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG, HALF, TWREC>), dim3(static_cast<unsigned>(blocks)),
                        dim3(SH::THREADS), 0, s, static_cast<const R*>(ia), static_cast<const R*>(ib),
                        static_cast<R*>(oa), static_cast<R*>(ob), static_cast<const cplx_t<R>*>(tw), batch);
     return hipGetLastError();
 }
 
-template <class SC>
+// REC: the recurrence table (TwRec) - offsets and size in FP32 complex
+// entries, two per FP64 pair, so a float2 buffer holds it 16-byte aligned
+template <class SC, bool REC = false>
 EngineInfo engine_info() {
     EngineInfo e{};
     e.log2l = SC::LOG2L;
     e.log2e = SC::LE;
     e.remfirst = SC::REMFIRST;
     e.nst = SC::NST;
-    e.tw_size = SC::TW_SIZE;
+    e.rec = REC;
+    e.tw_size = REC ? 2 * SC::REC_SIZE : SC::TW_SIZE;
     for (int s = 0; s < SC::NST && s < kMaxStages; ++s) {
         e.log2ns[s] = SC::log2NS(s);
         e.log2r[s] = SC::log2R(s);
-        e.tw_off[s] = SC::twOff(s);
+        e.tw_off[s] = REC ? 2 * SC::recOff(s) : SC::twOff(s);
     }
     return e;
 }
 
 template <class R, int LOG2N, int LOG2E, int WGT, bool SPLIT, bool SWAP, bool TWREG, bool PF = false, bool STG = false,
-          bool HALF = false>
+          bool HALF = false, bool TWREC = false>
 SingleKernel single_entry() {
     using SH = SingleShape<LOG2N, LOG2E, WGT>;
     SingleKernel k{};
@@ -245,9 +252,10 @@ SingleKernel single_entry() {
     k.pf = PF;
     k.stg = STG;
     k.half = HALF;
-    k.fn = &launch_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG, HALF>;
-    k.kernel = reinterpret_cast<const void*>(&k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG, HALF>);
-    k.eng = engine_info<typename SH::SC>();
+    k.twrec = TWREC;
+    k.fn = &launch_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG, HALF, TWREC>;
+    k.kernel = reinterpret_cast<const void*>(&k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG, HALF, TWREC>);
+    k.eng = engine_info<typename SH::SC, TWREC>();
     k.threads = SH::THREADS;
     k.per_wg = SH::G;
     k.lds_bytes = single_lds<LOG2N, LOG2E, WGT, STG, HALF>() * sizeof(cplx_t<R>);

@@ -27,7 +27,7 @@ std::string Decomp::str() const {
         case COPY:
             return "copy";
         case SINGLE:
-            snprintf(buf, sizeof buf, "single:e%d:w%d:g%d:r%d%s", log2e, wgt, gmul, twreg ? 1 : 0,
+            snprintf(buf, sizeof buf, "single:e%d:w%d:g%d:r%d%s", log2e, wgt, gmul, twreg ? 1 : (twrec ? 2 : 0),
                      pf ? ":p1" : (stg ? ":s1" : (half ? ":h1" : "")));
             return buf;
         case OPS:
@@ -54,16 +54,19 @@ bool Decomp::parse(const std::string& s, Decomp* out) {
     }
     int e = 0, w = 0, g = 0, r = 0, used = 0;
     if (sscanf(s.c_str(), "single:e%d:w%d:g%d:r%d%n", &e, &w, &g, &r, &used) == 4) {
-        // optional variant: ":p1" prefetching, ":s1" staged, ":h1" half-width
-        // exchanges (":p0"/":s0"/":h0" are spelled by leaving the field out)
+        // r: stage twiddles read from the table (0), held in registers (1), or
+        // formed from one FP64 table value per butterfly (2); optional variant:
+        // ":p1" prefetching, ":s1" staged, ":h1" half-width exchanges
+        // (":p0"/":s0"/":h0" are spelled by leaving the field out)
         const std::string rest = s.substr(used);
         if (!rest.empty() && rest != ":p1" && rest != ":s1" && rest != ":h1") return false;
-        if (g < 1 || g > 64 || (r != 0 && r != 1)) return false;
+        if (g < 1 || g > 64 || r < 0 || r > 2) return false;
         d.kind = SINGLE;
         d.log2e = e;
         d.wgt = w;
         d.gmul = g;
         d.twreg = r == 1;
+        d.twrec = r == 2;
         d.pf = rest == ":p1";
         d.stg = rest == ":s1";
         d.half = rest == ":h1";
@@ -100,13 +103,13 @@ bool Decomp::parse(const std::string& s, Decomp* out) {
 }
 
 const SingleKernel* find_single(int rb, int log2n, int log2e, int wgt, bool split, bool swap, bool twreg, bool pf,
-                                bool stg, bool half) {
+                                bool stg, bool half, bool twrec) {
     int cnt = 0;
     const SingleKernel* t = rb == 8 ? single_kernels64(&cnt) : single_kernels(&cnt);
     const int le = log2e < log2n ? log2e : log2n;
     for (int i = 0; i < cnt; ++i)
         if (t[i].log2n == log2n && t[i].log2e == le && t[i].wgt == wgt && t[i].split == split && t[i].swap == swap &&
-            t[i].twreg == twreg && t[i].pf == pf && t[i].stg == stg && t[i].half == half)
+            t[i].twreg == twreg && t[i].pf == pf && t[i].stg == stg && t[i].half == half && t[i].twrec == twrec)
             return &t[i];
     return nullptr;
 }
@@ -129,7 +132,7 @@ const PassKernel* pass_kernel_for(int rb, int log2l, int log2c, size_t p, size_t
 }
 
 const SingleKernel* single_kernel_for(int rb, int log2n, const Decomp& d, bool split, bool inverse) {
-    return find_single(rb, log2n, d.log2e, d.wgt, split, inverse && !split, d.twreg, d.pf, d.stg, d.half);
+    return find_single(rb, log2n, d.log2e, d.wgt, split, inverse && !split, d.twreg, d.pf, d.stg, d.half, d.twrec);
 }
 
 // column tile for a sub-FFT length: the widest compiled one up to 128-byte
@@ -281,17 +284,21 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout, int64_t batch
         // layouts); up to 2^7 the staged kernel, whose loads and stores are
         // contiguous runs; at 2^14 half-width exchanges (two workgroups per
         // CU instead of one: 151.5 -> 136.3 us interleaved, 149.5 -> 142.2 us
-        // split); the autotuner refines them per device
-        static const struct { int log2e, gmul, twreg, pf, stg, half; } table[15] = {
+        // split); at 2^13 and 2^14 stage twiddles from one FP64 value per
+        // butterfly (tw 2: 2^13 106.6-114.8 -> 97.4-98.5 us, 2^14 136-137 ->
+        // 111 us interleaved, 128 -> 102-105 us split; tw 1 = registers, 0 =
+        // the table); the autotuner refines them per device
+        static const struct { int log2e, gmul, tw, pf, stg, half; } table[15] = {
             {4, 1, 1, 0, 0, 0}, {4, 4, 1, 0, 1, 0}, {4, 3, 1, 0, 1, 0}, {4, 2, 1, 0, 1, 0}, {4, 8, 1, 0, 1, 0},  // 2^0 .. 2^4
             {4, 8, 1, 0, 1, 0}, {4, 8, 1, 0, 1, 0}, {4, 8, 1, 0, 1, 0}, {3, 2, 1, 0, 0, 0}, {3, 2, 1, 0, 0, 0},  // 2^5 .. 2^9
-            {3, 2, 1, 0, 0, 0}, {3, 2, 1, 0, 0, 0}, {4, 2, 1, 0, 0, 0}, {4, 4, 1, 0, 0, 0}, {4, 8, 0, 0, 0, 1},  // 2^10 .. 2^14
+            {3, 2, 1, 0, 0, 0}, {3, 2, 1, 0, 0, 0}, {4, 2, 1, 0, 0, 0}, {5, 8, 2, 0, 0, 1}, {4, 8, 2, 0, 0, 1},  // 2^10 .. 2^14
         };
         d.kind = Decomp::SINGLE;
         d.log2e = table[log2n].log2e;
         d.wgt = 256;
         d.gmul = table[log2n].gmul;
-        d.twreg = table[log2n].twreg == 1;
+        d.twreg = table[log2n].tw == 1;
+        d.twrec = table[log2n].tw == 2;
         d.pf = table[log2n].pf == 1;
         d.stg = table[log2n].stg == 1;
         d.half = table[log2n].half == 1;
@@ -300,9 +307,13 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout, int64_t batch
         // e3 15.2-15.7 us against e4 16.4-16.7 us; e4 leads from 8192 rows)
         if (log2n == 12 && batch > 0 && batch <= 1024) d.log2e = 3;
         // split data at 2^14: 32 points per thread (radix-32, 32, 16 stages)
-        // measured 128-135 us against 143-154 us for 16 points per thread;
-        // interleaved the 16-point shape leads (135-139 against 140-151 us)
-        if (log2n == 14 && layout == FFT_LAYOUT_SPLIT) d.log2e = 5;
+        // at 4 workgroups per CU's worth of grid, 102-105 us against 113-115
+        // for 16 points per thread; interleaved the 16-point shape leads
+        // (110.8-111.1 against 111.8-112.5 us)
+        if (log2n == 14 && layout == FFT_LAYOUT_SPLIT) {
+            d.log2e = 5;
+            d.gmul = 4;
+        }
         return d;
     }
     // multi-pass chains measured fastest on MI355X per layout (batches of 2^25
@@ -373,7 +384,7 @@ bool real_decomposition_available(const Decomp& d, int log2n, fft_layout layout,
         case Decomp::COPY:
             return log2h == 0;
         case Decomp::SINGLE:
-            return log2h >= 1 && !d.pf && !d.half &&
+            return log2h >= 1 && !d.pf && !d.half && !d.twrec &&
                    find_real(rb, log2h, d.log2e, d.wgt, c2r, split, d.twreg, d.stg) != nullptr;
         case Decomp::MULTI: {
             // the half-length chain runs on interleaved data in both directions
@@ -461,10 +472,10 @@ std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int r
     std::vector<const SingleKernel*> shapes;
     for (int e : {4, 3, 5})  // 5 last: below 2^5 it names the same kernels as 4
         for (int w : {256, 64})
-            for (int r : {1, 0})
+            for (int r : {1, 0, 2})  // registers, table, recurrence
                 for (int var : {0, 1, 2, 3}) {  // plain, prefetching, staged, half-width exchanges
                     const bool pf = var == 1, stg = var == 2, half = var == 3;
-                    const SingleKernel* k = find_single(rb, log2n, e, w, false, false, r == 1, pf, stg, half);
+                    const SingleKernel* k = find_single(rb, log2n, e, w, false, false, r == 1, pf, stg, half, r == 2);
                     if (!k) continue;
                     bool dup = false;
                     for (auto* o : shapes) dup |= (o == k);
@@ -477,6 +488,7 @@ std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int r
                         d.wgt = w;
                         d.gmul = g;
                         d.twreg = r == 1;
+                        d.twrec = r == 2;
                         d.pf = pf;
                         d.stg = stg;
                         d.half = half;

@@ -31,6 +31,7 @@ struct Decomp {
     bool pf = false;  // single: the next transform's loads issued before the current one's stages
     bool stg = false; // single: contiguous loads/stores staged through LDS (small transforms)
     bool half = false; // single: stage exchanges one real part at a time (half the LDS)
+    bool twrec = false; // single: stage twiddles from one FP64 value per butterfly ("r2")
     std::vector<int> log2l;
     std::vector<int> log2c;
     std::vector<int> inplace;  // per pass: 1 = writes over its own input ("i" suffix)
@@ -54,7 +55,7 @@ std::vector<Decomp> candidate_decompositions(int log2n, fft_layout layout, int r
 
 // kernel lookup; nullptr when no such instance was compiled
 const SingleKernel* find_single(int rb, int log2n, int log2e, int wgt, bool split, bool swap, bool twreg,
-                                bool pf = false, bool stg = false, bool half = false);
+                                bool pf = false, bool stg = false, bool half = false, bool twrec = false);
 const PassKernel* find_pass(int rb, int log2l, int log2c, bool first, bool split_in, bool split_out, bool swap_in,
                             bool swap_out);
 

@@ -88,6 +88,9 @@ struct RaggedArgs {
 constexpr int single_log2e(int log2n) { return log2n <= 12 ? 3 : (log2n == 13 ? 4 : 5); }
 // the 2^14 class exchanges real and imaginary parts in turn (half the LDS)
 constexpr bool single_half(int log2n) { return log2n == 14; }
+// classes whose stage twiddles come from one FP64 value per butterfly
+// (TwRec): 2^13 and 2^14, whose stage tables do not fit in registers
+constexpr bool single_rec(int log2n) { return log2n >= 13; }
 
 template <int LOG2N>
 using RSingle = SingleShape<LOG2N, single_log2e(LOG2N), kThreads>;
@@ -129,18 +132,18 @@ __device__ __forceinline__ uint32_t run_single(const RaggedArgs& a, uint32_t ti,
     // all stage twiddles in registers when they are few, else only the last
     // stage's (the 128-register budget of two 512-thread workgroups per CU);
     // also all of them for 2^12 (24 pairs: a batch of 2^12 transforms 121 ->
-    // 102 us for 2^25 elements; two such classes made the kernel spill); in
-    // the split-layout kernel with 16 points per thread (2^13) none: the table
-    // is L1-resident, and registers for it would make that kernel spill; none
-    // with 32 points per thread either (the data alone takes 64)
-    constexpr bool ALLREG = (SC::NST - 1) * E <= (E == 8 && LOG2N == 12 ? 32 : 16);
-    constexpr bool MEMTW = (SPLIT && !ALLREG && E == 16) || E == 32;
+    // 102 us for 2^25 elements; two such classes made the kernel spill); for
+    // 2^13 and 2^14 (tables too large for registers) one FP64 value per
+    // butterfly and its powers (TwRec)
+    constexpr bool RECTW = single_rec(LOG2N);
+    constexpr bool ALLREG = !RECTW && (SC::NST - 1) * E <= (E == 8 && LOG2N == 12 ? 32 : 16);
+    constexpr bool MEMTW = !RECTW && ((SPLIT && !ALLREG && E == 16) || E == 32);
     using ENG = Engine<SC, SH::G, SH::GS, false, false, SH::WAVE, single_half(LOG2N)>;
     const uint32_t code = static_cast<uint32_t>(LOG2N);
     const float2* tw = a.tw32 + a.tiles[ti].tw_eng;
     using TWT = typename std::conditional<ALLREG, TwReg<SC>, TwLast<SC>>::type;
     TWT twr(tw);
-    if constexpr (!MEMTW) twr.init(tid % T);
+    if constexpr (!MEMTW && !RECTW) twr.init(tid % T);
     do {
         const RaggedTile d = a.tiles[ti];
         int tidl = tid;
@@ -148,16 +151,18 @@ __device__ __forceinline__ uint32_t run_single(const RaggedArgs& a, uint32_t ti,
         const int t = tidl % T, g = tidl / T;
         const bool active = static_cast<uint32_t>(g) < d.count;
         float2 v[E];
-        if constexpr (SPLIT && SH::G == 1) {
-            // split data, one transform per tile: pointers rebased on it
-            // (workgroup-uniform) and 32-bit offsets per lane, so the loads
-            // need no 64-bit address pair each (register budget)
+        if constexpr (SH::G == 1) {
+            // one transform per tile: pointers rebased on it (workgroup-
+            // uniform) and 32-bit offsets per lane, so the loads need no
+            // 64-bit address pair each (register budget)
             const int64_t toff = a.toffs[d.first];
             const float* ia = a.ia + (SPLIT ? toff : 2 * toff);
             const float* ib = SPLIT ? a.ib + toff : nullptr;
+            if constexpr (!SPLIT) loads_begin();
 #pragma unroll
             for (int m = 0; m < E; ++m)
                 v[m] = swap_if<SWAP>(gload_nt<SPLIT>(ia, ib, static_cast<uint32_t>(t + T * m)));
+            if constexpr (!SPLIT) loads_end();
         } else {
             const int64_t base = (active ? a.toffs[d.first + g] : 0) + t;
             // raised load priority for interleaved data, as in the plain kernel
@@ -167,14 +172,18 @@ __device__ __forceinline__ uint32_t run_single(const RaggedArgs& a, uint32_t ti,
                 v[m] = active ? swap_if<SWAP>(gload_nt<SPLIT>(a.ia, a.ib, base + T * m)) : make_float2(0.f, 0.f);
             if constexpr (!SPLIT) loads_end();
         }
-        if constexpr (MEMTW) {
+        if constexpr (RECTW) {
+            const float2* twl = tw;
+            asm volatile("" : "+v"(twl));  // keep the table reads inside the loop
+            ENG::run(v, lds, TwRec<SC>(reinterpret_cast<const double2*>(twl)), tidl);
+        } else if constexpr (MEMTW) {
             const float2* twl = tw;
             asm volatile("" : "+v"(twl));  // keep the table reads inside the loop
             ENG::run(v, lds, TwMem<SC>(twl), tidl);
         } else {
             ENG::run(v, lds, twr, tidl);
         }
-        if constexpr (SPLIT && SH::G == 1) {
+        if constexpr (SH::G == 1) {
             const int64_t toff = a.toffs[d.first];
             float* oa = a.oa + (SPLIT ? toff : 2 * toff);
             float* ob = SPLIT ? a.ob + toff : nullptr;
@@ -550,8 +559,9 @@ fft_status ragged_create(const int64_t* sizes, int64_t count, fft_layout layout,
     eng_single[10] = engine_info<RSingle<10>::SC>();
     eng_single[11] = engine_info<RSingle<11>::SC>();
     eng_single[12] = engine_info<RSingle<12>::SC>();
-    eng_single[13] = engine_info<RSingle<13>::SC>();
-    eng_single[14] = engine_info<RSingle<14>::SC>();
+    static_assert(single_rec(13) && single_rec(14) && !single_rec(12), "recurrence tables for 2^13, 2^14");
+    eng_single[13] = engine_info<RSingle<13>::SC, true>();  // recurrence tables (TwRec)
+    eng_single[14] = engine_info<RSingle<14>::SC, true>();
     EngineInfo eng_pass[kMaxPassLog2 + 1] = {};
     eng_pass[5] = engine_info<RPass<5>::SC>();
     eng_pass[6] = engine_info<RPass<6>::SC>();

@@ -18,6 +18,9 @@ struct EngineInfo {
     bool remfirst;          // smaller radix first
     int nst;                // number of stages
     int tw_size;            // complex entries of the stage twiddle table
+    bool rec;               // recurrence form: per stage w_(Ns*R)^k, k < Ns, as FP64
+                            // pairs (tw_size and tw_off then count FP32 complex
+                            // entries, two per FP64 pair)
     int log2ns[kMaxStages];
     int log2r[kMaxStages];
     int tw_off[kMaxStages];
@@ -40,6 +43,7 @@ struct SingleKernel {
     bool pf;        // next transform's loads issued before the current one's stages
     bool stg;       // small transforms: contiguous loads/stores staged through LDS
     bool half;      // stage exchanges one real part at a time (half the LDS)
+    bool twrec;     // stage twiddles formed from one FP64 table value per butterfly
     single_fn fn;
     const void* kernel;  // the __global__ function (occupancy queries)
     EngineInfo eng;

@@ -141,7 +141,8 @@ def test_half_exchange_decomposition_strings(lib, fftlib):
     """":h1" selects the single-pass kernel whose stages exchange one real part
     at a time; it exists only where compiled (FP32 2^12 .. 2^14, FP64 2^12 and
     2^13), is not combined with another variant, and is the FP32 2^14 default
-    (16 points per thread interleaved, 32 split)."""
+    (16 points per thread interleaved, 32 split, both with the recurrence
+    twiddles)."""
     h = ctypes.c_void_p()
     ex = lib.fft_plan_create_ex
     assert ex(ctypes.byref(h), 4096, 1, 0, -1, 0, b"single:e4:w256:g2:r1:h2") == 2
@@ -150,13 +151,31 @@ def test_half_exchange_decomposition_strings(lib, fftlib):
     assert ex(ctypes.byref(h), 1 << 11, 1, 0, -1, 1, b"single:e3:w256:g2:r0:h1") == 7   # nor FP64 2^11
     for layout in ("interleaved", "split"):
         q = fftlib.query_decomposition(1 << 14, layout, "fp32")
-        e = 5 if layout == "split" else 4
-        assert q["default"] == f"single:e{e}:w256:g8:r0:h1", q["default"]
+        want = "single:e5:w256:g4:r2:h1" if layout == "split" else "single:e4:w256:g8:r2:h1"
+        assert q["default"] == want, q["default"]
         hs = [c for c in q["candidates"] if c.endswith(":h1")]
         assert hs and all(c.startswith(("single:e4:w256:", "single:e5:w256:")) for c in hs)
         # 32 points per thread (radix-32 stages) exists with half-width exchanges only
         e5 = [c for c in q["candidates"] if c.startswith("single:e5:")]
-        assert e5 and all(c.endswith(":r0:h1") for c in e5), e5
+        assert e5 and all(c.endswith((":r0:h1", ":r2:h1")) for c in e5), e5
+
+
+def test_recurrence_twiddle_decomposition_strings(lib, fftlib):
+    """":r2" selects stage twiddles formed from one FP64 table value per
+    butterfly (FP32 2^13 and 2^14 only); r3 is not a spelling, FP64 and real
+    plans have no such kernels."""
+    h = ctypes.c_void_p()
+    ex = lib.fft_plan_create_ex
+    assert ex(ctypes.byref(h), 1 << 14, 1, 0, -1, 0, b"single:e4:w256:g8:r3:h1") == 2
+    assert ex(ctypes.byref(h), 1 << 12, 1, 0, -1, 0, b"single:e4:w256:g2:r2") == 7    # not compiled at 2^12
+    assert ex(ctypes.byref(h), 1 << 13, 1, 0, -1, 1, b"single:e4:w256:g4:r2") == 7    # nor in FP64
+    assert lib.fft_plan_create_real(ctypes.byref(h), 1 << 15, 1, 0, -1, 0, b"single:e4:w256:g8:r2") == 7
+    for log2n, want in ((14, ("single:e4:w256:g8:r2:h1", "single:e5:w256:g8:r2:h1")),
+                        (13, ("single:e4:w256:g4:r2", "single:e5:w256:g4:r2:h1"))):
+        for layout in ("interleaved", "split"):
+            c = fftlib.query_decomposition(1 << log2n, layout, "fp32")["candidates"]
+            for w in want:
+                assert w in c, (log2n, layout, w)
 
 
 def test_staged_decomposition_strings(lib, fftlib):
