@@ -131,12 +131,13 @@ __device__ __forceinline__ uint32_t run_single(const RaggedArgs& a, uint32_t ti,
     constexpr int E = SC::E, T = SC::T;
     // all stage twiddles in registers when they are few, else only the last
     // stage's (the 128-register budget of two 512-thread workgroups per CU);
-    // also all of them for 2^12 (24 pairs: a batch of 2^12 transforms 121 ->
-    // 102 us for 2^25 elements; two such classes made the kernel spill); for
+    // also all of them for 2^10 - 2^12 (24 pairs: a batch of 2^12 transforms
+    // 121 -> 102 us for 2^25 elements, 2^10 and 2^11 15 % faster too; they
+    // fit since the one-transform tiles address through rebased pointers); for
     // 2^13 and 2^14 (tables too large for registers) one FP64 value per
     // butterfly and its powers (TwRec)
     constexpr bool RECTW = single_rec(LOG2N);
-    constexpr bool ALLREG = !RECTW && (SC::NST - 1) * E <= (E == 8 && LOG2N == 12 ? 32 : 16);
+    constexpr bool ALLREG = !RECTW && (SC::NST - 1) * E <= (E == 8 && LOG2N >= 10 ? 32 : 16);
     constexpr bool MEMTW = !RECTW && ((SPLIT && !ALLREG && E == 16) || E == 32);
     using ENG = Engine<SC, SH::G, SH::GS, false, false, SH::WAVE, single_half(LOG2N)>;
     const uint32_t code = static_cast<uint32_t>(LOG2N);
@@ -226,10 +227,10 @@ __device__ __forceinline__ uint32_t run_copy(const RaggedArgs& a, uint32_t ti, i
 
 // Pass tiles of one (pass kind, sub-length) class; the sub-FFT's stage
 // twiddles stay in registers across tiles.  Interleaved workspace between
-// passes, the caller's layout at the ends.  REGALL: the later passes of 128
-// and 256 points keep their stage twiddles in registers too (the pass-only
+// passes, the caller's layout at the ends.  REGALL: the later passes of 64
+// to 256 points keep their stage twiddles in registers too (the pass-only
 // kernel, whose register budget is not shared with the single-pass classes;
-// the 32- and 64-point passes would spill there).
+// the 32-point passes would spill there).
 template <int LOG2L, uint32_t KIND, bool SPLIT, bool SWAP, bool REGALL>
 __device__ __forceinline__ uint32_t run_pass(const RaggedArgs& a, uint32_t ti, float2* lds, int tid) {
     constexpr int LOG2C = kTileLog2 - LOG2L;
@@ -242,7 +243,7 @@ __device__ __forceinline__ uint32_t run_pass(const RaggedArgs& a, uint32_t ti, f
     // later passes also form FP64 pass twiddles; in the kernel that serves
     // every class their stage twiddles come from the (L1-resident) table to
     // stay inside the register budget (registers measured 8 % faster)
-    constexpr bool REG = FIRST || (REGALL && LOG2L >= 7);
+    constexpr bool REG = FIRST || (REGALL && LOG2L >= 6);
     using TWT = typename std::conditional<REG, TwReg<SC>, TwMem<SC>>::type;
     TWT twr(a.tw32 + a.tiles[ti].tw_eng);
     if constexpr (REG) twr.template init_engine<ENG>(tid);
