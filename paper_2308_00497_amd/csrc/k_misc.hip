@@ -35,11 +35,12 @@ __global__ void k_gen_pow64(double2* dst, int log2M, int64_t step, int64_t count
 
 hipError_t launch_gen_engine_tw(const EngineInfo& e, void* dst, int real_bytes, hipStream_t s) {
     if (e.rec) {
-        // recurrence form (FP32 plans only): w_(Ns*R)^k for k < Ns per stage, FP64
-        if (real_bytes != 4) return hipErrorInvalidValue;
+        // recurrence form: w_(Ns*R)^k for k < Ns per stage, FP64 pairs at
+        // offsets counted in complex entries of the plan's precision
+        const size_t entry = real_bytes == 8 ? sizeof(double2) : sizeof(float2);
         for (int st = 1; st < e.nst; ++st) {
-            hipError_t err = launch_gen_pow64(reinterpret_cast<double2*>(static_cast<float2*>(dst) + e.tw_off[st]),
-                                              e.log2ns[st] + e.log2r[st], 1, int64_t(1) << e.log2ns[st], s);
+            double2* t = reinterpret_cast<double2*>(static_cast<char*>(dst) + size_t(e.tw_off[st]) * entry);
+            hipError_t err = launch_gen_pow64(t, e.log2ns[st] + e.log2r[st], 1, int64_t(1) << e.log2ns[st], s);
             if (err != hipSuccess) return err;
         }
         return hipSuccess;

@@ -218,9 +218,10 @@ hipError_t launch_single(const void* ia, const void* ib, void* oa, void* ob, con
     return hipGetLastError();
 }
 
-// REC: the recurrence table (TwRec) - offsets and size in FP32 complex
-// entries, two per FP64 pair, so a float2 buffer holds it 16-byte aligned
-template <class SC, bool REC = false>
+// REC: the recurrence table (TwRec) - offsets and size in complex entries of
+// the plan's precision, PAIR per FP64 pair (2 in a float2 buffer, which then
+// holds it 16-byte aligned; 1 in a double2 buffer)
+template <class SC, bool REC = false, int PAIR = 2>
 EngineInfo engine_info() {
     EngineInfo e{};
     e.log2l = SC::LOG2L;
@@ -228,11 +229,11 @@ EngineInfo engine_info() {
     e.remfirst = SC::REMFIRST;
     e.nst = SC::NST;
     e.rec = REC;
-    e.tw_size = REC ? 2 * SC::REC_SIZE : SC::TW_SIZE;
+    e.tw_size = REC ? PAIR * SC::REC_SIZE : SC::TW_SIZE;
     for (int s = 0; s < SC::NST && s < kMaxStages; ++s) {
         e.log2ns[s] = SC::log2NS(s);
         e.log2r[s] = SC::log2R(s);
-        e.tw_off[s] = REC ? 2 * SC::recOff(s) : SC::twOff(s);
+        e.tw_off[s] = REC ? PAIR * SC::recOff(s) : SC::twOff(s);
     }
     return e;
 }
@@ -425,6 +426,12 @@ __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R
 //
 // The tile loop, with the stream bits in KMASK fixed at compile time to KVAL
 // (pass_tile): the split-array sides take their stream bit as a constant.
+// stage twiddles of a pass kernel in registers (else the recurrence table)
+template <class R, int LOG2L, int LOG2E, int LOG2C>
+constexpr bool pass_regtw() {
+    return PassShape<LOG2L, LOG2E, LOG2C>::THREADS <= 512 && sizeof(R) == 4;
+}
+
 template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN,
           bool SWAP_OUT, int KMASK, int KVAL>
 __device__ __forceinline__ void pass_loop(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw,
@@ -437,8 +444,9 @@ __device__ __forceinline__ void pass_loop(const R* ia, const R* ib, R* oa, R* ob
     using ENG = Engine<SC, SH::C, SH::GS, true, !FIRST, false>;
     // stage twiddles in registers unless the workgroup is so large (1024
     // threads: at most 128 registers per lane) that they would spill, or the
-    // elements are FP64 (twice the registers per entry)
-    constexpr bool REGTW = SH::THREADS <= 512 && sizeof(R) == 4;
+    // elements are FP64 (twice the registers per entry); else one FP64 table
+    // value per butterfly and its powers (TwRec)
+    constexpr bool REGTW = pass_regtw<R, LOG2L, LOG2E, LOG2C>();
     const int tid = threadIdx.x;
     TwReg<SC, V> twr(tw);
     if constexpr (REGTW) twr.template init_engine<ENG>(tid);
@@ -458,9 +466,9 @@ __device__ __forceinline__ void pass_loop(const R* ia, const R* ib, R* oa, R* ob
                       KMASK, KVAL>(ia, ib, oa, ob, twr, ta, tb, log2N, log2Ns, hbits, b << log2N, j0, lds, tidl,
                                    stream, twshift, ain, aout);
         else
-            pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT, TwMem<SC, V>, R, true,
-                      KMASK, KVAL>(ia, ib, oa, ob, TwMem<SC, V>(tw), ta, tb, log2N, log2Ns, hbits, b << log2N, j0,
-                                   lds, tidl, stream, twshift, ain, aout);
+            pass_tile<LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT, TwRec<SC, V>, R, true,
+                      KMASK, KVAL>(ia, ib, oa, ob, TwRec<SC, V>(reinterpret_cast<const double2*>(tw)), ta, tb, log2N,
+                                   log2Ns, hbits, b << log2N, j0, lds, tidl, stream, twshift, ain, aout);
     }
 }
 
@@ -527,7 +535,7 @@ PassKernel pass_entry() {
     k.fn = &launch_pass<R, LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>;
     k.kernel =
         reinterpret_cast<const void*>(&k_pass<R, LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>);
-    k.eng = engine_info<typename SH::SC>();
+    k.eng = engine_info<typename SH::SC, !pass_regtw<R, LOG2L, LOG2E, LOG2C>(), sizeof(R) == 4 ? 2 : 1>();
     k.threads = SH::THREADS;
     k.lds_bytes = SH::LDS * sizeof(cplx_t<R>);
     return k;
