@@ -41,6 +41,13 @@ static const SingleKernel kSingle64[] = {
         single_entry<double, n, e, 256, true, false, r, false, false, true>()
     FFT_DH(12, 3, true), FFT_DH(12, 3, false), FFT_DH(12, 4, false), FFT_DH(13, 4, false), FFT_DH(13, 3, false),
 #undef FFT_DH
+    // stage twiddles from one FP64 table value per butterfly and its powers
+#define FFT_DR(n, e, h)                                                                                     \
+    single_entry<double, n, e, 256, false, false, false, false, false, h, true>(),                          \
+        single_entry<double, n, e, 256, false, true, false, false, false, h, true>(),                       \
+        single_entry<double, n, e, 256, true, false, false, false, false, h, true>()
+    FFT_DR(13, 4, true), FFT_DR(13, 3, true), FFT_DR(12, 3, true),
+#undef FFT_DR
 };
 
 #undef FFT_D

@@ -86,7 +86,7 @@ k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ t
     constexpr int E = SC::E, T = SC::T, L = SC::L, G = SH::G;
     static_assert(!(STG && PF), "staging and prefetching are separate variants");
     static_assert(!(STG && HALF), "staged transforms use the complex exchange");
-    static_assert(!TWREC || (!TWREG && !STG && sizeof(R) == 4), "the recurrence twiddles serve FP32 plain kernels");
+    static_assert(!TWREC || (!TWREG && !STG), "the recurrence twiddles serve the unstaged table kernels");
     static_assert(!STG || (SH::WAVE && (64 % T) == 0 && SH::THREADS % 64 == 0),
                   "staging needs every transform inside one wavefront");
     __shared__ V lds[single_lds<LOG2N, LOG2E, WGT, STG, HALF>()];
@@ -256,7 +256,7 @@ SingleKernel single_entry() {
     k.twrec = TWREC;
     k.fn = &launch_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG, HALF, TWREC>;
     k.kernel = reinterpret_cast<const void*>(&k_single<R, LOG2N, LOG2E, WGT, SPLIT, SWAP, TWREG, PF, STG, HALF, TWREC>);
-    k.eng = engine_info<typename SH::SC, TWREC>();
+    k.eng = engine_info<typename SH::SC, TWREC, sizeof(R) == 4 ? 2 : 1>();
     k.threads = SH::THREADS;
     k.per_wg = SH::G;
     k.lds_bytes = single_lds<LOG2N, LOG2E, WGT, STG, HALF>() * sizeof(cplx_t<R>);

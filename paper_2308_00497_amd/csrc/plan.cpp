@@ -217,11 +217,13 @@ static std::vector<int> even_split(int log2n, int parts) {
 // their middle pass in place (2^24 split: 351 -> 287 us)
 static Decomp default_decomposition64(int log2n, fft_layout layout) {
     // 2^13: half-width exchanges (two workgroups per CU instead of one;
-    // 2^25 elements: interleaved 269 -> 256 us, split 279 -> 280 us)
-    static const struct { int log2e, wgt, gmul, twreg, pf, half; } single[14] = {
+    // 2^25 elements: interleaved 269 -> 256 us, split 279 -> 280 us), and the
+    // stage twiddles from one table value per butterfly (tw 2: interleaved
+    // 260-269 -> 200 us, split 289 -> 228 us; tw 1 = registers, 0 = table)
+    static const struct { int log2e, wgt, gmul, tw, pf, half; } single[14] = {
         {4, 256, 1, 1, 0, 0}, {4, 256, 2, 0, 0, 0}, {4, 64, 3, 0, 0, 0}, {4, 64, 1, 0, 0, 0}, {3, 256, 8, 1, 0, 0},
         {3, 256, 8, 1, 0, 0}, {3, 256, 1, 1, 0, 0}, {3, 64, 3, 1, 0, 0}, {3, 64, 3, 1, 0, 0}, {3, 64, 4, 1, 0, 0},
-        {3, 256, 2, 1, 0, 0}, {3, 256, 2, 1, 0, 0}, {3, 256, 1, 1, 1, 0}, {4, 256, 3, 0, 0, 1},  // 2^10 .. 2^13
+        {3, 256, 2, 1, 0, 0}, {3, 256, 2, 1, 0, 0}, {3, 256, 1, 1, 1, 0}, {4, 256, 3, 2, 0, 1},  // 2^10 .. 2^13
     };
     static const char* multi_il[kMaxLog2N + 1] = {
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
@@ -262,9 +264,20 @@ static Decomp default_decomposition64(int log2n, fft_layout layout) {
         d.log2e = single[log2n].log2e;
         d.wgt = single[log2n].wgt;
         d.gmul = single[log2n].gmul;
-        d.twreg = single[log2n].twreg == 1;
+        d.twreg = single[log2n].tw == 1;
+        d.twrec = single[log2n].tw == 2;
         d.pf = single[log2n].pf == 1;
         d.half = single[log2n].half == 1;
+        // split 2^12: half-width exchanges and the recurrence twiddles at 8
+        // workgroups per CU's worth of grid (231 -> 195 us for 2^25 elements;
+        // interleaved the prefetching kernel stays ahead, 177 against 190 us)
+        if (log2n == 12 && layout == FFT_LAYOUT_SPLIT) {
+            d.gmul = 8;
+            d.twreg = false;
+            d.twrec = true;
+            d.pf = false;
+            d.half = true;
+        }
     } else {
         Decomp::parse(multi[log2n], &d);
     }
