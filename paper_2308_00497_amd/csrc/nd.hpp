@@ -22,7 +22,7 @@ k_strided(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ 
     using SH = PassShape<LOG2L, 4, LOG2C>;
     using SC = typename SH::SC;
     using ENG = Engine<SC, SH::C, SH::GS, true, true, false>;
-    constexpr bool REGTW = SH::THREADS <= 512 && sizeof(R) == 4;
+    constexpr bool REGTW = pass_regtw<R, LOG2L, 4, LOG2C>();  // else the recurrence table
     __shared__ V lds[SH::LDS];
     const int tid = threadIdx.x;
     TwReg<SC, V> twr(tw);
@@ -38,8 +38,9 @@ k_strided(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ 
             pass_tile<LOG2L, 4, LOG2C, false, SPLIT, SPLIT, SWAP, SWAP, TwReg<SC, V>, R, false, 3, 0>(
                 ia, ib, oa, ob, twr, nullptr, nullptr, log2s + LOG2L, log2s, 0, tbase, j0, lds, tidl, 0);
         else
-            pass_tile<LOG2L, 4, LOG2C, false, SPLIT, SPLIT, SWAP, SWAP, TwMem<SC, V>, R, false, 3, 0>(
-                ia, ib, oa, ob, TwMem<SC, V>(tw), nullptr, nullptr, log2s + LOG2L, log2s, 0, tbase, j0, lds, tidl, 0);
+            pass_tile<LOG2L, 4, LOG2C, false, SPLIT, SPLIT, SWAP, SWAP, TwRec<SC, V>, R, false, 3, 0>(
+                ia, ib, oa, ob, TwRec<SC, V>(reinterpret_cast<const double2*>(tw)), nullptr, nullptr, log2s + LOG2L,
+                log2s, 0, tbase, j0, lds, tidl, 0);
     }
 }
 
@@ -98,7 +99,7 @@ StridedKernel strided_entry() {
     k.swap = SWAP;
     k.fn = &launch_strided<R, LOG2L, LOG2C, SPLIT, SWAP>;
     k.kernel = reinterpret_cast<const void*>(&k_strided<R, LOG2L, LOG2C, SPLIT, SWAP>);
-    k.eng = engine_info<typename SH::SC>();
+    k.eng = engine_info<typename SH::SC, !pass_regtw<R, LOG2L, 4, LOG2C>(), sizeof(R) == 4 ? 2 : 1>();
     k.threads = SH::THREADS;
     k.lds_bytes = SH::LDS * sizeof(cplx_t<R>);
     return k;
