@@ -304,8 +304,9 @@ fft_status resolve_real(fft_plan p, const Decomp& dec) {
             add_wn_tables();
             break;
         case Decomp::SINGLE:
-            p->rk = fftk::find_real(p->rb, p->log2h, dec.log2e, dec.wgt, c2r, split, dec.twreg, dec.stg);
-            p->rk_adj = fftk::find_real(p->rb, p->log2h, dec.log2e, dec.wgt, !c2r, split, dec.twreg, dec.stg);
+            p->rk = fftk::find_real(p->rb, p->log2h, dec.log2e, dec.wgt, c2r, split, dec.twreg, dec.stg, dec.twrec);
+            p->rk_adj =
+                fftk::find_real(p->rb, p->log2h, dec.log2e, dec.wgt, !c2r, split, dec.twreg, dec.stg, dec.twrec);
             if (!p->rk || !p->rk_adj) return FFT_ERR_NOT_SUPPORTED;
             p->twe_n = p->rk->eng.tw_size;
             break;

@@ -182,6 +182,14 @@ static const RealKernel kReal[] = {
     FFT_RS(4, 4), FFT_RS(5, 4), FFT_RS(6, 4), FFT_RS(7, 4), FFT_RS(8, 4), FFT_RS(9, 4), FFT_RS(10, 4),
     FFT_RS(11, 4), FFT_RS(12, 4), FFT_RS(13, 4),
     FFT_RS1(14, 4, false),
+    // the largest half lengths: stage twiddles as one FP64 value per butterfly
+#define FFT_RR(h, e)                                                                                          \
+    real_entry<float, h, e, 256, false, false, false, false, true>(),                                         \
+        real_entry<float, h, e, 256, false, true, false, false, true>(),                                      \
+        real_entry<float, h, e, 256, true, false, false, false, true>(),                                      \
+        real_entry<float, h, e, 256, true, true, false, false, true>()
+    FFT_RR(13, 3), FFT_RR(13, 4), FFT_RR(14, 4),
+#undef FFT_RR
     // short rows (whole rows inside one wavefront): staged through LDS
 #define FFT_RT(h, e)                                                                                          \
     real_entry<float, h, e, 256, false, false, true, true>(), real_entry<float, h, e, 256, false, true, true, true>(), \

@@ -14,6 +14,14 @@ static const RealKernel kReal64[] = {
     FFT_RD(11, 3), FFT_RD1(12, 3, false), FFT_RD1(13, 3, false),
     FFT_RD(4, 4), FFT_RD(5, 4), FFT_RD(6, 4), FFT_RD(7, 4), FFT_RD(8, 4), FFT_RD1(9, 4, false),
     FFT_RD1(10, 4, false), FFT_RD1(11, 4, false), FFT_RD1(12, 4, false), FFT_RD1(13, 4, false),
+    // the largest half lengths: stage twiddles as one FP64 value per butterfly
+#define FFT_RR(h, e)                                                                                          \
+    real_entry<double, h, e, 256, false, false, false, false, true>(),                                        \
+        real_entry<double, h, e, 256, false, true, false, false, true>(),                                     \
+        real_entry<double, h, e, 256, true, false, false, false, true>(),                                     \
+        real_entry<double, h, e, 256, true, true, false, false, true>()
+    FFT_RR(12, 3), FFT_RR(12, 4), FFT_RR(13, 3), FFT_RR(13, 4),
+#undef FFT_RR
     // short rows (whole rows inside one wavefront): staged through LDS
 #define FFT_RT(h, e)                                                                                          \
     real_entry<double, h, e, 256, false, false, true, true>(), real_entry<double, h, e, 256, false, true, true, true>(), \

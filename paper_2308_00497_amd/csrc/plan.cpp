@@ -376,13 +376,14 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout, int64_t batch
     return d;
 }
 
-const RealKernel* find_real(int rb, int log2h, int log2e, int wgt, bool c2r, bool split, bool twreg, bool stg) {
+const RealKernel* find_real(int rb, int log2h, int log2e, int wgt, bool c2r, bool split, bool twreg, bool stg,
+                            bool twrec) {
     int cnt = 0;
     const RealKernel* t = rb == 8 ? real_kernels64(&cnt) : real_kernels(&cnt);
     const int le = log2e < log2h ? log2e : log2h;
     for (int i = 0; i < cnt; ++i)
         if (t[i].log2h == log2h && t[i].log2e == le && t[i].wgt == wgt && t[i].c2r == c2r && t[i].split == split &&
-            t[i].twreg == twreg && t[i].stg == stg)
+            t[i].twreg == twreg && t[i].stg == stg && t[i].twrec == twrec)
             return &t[i];
     return nullptr;
 }
@@ -397,8 +398,8 @@ bool real_decomposition_available(const Decomp& d, int log2n, fft_layout layout,
         case Decomp::COPY:
             return log2h == 0;
         case Decomp::SINGLE:
-            return log2h >= 1 && !d.pf && !d.half && !d.twrec &&
-                   find_real(rb, log2h, d.log2e, d.wgt, c2r, split, d.twreg, d.stg) != nullptr;
+            return log2h >= 1 && !d.pf && !d.half &&
+                   find_real(rb, log2h, d.log2e, d.wgt, c2r, split, d.twreg, d.stg, d.twrec) != nullptr;
         case Decomp::MULTI: {
             // the half-length chain runs on interleaved data in both directions
             int sum = 0;
@@ -427,21 +428,25 @@ bool real_decomposition_available(const Decomp& d, int log2n, fft_layout layout,
 // both layouts, where the staged kernel wins; N = 4096 re-measured on rows
 // not in any cache: e3 g3 49.6 us against e4 g2 52-54 us for 8192 rows),
 // indexed by log2 N; above the single-pass limit, the half length's complex
-// pass chain.
+// pass chain.  tw: stage twiddles from the table (0), in registers (1), or as
+// one FP64 value per butterfly (2: the two largest sizes of each precision,
+// R2C + C2R FP32 2^14 152-165 -> 131 us interleaved and 183 -> 133 us split,
+// 2^15 186 -> 154 and 200 -> 166 us; FP64 2^13 138-146 -> 107-109 and 139 ->
+// 112 us, 2^14 173 -> 138 and 177 -> 143 us).
 struct RealShapeChoice {
-    int log2e, gmul, twreg, stg;
+    int log2e, gmul, tw, stg;
 };
 
 Decomp default_real_decomposition(int log2n, int rb) {
     static const RealShapeChoice r32[16] = {
         {4, 1, 1, 0}, {4, 1, 1, 0}, {3, 4, 1, 1}, {4, 4, 1, 1}, {3, 3, 1, 1}, {3, 3, 1, 1}, {3, 3, 1, 1},  // 2^0 .. 2^6
         {3, 3, 1, 1}, {3, 3, 1, 1}, {3, 2, 1, 0}, {3, 2, 1, 0}, {4, 2, 1, 0}, {3, 3, 1, 0}, {3, 2, 1, 0},  // 2^7 .. 2^13
-        {3, 8, 0, 0}, {4, 1, 0, 0},                                                                        // 2^14 .. 2^15
+        {4, 8, 2, 0}, {4, 1, 2, 0},                                                                        // 2^14 .. 2^15
     };
     static const RealShapeChoice r64[15] = {
         {4, 1, 1, 0}, {4, 1, 1, 0}, {3, 3, 1, 1}, {3, 8, 1, 1}, {3, 8, 1, 1}, {3, 2, 1, 1}, {3, 2, 1, 1},  // 2^0 .. 2^6
-        {3, 2, 1, 1}, {3, 2, 1, 1}, {3, 2, 1, 0}, {3, 2, 1, 0}, {3, 2, 1, 0}, {3, 2, 1, 0}, {4, 4, 0, 0},  // 2^7 .. 2^13
-        {4, 1, 0, 0},                                                                                      // 2^14
+        {3, 2, 1, 1}, {3, 2, 1, 1}, {3, 2, 1, 0}, {3, 2, 1, 0}, {3, 2, 1, 0}, {3, 2, 1, 0}, {4, 8, 2, 0},  // 2^7 .. 2^13
+        {4, 1, 2, 0},                                                                                      // 2^14
     };
     const int log2h = log2n - 1;
     Decomp d;
@@ -456,7 +461,8 @@ Decomp default_real_decomposition(int log2n, int rb) {
     d.log2e = t.log2e;
     d.wgt = 256;
     d.gmul = t.gmul;
-    d.twreg = t.twreg == 1;
+    d.twreg = t.tw == 1;
+    d.twrec = t.tw == 2;
     d.stg = t.stg == 1;
     return d;
 }

@@ -72,7 +72,7 @@ bool decomposition_available(const Decomp& d, int log2n, fft_layout layout, int 
 // "single:..." for the fused single-pass kernel, "multi:..." for the
 // half-length pass chain plus one pre/post pass.  N = 1 has no decomposition.
 const RealKernel* find_real(int rb, int log2h, int log2e, int wgt, bool c2r, bool split, bool twreg,
-                            bool stg = false);
+                            bool stg = false, bool twrec = false);
 Decomp default_real_decomposition(int log2n, int rb);
 bool real_decomposition_available(const Decomp& d, int log2n, fft_layout layout, int rb, bool c2r);
 

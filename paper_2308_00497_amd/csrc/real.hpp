@@ -86,7 +86,8 @@ constexpr int real_lds() {
 // takes elements l, l + 64, ...), staged through LDS rows of H + 1 values, so
 // that no access is a short strided one; C2R then pairs X[k] with X[H - k]
 // straight from the staged rows.
-template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG, bool STG = false>
+template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG, bool STG = false,
+          bool TWREC = false>
 __global__ void __launch_bounds__((SingleShape<LOG2H, LOG2E, WGT>::THREADS))
 k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw,
               const cplx_t<R>* __restrict__ twn, int64_t batch, R iscale) {
@@ -99,6 +100,7 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
     static_assert(LOG2H >= 1, "H = 1 runs as a pre/post pass only");
     static_assert(!STG || (SH::WAVE && (64 % T) == 0 && SH::THREADS % 64 == 0),
                   "staging needs whole rows inside one wavefront");
+    static_assert(!TWREC || (!TWREG && !STG), "the recurrence twiddles serve the unstaged table kernels");
     __shared__ V lds[real_lds<R, LOG2H, LOG2E, WGT, STG>()];
     V* const xch = RS::SEP ? lds + RS::EX : lds;  // pairing exchange region
     V* const stg = lds + RS::LDS;                 // staged rows (STG), stride H + 1
@@ -145,6 +147,7 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
 #pragma unroll
                 for (int m = 0; m < E; ++m) v[m] = stg[gl * SGS + tl + T * m];
                 if constexpr (TWREG) ENG::run(v, lds, twr, tidl);
+                else if constexpr (TWREC) ENG::run(v, lds, TwRec<SC, V>(reinterpret_cast<const double2*>(twl)), tidl);
                 else ENG::run(v, lds, TwMem<SC, V>(twl), tidl);
                 if constexpr (!RS::SEP) stage_sync<true>();
 #pragma unroll
@@ -203,6 +206,7 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
                     v[m] = swap_if<true>(k == 0 ? zk : c_scale(zk, iscale));
                 }
                 if constexpr (TWREG) ENG::run(v, lds, twr, tidl);
+                else if constexpr (TWREC) ENG::run(v, lds, TwRec<SC, V>(reinterpret_cast<const double2*>(twl)), tidl);
                 else ENG::run(v, lds, TwMem<SC, V>(twl), tidl);
                 stage_sync<true>();  // every lane's reads of the staged input rows are done
 #pragma unroll
@@ -225,6 +229,7 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
             for (int m = 0; m < E; ++m) v[m] = active ? gload_nt<false>(ia, ia, base + T * m) : c_zero<V>();
             loads_end();
             if constexpr (TWREG) ENG::run(v, lds, twr, tidl);
+            else if constexpr (TWREC) ENG::run(v, lds, TwRec<SC, V>(reinterpret_cast<const double2*>(twl)), tidl);
             else ENG::run(v, lds, TwMem<SC, V>(twl), tidl);
             if constexpr (!RS::SEP) stage_sync<SH::WAVE>();  // the engine's last reads of LDS are done
 #pragma unroll
@@ -271,6 +276,7 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
                 v[m] = swap_if<true>(k == 0 ? zk : c_scale(zk, iscale));
             }
             if constexpr (TWREG) ENG::run(v, lds, twr, tidl);
+            else if constexpr (TWREC) ENG::run(v, lds, TwRec<SC, V>(reinterpret_cast<const double2*>(twl)), tidl);
             else ENG::run(v, lds, TwMem<SC, V>(twl), tidl);
             if (active) {
                 const int64_t base = tr * H + tl;
@@ -281,21 +287,23 @@ k_real_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restric
     }
 }
 
-template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG, bool STG = false>
+template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG, bool STG = false,
+          bool TWREC = false>
 hipError_t launch_real_single(const void* ia, const void* ib, void* oa, void* ob, const void* tw, const void* twn,
                               int64_t batch, int grid, double iscale, hipStream_t s) {
     using SH = SingleShape<LOG2H, LOG2E, WGT>;
     const int64_t groups = (batch + SH::G - 1) / SH::G;
     const int64_t blocks = groups < grid ? groups : grid;
     if (blocks < 1) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG, STG>), dim3(static_cast<unsigned>(blocks)),
+    hipLaunchKernelGGL((k_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG, STG, TWREC>), dim3(static_cast<unsigned>(blocks)),
                        dim3(SH::THREADS), 0, s, static_cast<const R*>(ia), static_cast<const R*>(ib),
                        static_cast<R*>(oa), static_cast<R*>(ob), static_cast<const cplx_t<R>*>(tw),
                        static_cast<const cplx_t<R>*>(twn), batch, static_cast<R>(iscale));
     return hipGetLastError();
 }
 
-template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG, bool STG = false>
+template <class R, int LOG2H, int LOG2E, int WGT, bool C2R, bool SPLIT, bool TWREG, bool STG = false,
+          bool TWREC = false>
 RealKernel real_entry() {
     using SH = SingleShape<LOG2H, LOG2E, WGT>;
     RealKernel k{};
@@ -307,9 +315,10 @@ RealKernel real_entry() {
     k.split = SPLIT;
     k.twreg = TWREG;
     k.stg = STG;
-    k.fn = &launch_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG, STG>;
-    k.kernel = reinterpret_cast<const void*>(&k_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG, STG>);
-    k.eng = engine_info<typename SH::SC>();
+    k.twrec = TWREC;
+    k.fn = &launch_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG, STG, TWREC>;
+    k.kernel = reinterpret_cast<const void*>(&k_real_single<R, LOG2H, LOG2E, WGT, C2R, SPLIT, TWREG, STG, TWREC>);
+    k.eng = engine_info<typename SH::SC, TWREC, sizeof(R) == 4 ? 2 : 1>();
     k.threads = SH::THREADS;
     k.per_wg = SH::G;
     k.lds_bytes = real_lds<R, LOG2H, LOG2E, WGT, STG>() * sizeof(cplx_t<R>);

@@ -104,6 +104,7 @@ struct RealKernel {
     bool split;     // complex side split into re/im arrays
     bool twreg;
     bool stg;       // short rows: contiguous loads/stores staged through LDS
+    bool twrec;     // stage twiddles as one FP64 value per butterfly and its powers
     real_fn fn;
     const void* kernel;
     EngineInfo eng;

@@ -162,14 +162,18 @@ def test_half_exchange_decomposition_strings(lib, fftlib):
 
 def test_recurrence_twiddle_decomposition_strings(lib, fftlib):
     """":r2" selects stage twiddles formed from one FP64 table value per
-    butterfly (FP32 2^13 and 2^14 only); r3 is not a spelling, FP64 and real
-    plans have no such kernels."""
+    butterfly, compiled for the largest single-pass sizes only (complex FP32
+    2^13 and 2^14, FP64 2^12 and 2^13 in some shapes; real half lengths FP32
+    2^13 and 2^14, FP64 2^12 and 2^13); r3 is not a spelling."""
     h = ctypes.c_void_p()
     ex = lib.fft_plan_create_ex
     assert ex(ctypes.byref(h), 1 << 14, 1, 0, -1, 0, b"single:e4:w256:g8:r3:h1") == 2
     assert ex(ctypes.byref(h), 1 << 12, 1, 0, -1, 0, b"single:e4:w256:g2:r2") == 7    # not compiled at 2^12
     assert ex(ctypes.byref(h), 1 << 13, 1, 0, -1, 1, b"single:e4:w256:g4:r2") == 7    # nor in FP64
-    assert lib.fft_plan_create_real(ctypes.byref(h), 1 << 15, 1, 0, -1, 0, b"single:e4:w256:g8:r2") == 7
+    real = lib.fft_plan_create_real
+    assert real(ctypes.byref(h), 1 << 12, 1, 0, -1, 0, b"single:e4:w256:g8:r2") == 7   # half length 2^11
+    assert real(ctypes.byref(h), 1 << 15, 1, 0, -1, 0, b"single:e4:w256:g8:r2:h1") == 7  # no half-width real kernel
+    assert real(ctypes.byref(h), 1 << 15, 1, 0, -1, 0, b"single:e4:w256:g8:r2:s1") == 7  # staged kernels: registers
     for log2n, want in ((14, ("single:e4:w256:g8:r2:h1", "single:e5:w256:g8:r2:h1")),
                         (13, ("single:e4:w256:g4:r2", "single:e5:w256:g4:r2:h1"))):
         for layout in ("interleaved", "split"):

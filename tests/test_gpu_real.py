@@ -94,9 +94,10 @@ def test_c2r_sweep(fftlib, log2n, layout, precision):
 @pytest.mark.parametrize("precision,log2n", [(p, k) for p in ("fp32", "fp64") for k in (2, 3, 4, 5, 6, 8, 10, 13, 14, 15)
                                              if not (p == "fp64" and k == 15)])
 def test_every_real_single_variant(fftlib, log2n, precision):
-    """Both twiddle sources, plain and staged (short rows), and every compiled
-    shape of the fused kernel (half lengths up to the single-pass limit: 2^14
-    FP32, 2^13 FP64), forward and backward."""
+    """Every stage-twiddle source (table, registers, and at the largest half
+    lengths one FP64 value per butterfly), plain and staged (short rows), and
+    every compiled shape of the fused kernel (half lengths up to the
+    single-pass limit: 2^14 FP32, 2^13 FP64), forward and backward."""
     n = 1 << log2n
     dt, tol = PREC[precision]
     x = real_rows(batch_for(n), n, 8200 + log2n, dt)
@@ -107,9 +108,9 @@ def test_every_real_single_variant(fftlib, log2n, precision):
     ref_bf = r2c_vjp_definition(g_c, n)           # backward of R2C
     ref_bi = oracle.rfft(x.astype(np.float64), threads=8)
     ref_bi[:, 1:n // 2] *= 2.0                     # backward of C2R (pinned on the CPU)
-    seen = staged = 0
+    seen = staged = rec = 0
     for e in (3, 4):
-        for r in (0, 1):
+        for r in (0, 1, 2):
             for var in ("", ":s1"):
                 dec = f"single:e{e}:w256:g2:r{r}{var}"
                 for layout in ("interleaved", "split"):
@@ -130,8 +131,10 @@ def test_every_real_single_variant(fftlib, log2n, precision):
                     assert_parity(gb, ref_bi, f"C2R backward {precision} n=2^{log2n} {layout} {dec}", tol)
                     seen += 1
                     staged += var == ":s1"
+                    rec += r == 2
     assert seen > 0
     assert staged > 0 or log2n > 8
+    assert rec > 0 or log2n < (13 if precision == "fp64" else 14)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
