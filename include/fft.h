@@ -92,11 +92,15 @@ fft_status fft_plan_create(fft_plan *out, int64_t n, int64_t batch,
                            fft_layout layout, fft_direction dir);
 
 /* As fft_plan_create, with the decomposition given explicitly instead of
- * chosen: "single:e<log2 E>:w<threads>:g<G>:r<0|1>" (persistent single-pass
- * kernel, 2^E elements per thread, workgroups of at least <threads> threads,
- * G workgroups per compute unit, stage twiddles in registers if r1) or
+ * chosen: "single:e<log2 E>:w<threads>:g<G>:r<0|1|2>[:p1|:s1|:h1]"
+ * (persistent single-pass kernel, 2^E elements per thread, workgroups of at
+ * least <threads> threads, G workgroups per compute unit; stage twiddles read
+ * from the table (r0), held in registers (r1), or formed from one FP64 table
+ * value per butterfly (r2); optionally the prefetching (p1), LDS-staged short
+ * transform (s1) or half-width-exchange (h1) variant) or
  * "multi:<log2 L1>c<log2 C1>,<log2 L2>c<log2 C2>,..." (one pass per sub-FFT
- * length L_p with C_p columns per workgroup; the log2 L_p sum to log2 n), or
+ * length L_p with C_p columns per workgroup; the log2 L_p sum to log2 n; an
+ * "i" after the penultimate pass of three or more runs it in place), or
  * "copy" for n = 1 - the strings fft_plan_describe and
  * fft_query_decomposition report - or "ops:r<log2 R>", the per-operator
  * baseline (Table 1's Permute, FusedIKMV, Mul and FusedMKIV as one kernel each,
