@@ -183,11 +183,14 @@ k_single(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ t
             }
         } else if (active) {
             // raised load priority: measured faster for interleaved data
-            // (N = 4096: 97 -> 92 us), slower for split data at N = 8192
-            if constexpr (!SPLIT) loads_begin();
+            // (N = 4096: 97 -> 92 us) and for FP32 split data at N = 4096
+            // (batch 1024: 15.2 -> 14.6 us; batch 8192: 0-1 %), slower for
+            // split data at N = 8192
+            constexpr bool PRIO = !SPLIT || (LOG2N == 12 && sizeof(R) == 4);
+            if constexpr (PRIO) loads_begin();
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = swap_if<SWAP>(gload_nt<SPLIT>(ia, ib, base + T * m));
-            if constexpr (!SPLIT) loads_end();
+            if constexpr (PRIO) loads_end();
         } else {
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = c_zero<V>();
