@@ -280,6 +280,27 @@ struct PassShape {
     static constexpr int LDS = C * GS;
 };
 
+// FP32 first-pass tiles whose complex exchange would need more than 80 KB of
+// LDS (one workgroup per CU) exchange the real and the imaginary parts in
+// turn through half of it, so that two workgroups fit on a CU; their register
+// allocation is then held to what two workgroups allow (the first pass forms
+// no pass twiddles and fits; later passes would spill)
+template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST>
+constexpr bool pass_half() {
+    return FIRST && sizeof(R) == 4 && PassShape<LOG2L, LOG2E, LOG2C>::LDS * 8 > 80 * 1024;
+}
+template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST>
+constexpr int pass_lds() {
+    constexpr int L = PassShape<LOG2L, LOG2E, LOG2C>::LDS;
+    return pass_half<R, LOG2L, LOG2E, LOG2C, FIRST>() ? (L + 1) / 2 : L;
+}
+// minimum waves per SIMD for the launch bounds: two workgroups per CU with
+// half-width exchanges, else no constraint
+template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST>
+constexpr int pass_waves() {
+    return pass_half<R, LOG2L, LOG2E, LOG2C, FIRST>() ? 2 * PassShape<LOG2L, LOG2E, LOG2C>::THREADS / 256 : 1;
+}
+
 // One tile of one pass: C consecutive butterfly columns j0 .. j0+C-1 of the
 // transform starting at element tbase.  Shared by the pass kernel and the
 // ragged persistent kernel.  `lds` holds PassShape::LDS complex elements; TW
@@ -377,7 +398,7 @@ __device__ __forceinline__ void pass_tile(const R* ia, const typename nodeduce<R
 
     // first pass stores whole columns (thread-fast), later passes store runs of
     // C consecutive columns (column-fast)
-    Engine<SC, C, SH::GS, true, !FIRST, false>::run(v, lds, tw, tid);
+    Engine<SC, C, SH::GS, true, !FIRST, false, pass_half<R, LOG2L, LOG2E, LOG2C, FIRST>()>::run(v, lds, tw, tid);
 
     if constexpr (FIRST) {
         const int t = tid % T, c = tid / T;
@@ -477,12 +498,11 @@ __device__ __forceinline__ void pass_loop(const R* ia, const R* ib, R* oa, R* ob
 
 template <class R, int LOG2L, int LOG2E, int LOG2C, bool FIRST, bool SPLIT_IN, bool SPLIT_OUT, bool SWAP_IN,
           bool SWAP_OUT>
-__global__ void __launch_bounds__((PassShape<LOG2L, LOG2E, LOG2C>::THREADS))
+__global__ void __launch_bounds__((PassShape<LOG2L, LOG2E, LOG2C>::THREADS), (pass_waves<R, LOG2L, LOG2E, LOG2C, FIRST>()))
 k_pass(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw, const double2* __restrict__ ta,
        const double2* __restrict__ tb, int log2N, int log2Ns, int hbits, int64_t tiles, int stream, int twshift,
        int ain, int aout) {
-    using SH = PassShape<LOG2L, LOG2E, LOG2C>;
-    __shared__ cplx_t<R> lds[SH::LDS];
+    __shared__ cplx_t<R> lds[pass_lds<R, LOG2L, LOG2E, LOG2C, FIRST>()];
 #define FFTK_PASS_LOOP(KM, KV)                                                                                   \
     pass_loop<R, LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT, KM, KV>(                    \
         ia, ib, oa, ob, tw, ta, tb, log2N, log2Ns, hbits, tiles, stream, twshift, ain, aout, lds)
@@ -540,7 +560,7 @@ PassKernel pass_entry() {
         reinterpret_cast<const void*>(&k_pass<R, LOG2L, LOG2E, LOG2C, FIRST, SPLIT_IN, SPLIT_OUT, SWAP_IN, SWAP_OUT>);
     k.eng = engine_info<typename SH::SC, !pass_regtw<R, LOG2L, LOG2E, LOG2C>(), sizeof(R) == 4 ? 2 : 1>();
     k.threads = SH::THREADS;
-    k.lds_bytes = SH::LDS * sizeof(cplx_t<R>);
+    k.lds_bytes = pass_lds<R, LOG2L, LOG2E, LOG2C, FIRST>() * sizeof(cplx_t<R>);
     return k;
 }
 

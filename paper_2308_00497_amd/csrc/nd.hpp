@@ -16,14 +16,14 @@ namespace fftk {
 // (tiles = B * s / C), in place or out of place; the inverse swaps re/im of
 // interleaved data in the kernel (split data: the caller swaps pointers).
 template <class R, int LOG2L, int LOG2C, bool SPLIT, bool SWAP>
-__global__ void __launch_bounds__((PassShape<LOG2L, 4, LOG2C>::THREADS))
+__global__ void __launch_bounds__((PassShape<LOG2L, 4, LOG2C>::THREADS), (pass_waves<R, LOG2L, 4, LOG2C, false>()))
 k_strided(const R* ia, const R* ib, R* oa, R* ob, const cplx_t<R>* __restrict__ tw, int log2s, int64_t tiles) {
     using V = cplx_t<R>;
     using SH = PassShape<LOG2L, 4, LOG2C>;
     using SC = typename SH::SC;
     using ENG = Engine<SC, SH::C, SH::GS, true, true, false>;
     constexpr bool REGTW = pass_regtw<R, LOG2L, 4, LOG2C>();  // else the recurrence table
-    __shared__ V lds[SH::LDS];
+    __shared__ V lds[pass_lds<R, LOG2L, 4, LOG2C, false>()];
     const int tid = threadIdx.x;
     TwReg<SC, V> twr(tw);
     if constexpr (REGTW) twr.template init_engine<ENG>(tid);
@@ -101,7 +101,7 @@ StridedKernel strided_entry() {
     k.kernel = reinterpret_cast<const void*>(&k_strided<R, LOG2L, LOG2C, SPLIT, SWAP>);
     k.eng = engine_info<typename SH::SC, !pass_regtw<R, LOG2L, 4, LOG2C>(), sizeof(R) == 4 ? 2 : 1>();
     k.threads = SH::THREADS;
-    k.lds_bytes = SH::LDS * sizeof(cplx_t<R>);
+    k.lds_bytes = pass_lds<R, LOG2L, 4, LOG2C, false>() * sizeof(cplx_t<R>);
     return k;
 }
 

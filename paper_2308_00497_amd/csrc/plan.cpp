@@ -335,7 +335,11 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout, int64_t batch
     // interleaved 2^18 .. 2^20, and an in-place middle pass for three-pass
     // chains: one workspace half instead of two, 15-25 % faster at every size;
     // split chains re-measured once their first and last passes stream the
-    // caller's arrays: the interleaved shapes win there too, 2^18 by 22 %)
+    // caller's arrays: the interleaved shapes win there too, 2^18 by 22 %;
+    // first passes of 1024-thread tiles since they exchange through half the
+    // LDS (two workgroups per CU): interleaved 2^22 8c6,8c5i,6c7 132.2-132.5
+    // against 135.4-135.9 us, split 2^20 7c7,7c4i,6c6 139.1-139.3 against
+    // 141.4-141.9 us)
     static const char* measured_il[kMaxLog2N + 1] = {
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
         nullptr, nullptr, nullptr, nullptr, nullptr,
@@ -346,7 +350,7 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout, int64_t batch
         "multi:10c3,9c4",         // 2^19
         "multi:10c3,10c3",        // 2^20
         "multi:7c6,7c6i,7c6",     // 2^21
-        "multi:8c5,7c5i,7c6",     // 2^22
+        "multi:8c6,8c5i,6c7",     // 2^22
         "multi:8c5,8c5i,7c6",     // 2^23
         "multi:8c5,8c5i,8c5",     // 2^24
     };
@@ -358,7 +362,7 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout, int64_t batch
         "multi:9c4,8c5",          // 2^17
         "multi:9c4,9c4",          // 2^18
         "multi:7c6,6c6i,6c6",     // 2^19
-        "multi:7c6,7c6i,6c6",     // 2^20
+        "multi:7c7,7c4i,6c6",     // 2^20
         "multi:7c6,7c6i,7c6",     // 2^21
         "multi:8c6,8c5i,6c7",     // 2^22
         "multi:8c6,8c5i,7c6",     // 2^23
