@@ -231,6 +231,31 @@ def test_create_real_validation(lib):
     assert cr(None, 64, 1, 0, -1, 0, None) == 3
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_real_defaults_pass_validation(lib, precision):
+    """Every real-input size's default decomposition (fused kernel up to half
+    length 2^14 FP32 / 2^13 FP64, among them the recurrence-twiddle shapes,
+    else the half-length chain) names compiled kernels in both layouts and
+    directions: plan creation gets past every check made before the first HIP
+    call (here, without a GPU, it then fails at that call)."""
+    h = ctypes.c_void_p()
+    for log2n in range(1, 25):
+        for layout in (0, 1):
+            for direction in (-1, 1):
+                rc = lib.fft_plan_create_real(ctypes.byref(h), 1 << log2n, 2, layout, direction, precision, None)
+                assert rc not in (1, 2, 7), (log2n, layout, direction, precision, rc)
+                if rc == 0:
+                    lib.fft_plan_destroy(h)
+    explicit = [(14, 1, -1, 0, b"single:e4:w256:g8:r2"), (15, 1, -1, 0, b"single:e4:w256:g1:r2"),
+                (14, 1, -1, 0, b"single:e3:w256:g8:r2"), (13, 0, 1, 1, b"single:e4:w256:g8:r2"),
+                (14, 0, 1, 1, b"single:e4:w256:g1:r2"), (14, 0, 1, 1, b"single:e3:w256:g1:r2")]
+    for log2n, layout, direction, prec, dec in explicit:
+        rc = lib.fft_plan_create_real(ctypes.byref(h), 1 << log2n, 2, layout, direction, prec, dec)
+        assert rc not in (1, 2, 7), (dec, rc)
+        if rc == 0:
+            lib.fft_plan_destroy(h)
+
+
 def test_create_nd_validation(lib):
     """Multi-dimensional plans: rank, dims and limits checked before any HIP call."""
     h = ctypes.c_void_p()
