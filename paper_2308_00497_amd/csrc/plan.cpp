@@ -338,32 +338,37 @@ Decomp default_decomposition(int log2n, int rb, fft_layout layout, int64_t batch
     // caller's arrays: the interleaved shapes win there too, 2^18 by 22 %;
     // first passes of 1024-thread tiles since they exchange through half the
     // LDS (two workgroups per CU): interleaved 2^22 8c6,8c5i,6c7 132.2-132.5
-    // against 135.4-135.9 us, split 2^20 7c7,7c4i,6c6 139.1-139.3 against
-    // 141.4-141.9 us)
+    // against 135.4-135.9 us and split 2^20 7c7,7c4i,6c6 139.1-139.3 against
+    // 141.4-141.9 (2^24 elements); for 2^25 elements interleaved 2^15
+    // 165-166 against 173-179, split 2^15 168.8 against 171.7, interleaved
+    // 2^16 164.6-164.9 against 166.5-166.9, split 2^19 261.6-262.0 against
+    // 272.5-272.7, split 2^21 258.3-259.2 against 264.2-264.9, interleaved
+    // 2^23 256.6-256.8 against 265.0-265.6; interleaved 2^21 keeps its chain,
+    // 250 against 254 us)
     static const char* measured_il[kMaxLog2N + 1] = {
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
         nullptr, nullptr, nullptr, nullptr, nullptr,
-        "multi:8c4,7c5",          // 2^15
-        "multi:8c5,8c5",          // 2^16
+        "multi:8c6,7c5",          // 2^15
+        "multi:8c6,8c5",          // 2^16
         "multi:9c4,8c5",          // 2^17
         "multi:9c4,9c4",          // 2^18
         "multi:10c3,9c4",         // 2^19
         "multi:10c3,10c3",        // 2^20
         "multi:7c6,7c6i,7c6",     // 2^21
         "multi:8c6,8c5i,6c7",     // 2^22
-        "multi:8c5,8c5i,7c6",     // 2^23
+        "multi:8c6,8c5i,7c6",     // 2^23
         "multi:8c5,8c5i,8c5",     // 2^24
     };
     static const char* measured_sp[kMaxLog2N + 1] = {
         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
         nullptr, nullptr, nullptr, nullptr, nullptr,
-        "multi:8c5,7c5",          // 2^15
+        "multi:8c6,7c5",          // 2^15
         "multi:8c5,8c5",          // 2^16
         "multi:9c4,8c5",          // 2^17
         "multi:9c4,9c4",          // 2^18
-        "multi:7c6,6c6i,6c6",     // 2^19
+        "multi:7c7,6c6i,6c6",     // 2^19
         "multi:7c7,7c4i,6c6",     // 2^20
-        "multi:7c6,7c6i,7c6",     // 2^21
+        "multi:7c7,7c6i,7c6",     // 2^21
         "multi:8c6,8c5i,6c7",     // 2^22
         "multi:8c6,8c5i,7c6",     // 2^23
         "multi:8c5,8c5i,8c5",     // 2^24
